@@ -1,0 +1,246 @@
+"""A stack of spherical shells: Cartesian gradient, boundaries, SSP-RK3 -- oracle side.
+
+Test infrastructure only (see package docstring).
+
+Data layout (shared with the GPU path's C interface, so that arrays can be
+compared element by element): shells are concatenated in the given order
+(grouped by instance, inner to outer); each shell holds a block
+[component][r][theta][phi] with N_r*S points, S = (L+1) * 2(L+1).
+
+Per-point inputs beside the 50 fields: H [4] (gauge source H_a), dH [16]
+(d_a H_b, row a*4+b, a = 0 is the time derivative), u_bg [50] (the background
+state that freezes the characteristic projections at interfaces).
+"""
+
+import numpy as np
+
+from . import grid as _grid
+from . import spectral as _spec
+from . import gh as _gh
+
+
+class Shell:
+    def __init__(self, instance, n_r, L, r_in, r_out):
+        self.instance = int(instance)
+        self.n_r, self.L = int(n_r), int(L)
+        self.r_in, self.r_out = float(r_in), float(r_out)
+
+
+class Domain:
+    """Shells of one or more independent instances (black holes)."""
+
+    def __init__(self, shells, filter_params=None):
+        self.shells = list(shells)
+        self.grids = [_grid.ShellGrid(s.n_r, s.L, s.r_in, s.r_out) for s in self.shells]
+        self.spheres = {}
+        for s in self.shells:
+            if s.L not in self.spheres:
+                self.spheres[s.L] = _spec.Sphere(s.L)
+        self.n_inst = 1 + max(s.instance for s in self.shells)
+        self.npts = [g.npts for g in self.grids]
+        self.offsets = np.concatenate([[0], np.cumsum(self.npts)])
+        self.P = int(self.offsets[-1])
+        self.filter_params = filter_params
+        # interfaces: consecutive shells of one instance
+        self.interfaces = []
+        for k in range(len(self.shells) - 1):
+            a, b = self.shells[k], self.shells[k + 1]
+            if a.instance == b.instance:
+                if a.L != b.L or abs(a.r_out - b.r_in) > 0.0:
+                    raise ValueError("adjacent shells must share L and the interface radius")
+                self.interfaces.append((k, k + 1))
+        self.outer = [k for k in range(len(self.shells))
+                      if k == len(self.shells) - 1 or self.shells[k + 1].instance != self.shells[k].instance]
+        self.inner = [k for k in range(len(self.shells))
+                      if k == 0 or self.shells[k - 1].instance != self.shells[k].instance]
+
+    # -- layout helpers ------------------------------------------------------
+    def split(self, v, ncomp):
+        """Global array [ncomp * P] -> list of per-shell [ncomp, N_r, N_th, N_ph]."""
+        out = []
+        for k, g in enumerate(self.grids):
+            o = ncomp * self.offsets[k]
+            out.append(v[o:o + ncomp * g.npts].reshape(ncomp, g.n_r, g.n_th, g.n_ph))
+        return out
+
+    def join(self, blocks):
+        return np.concatenate([b.ravel() for b in blocks])
+
+    def xyz(self):
+        """Collocation coordinates in layout order, shape [3, P]."""
+        return np.concatenate([g.xyz() for g in self.grids], axis=1)
+
+    def to_layout(self, a):
+        """[ncomp, P] (points in shell order) -> flat layout [ncomp*P] (per-shell blocks)."""
+        return np.concatenate([a[:, self.offsets[k]:self.offsets[k + 1]].ravel()
+                               for k in range(len(self.grids))])
+
+    def from_layout(self, v, ncomp):
+        """Flat layout [ncomp*P] -> [ncomp, P]."""
+        return np.concatenate([b.reshape(ncomp, -1) for b in self.split(v, ncomp)], axis=1)
+
+    def per_point(self, blocks):
+        """List of per-shell [ncomp, N_r, N_th, N_ph] -> [ncomp, P]."""
+        return np.concatenate([b.reshape(b.shape[0], -1) for b in blocks], axis=1)
+
+    # -- derivatives (the paper's DiffJac after the shell differentiator) ----
+    def cartesian_derivs(self, k, ublk):
+        """d_x, d_y, d_z of every component of one shell block [nc, N_r, N_th, N_ph].
+
+        Radial and angular derivatives by transforms, then the Jacobian of the
+        map (r, theta, phi) -> (x, y, z) (the paper's eq. DiffJac):
+          d_x = s_th c_ph d_r + c_th c_ph / r d_th - s_ph / (r s_th) d_ph
+          d_y = s_th s_ph d_r + c_th s_ph / r d_th + c_ph / (r s_th) d_ph
+          d_z = c_th d_r - s_th / r d_th
+        """
+        g = self.grids[k]
+        sph = self.spheres[g.L]
+        dr = np.moveaxis(_spec.d_dxi(np.moveaxis(ublk, 1, 0)), 0, 1) * (2.0 / (g.r_out - g.r_in))
+        dth = sph.d_dtheta(ublk)
+        dph = sph.d_dphi(ublk)
+        st, ct = np.sin(g.TH), np.cos(g.TH)
+        sp, cp = np.sin(g.PH), np.cos(g.PH)
+        r = g.R
+        dx = st * cp * dr + ct * cp / r * dth - sp / (r * st) * dph
+        dy = st * sp * dr + ct * sp / r * dth + cp / (r * st) * dph
+        dz = ct * dr - st / r * dth
+        return np.stack([dx, dy, dz])
+
+    # -- right-hand side ----------------------------------------------------
+    def rhs(self, u, H, dH, u_bg, gammas, apply_bc=True):
+        """d_t u for the whole domain (interior algebra, then boundaries).
+
+        u [50*P]; H [4*P]; dH [16*P]; u_bg [50*P]; gammas [n_inst, 3].
+        """
+        ub = self.split(u, 50)
+        Hb = self.split(H, 4)
+        dHb = self.split(dH, 16)
+        out = []
+        for k, g in enumerate(self.grids):
+            inst = self.shells[k].instance
+            g0, g1, g2 = gammas[inst]
+            du = self.cartesian_derivs(k, ub[k])
+            dHk = dHb[k].reshape((4, 4) + dHb[k].shape[1:])
+            out.append(_gh.rhs_pointwise(ub[k], du, Hb[k], dHk, g0, g1, g2))
+        if apply_bc:
+            self.apply_bc(out, self.split(u_bg, 50), gammas)
+        return self.join(out)
+
+    def interface_projection(self, k, ubg_blk):
+        """Frozen unit normal s = +r_hat (g-normalised) at the outer face of shell k."""
+        g = self.grids[k]
+        psi, _, _ = _gh.unpack_fields(ubg_blk[:, -1])
+        geo = _gh.Geometry(psi)
+        nhat = np.stack([np.sin(g.TH[-1]) * np.cos(g.PH[-1]),
+                         np.sin(g.TH[-1]) * np.sin(g.PH[-1]),
+                         np.cos(g.TH[-1])])
+        s_lo, s_up = _gh.unit_normal(geo, nhat)
+        return geo, s_lo, s_up
+
+    def apply_bc(self, rhs_blocks, ubg_blocks, gammas):
+        """Boundary treatment of the per-shell d_t u blocks, in place.
+
+        Paper (section on benchmarks of the overall code, closing remarks):
+        internal boundaries exchange characteristic fields, the outer boundary
+        gets a boundary condition, excision boundaries need none.  Readings:
+        * interface (shell A inside, B outside, s = +r_hat normalised with the
+          background metric of u_bg): project both sides' d_t u onto u^psi,
+          u^0, u^+, u^-; take each of u^0, u^+-  from the upwind side (speed > 0:
+          A, < 0: B, = 0: the average) and u^psi as the average of both sides;
+          reconstruct and store the same d_t u on both sides;
+        * outer boundary: Dirichlet, d_t u = 0 for all 50 fields;
+        * inner (excision) boundary: nothing.
+        """
+        for (ka, kb) in self.interfaces:
+            inst = self.shells[ka].instance
+            g1, g2 = gammas[inst][1], gammas[inst][2]
+            geo, s_lo, s_up = self.interface_projection(ka, ubg_blocks[ka])
+            _, v0, vp, vm = _gh.char_speeds(geo, s_lo, g1)
+            A = rhs_blocks[ka][:, -1]
+            B = rhs_blocks[kb][:, 0]
+            pa, u0a, upa, uma = _gh.char_fields(A, s_lo, s_up, g2)
+            pb, u0b, upb, umb = _gh.char_fields(B, s_lo, s_up, g2)
+
+            def pick(speed, xa, xb):
+                wa = np.where(speed > 0, 1.0, np.where(speed < 0, 0.0, 0.5))
+                return wa * xa + (1.0 - wa) * xb
+
+            upsi = 0.5 * (pa + pb)
+            u0 = pick(v0, u0a, u0b)
+            up = pick(vp, upa, upb)
+            um = pick(vm, uma, umb)
+            new = _gh.char_reconstruct(upsi, u0, up, um, s_lo, g2)
+            rhs_blocks[ka][:, -1] = new
+            rhs_blocks[kb][:, 0] = new
+        for k in self.outer:
+            rhs_blocks[k][:, -1] = 0.0
+
+    def excision_speeds(self, u_bg):
+        """Speeds (u^0, u^+, u^-) at every inner boundary, normal s = -r_hat."""
+        ubg = self.split(u_bg, 50)
+        out = []
+        for k in self.inner:
+            g = self.grids[k]
+            psi, _, _ = _gh.unpack_fields(ubg[k][:, 0])
+            geo = _gh.Geometry(psi)
+            nhat = -np.stack([np.sin(g.TH[0]) * np.cos(g.PH[0]),
+                              np.sin(g.TH[0]) * np.sin(g.PH[0]), np.cos(g.TH[0])])
+            s_lo, _ = _gh.unit_normal(geo, nhat)
+            _, v0, vp, vm = _gh.char_speeds(geo, s_lo, 0.0)
+            out.append(np.stack([v0, vp, vm]))
+        return out
+
+    # -- filter -------------------------------------------------------------
+    def apply_filter(self, u):
+        """Angular exponential filter on every component of every shell."""
+        if self.filter_params is None:
+            return u
+        eta_c, alpha, order = self.filter_params
+        blocks = self.split(u, 50)
+        out = []
+        for k, g in enumerate(self.grids):
+            sig = _spec.exp_filter_sigma(g.L, eta_c, alpha, order)
+            out.append(self.spheres[g.L].filter(blocks[k], sig))
+        return self.join(out)
+
+    # -- time step ------------------------------------------------------------
+    def dt_per_point(self, dt):
+        """Per-instance time step broadcast to [50*P] in layout order."""
+        return self.join([np.full((50, g.npts), dt[self.shells[k].instance])
+                          for k, g in enumerate(self.grids)])
+
+    def rk3_step(self, u, H, dH, u_bg, gammas, dt, rhs_fn=None):
+        """One SSP-RK3 (Shu-Osher) step, then the angular filter if enabled.
+
+        u1 = u + dt L(u); u2 = 3/4 u + 1/4 (u1 + dt L(u1));
+        u_new = 1/3 u + 2/3 (u2 + dt L(u2)).
+        """
+        L = rhs_fn or (lambda v: self.rhs(v, H, dH, u_bg, gammas))
+        h = self.dt_per_point(dt)
+        u1 = u + h * L(u)
+        u2 = 0.75 * u + 0.25 * (u1 + h * L(u1))
+        un = (1.0 / 3.0) * u + (2.0 / 3.0) * (u2 + h * L(u2))
+        return self.apply_filter(un)
+
+    # -- constraints ------------------------------------------------------------
+    def constraints(self, u, H):
+        """The 64 constraint components at every point, layout [64*P] per shell block."""
+        ub = self.split(u, 50)
+        Hb = self.split(H, 4)
+        out = []
+        for k in range(len(self.grids)):
+            du = self.cartesian_derivs(k, ub[k])
+            out.append(_gh.constraints_pointwise(ub[k], du, Hb[k]))
+        return self.join(out)
+
+    def constraint_norm(self, u, H):
+        """Per instance ||C|| = sqrt(sum_p w_p sum_c C_c(p)^2 / sum_p w_p)."""
+        Cb = self.split(self.constraints(u, H), 64)
+        num = [0.0] * self.n_inst
+        den = [0.0] * self.n_inst
+        for k, g in enumerate(self.grids):
+            w = g.volume_weights().reshape(g.n_r, g.n_th, g.n_ph)
+            inst = self.shells[k].instance
+            num[inst] = num[inst] + np.sum(w[None] * Cb[k] * Cb[k])
+            den[inst] = den[inst] + np.sum(w)
+        return np.array([np.sqrt(num[i] / den[i]) for i in range(self.n_inst)])

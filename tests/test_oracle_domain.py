@@ -1,0 +1,131 @@
+"""Pins of the oracle's domain-level operations: discrete convergence,
+boundary treatment, SSP-RK3 and the constraint norm."""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import domain, gh
+from paper_1804_09101_amd import inputs
+
+
+def _ks_domain(shells, M=1.0, chi=0.0, axis=(0.0, 0.0, 1.0), filt=None):
+    d = domain.Domain(shells, filter_params=filt)
+    ex = inputs.kerr_schild(d.xyz(), M=M, chi=chi, axis=axis)
+    L = d.to_layout
+    return d, L(ex["u"]), L(ex["H"]), L(ex["dH"])
+
+
+def test_kerr_schild_rhs_converges_at_bernstein_rate():
+    """Schwarzschild on [1.8, 5]: fields are analytic inside the Bernstein ellipse
+    through r = 0 (xi = -2.125, rho = 2.125 + sqrt(2.125^2 - 1) = 4), and a first
+    derivative costs a factor N^2, so e(N)/e(N+4) ~ 4^4 (N/(N+4))^2."""
+    errs = {}
+    for n in (11, 15, 19, 23):
+        d, u, H, dH = _ks_domain([domain.Shell(0, n, 5, 1.8, 5.0)])
+        r = d.rhs(u, H, dH, u, np.array([[1.0, -1.0, 1.0]]), apply_bc=False)
+        errs[n] = np.max(np.abs(r))
+    for n in (11, 15, 19):
+        ratio = errs[n] / errs[n + 4]
+        model = 4.0 ** 4 * (n / (n + 4.0)) ** 2
+        assert 0.5 * model < ratio < 2.0 * model, (n, ratio, model)
+    assert errs[23] < 1e-10
+
+
+def test_constraints_vanish_on_kerr_schild_and_converge():
+    norms = []
+    for n, L in ((9, 6), (13, 10), (17, 14)):
+        d, u, H, dH = _ks_domain([domain.Shell(0, n, L, 2.0, 4.0)], chi=0.5, axis=(1, 1, 0))
+        C = d.split(d.constraints(u, H), 64)[0]
+        assert np.max(np.abs(C[0:4])) < 1e-13          # C_a = 0 by construction of H_a
+        norms.append(d.constraint_norm(u, H)[0])
+    # spinning hole: resolution raised in both directions together
+    assert norms[0] / norms[1] > 100 and norms[1] / norms[2] > 100
+
+
+def test_interface_and_outer_boundary():
+    shells = [domain.Shell(0, 7, 5, 1.8, 3.0), domain.Shell(0, 7, 5, 3.0, 4.5),
+              domain.Shell(0, 9, 5, 4.5, 7.0)]
+    d, ubg, H, dH = _ks_domain(shells, chi=0.6, axis=(0.3, -0.2, 1.0))
+    rng = np.random.default_rng(11)
+    u = ubg + 1e-3 * rng.standard_normal(ubg.shape)
+    gam = np.array([[0.7, -0.4, 1.2]])
+    raw = d.split(d.rhs(u, H, dH, ubg, gam, apply_bc=False), 50)
+    b = d.split(d.rhs(u, H, dH, ubg, gam), 50)
+    for (ka, kb) in d.interfaces:
+        assert np.array_equal(b[ka][:, -1], b[kb][:, 0])
+        assert np.max(np.abs(b[ka][:, -1] - raw[ka][:, -1])) > 0
+    assert np.all(b[-1][:, -1] == 0.0)
+    assert np.array_equal(b[0][:, 0], raw[0][:, 0])        # excision: untouched
+    assert np.array_equal(b[0][:, 1:-1], raw[0][:, 1:-1])  # interior: untouched
+    # boundary treatment is a projection: applying it again changes nothing
+    again = [x.copy() for x in b]
+    d.apply_bc(again, d.split(ubg, 50), gam)
+    for x, y in zip(again, b):
+        assert np.max(np.abs(x - y)) < 1e-15 * max(1.0, np.max(np.abs(y)))
+
+
+def test_interface_takes_each_characteristic_field_from_upwind_side():
+    shells = [domain.Shell(0, 5, 3, 2.0, 3.0), domain.Shell(0, 5, 3, 3.0, 4.0)]
+    d, ubg, H, dH = _ks_domain(shells)
+    gam = np.array([[1.0, -1.0, 1.0]])
+    geo, s_lo, s_up = d.interface_projection(0, d.split(ubg, 50)[0])
+    _, v0, vp, vm = gh.char_speeds(geo, s_lo, -1.0)
+    # Schwarzschild at r = 3: outward shift, so u^0 and u^- come from outside,
+    # u^+ from inside
+    assert np.all(v0 < 0) and np.all(vp > 0) and np.all(vm < 0)
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((50,) + v0.shape)
+    B = rng.standard_normal((50,) + v0.shape)
+    blocks = [np.zeros((50, 5, 4, 8)), np.zeros((50, 5, 4, 8))]
+    blocks[0][:, -1] = A
+    blocks[1][:, 0] = B
+    d.apply_bc(blocks, d.split(ubg, 50), gam)
+    got = gh.char_fields(blocks[0][:, -1], s_lo, s_up, 1.0)
+    fa = gh.char_fields(A, s_lo, s_up, 1.0)
+    fb = gh.char_fields(B, s_lo, s_up, 1.0)
+    assert np.allclose(got[0], 0.5 * (fa[0] + fb[0]), atol=1e-14)
+    assert np.allclose(got[1], fb[1], atol=1e-13)
+    assert np.allclose(got[2], fa[2], atol=1e-13)
+    assert np.allclose(got[3], fb[3], atol=1e-13)
+
+
+def test_rk3_amplification_is_third_order_taylor_polynomial():
+    d = domain.Domain([domain.Shell(0, 5, 2, 1.0, 2.0)])
+    u = np.random.default_rng(0).standard_normal(50 * d.P)
+    for lam, dt in ((-1.3, 0.2), (2.0, 0.05), (-0.5, 1.0)):
+        z = lam * dt
+        got = d.rk3_step(u, None, None, None, None, np.array([dt]), rhs_fn=lambda v: lam * v)
+        assert np.max(np.abs(got - (1 + z + z * z / 2 + z ** 3 / 6) * u)) < 1e-14 * np.max(np.abs(u)) * 4
+
+
+def test_rk3_time_convergence_is_third_order():
+    shells = [domain.Shell(0, 7, 3, 1.8, 3.0), domain.Shell(0, 7, 3, 3.0, 4.2)]
+    d, ubg, H, dH = _ks_domain(shells, filt=None)
+    u0 = ubg + d.to_layout(inputs.gaussian_pulse_Pi(d.xyz(), 1e-2, 3.0, 0.5, 0))
+    gam = np.array([[1.0, -1.0, 1.0]])
+    T = 0.08
+    sol = {}
+    for nsteps in (4, 8, 16):
+        u = u0.copy()
+        for _ in range(nsteps):
+            u = d.rk3_step(u, H, dH, ubg, gam, np.array([T / nsteps]))
+        sol[nsteps] = u
+    e1 = np.max(np.abs(sol[4] - sol[8]))
+    e2 = np.max(np.abs(sol[8] - sol[16]))
+    assert 6.0 < e1 / e2 < 10.0          # 2^3 = 8 for a third-order method
+
+
+def test_pulse_evolution_stays_bounded_and_filter_keeps_interfaces_equal():
+    shells = [domain.Shell(0, 9, 6, 1.8, 3.4), domain.Shell(0, 9, 6, 3.4, 5.0)]
+    d, ubg, H, dH = _ks_domain(shells, filt=(2.0 / 3.0, 36.0, 8.0))
+    u = ubg + d.to_layout(inputs.gaussian_pulse_Pi(d.xyz(), 1e-3, 3.0, 0.5, 0))
+    gam = np.array([[1.0, -1.0, 1.0]])
+    n0 = d.constraint_norm(u, H)[0]
+    for _ in range(10):
+        u = d.rk3_step(u, H, dH, ubg, gam, np.array([0.01]))
+    b = d.split(u, 50)
+    assert np.max(np.abs(b[0][:, -1] - b[1][:, 0])) < 1e-13      # roundoff only
+    assert np.max(np.abs(u - ubg)) < 2e-3
+    assert d.constraint_norm(u, H)[0] < 1.5 * n0
