@@ -46,6 +46,21 @@ def cheb_T(n, xi):
     return np.cos(np.outer(np.arange(n), ang))
 
 
+def cheb_T_at_cgl(n):
+    """T_k(xi_j) at the n CGL nodes, [k, j], from the exact node angle.
+
+    xi_j = cos(pi (N - j)/N) with N = n - 1, so T_k(xi_j) = cos(pi m / N) with
+    m = k (N - j) mod 2N.  Same values as cheb_T(n, cgl_nodes(n)) but without the
+    rounding of arccos of a rounded node, which the derivative recurrence
+    would amplify by ~N^2.
+    """
+    N = n - 1
+    k = np.arange(n)[:, None]
+    j = np.arange(n)[None, :]
+    m = (k * (N - j)) % (2 * N)
+    return np.cos(np.pi * m / N)
+
+
 def clenshaw_curtis_weights(n):
     """Quadrature weights on the CGL nodes: integrate the Chebyshev interpolant.
 

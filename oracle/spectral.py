@@ -32,8 +32,7 @@ def cheb_analysis_matrix(n):
     a_k = (2/(n-1)) / c_k * sum_j'' u_j T_k(xi_j), with the end terms of the sum
     halved and c_0 = c_{n-1} = 2, c_k = 1 otherwise.
     """
-    xi = _grid.cgl_nodes(n)
-    T = _grid.cheb_T(n, xi)                   # [k, j]
+    T = _grid.cheb_T_at_cgl(n)                # [k, j] = T_k(xi_j)
     half = np.ones(n)
     half[0] = half[-1] = 0.5
     ck = np.ones(n)
@@ -63,7 +62,7 @@ def d_dxi(u):
     """d/dxi along axis 0 of CGL samples: PhysToSpec, recurrence, SpecToPhys."""
     n = u.shape[0]
     A = cheb_analysis_matrix(n)
-    T = _grid.cheb_T(n, _grid.cgl_nodes(n))   # SpecToPhys: u_j = sum_k T[k, j] a_k
+    T = _grid.cheb_T_at_cgl(n)                # SpecToPhys: u_j = sum_k T[k, j] a_k
     a = np.tensordot(A, u, axes=(1, 0))
     b = cheb_deriv_coeffs(a)
     return np.tensordot(T.T, b, axes=(1, 0))
