@@ -1,0 +1,144 @@
+"""Throughput of the GH shell evolution on one MI355X.
+
+A step is one SSP-RK3 step of the whole domain: three right-hand-side
+evaluations (angular derivative GEMM, radial derivative, pointwise GH algebra,
+boundary treatment), three stage updates and the angular filter.  The workload
+is the 8-shell pulse problem: 8 shells r in [1.8, 100], N_r = 21, L = 15
+(16 x 32), Schwarzschild M = 1 with a Gaussian pulse in Pi_ab, FP64.
+
+Metric: grid-point RHS evaluations per second = points * 3 * steps / time.
+
+Prints one JSON line (rank 0).  With --gpus > 1 it exits: this build runs on
+one GPU.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MI355X_FP64_PEAK_TFLOPS = 78.6
+MI355X_HBM_PEAK_GBS = 8000.0
+
+
+def deriv_gemm_flops(shells):
+    """Algorithmic flops of one angular derivative GEMM launch over the domain.
+
+    Per shell: C[50 n_r x 2S] = U[50 n_r x S] B[S x 2S], 2 * 50 n_r * 2S * S flops
+    (the paper's angular transform count N_e N_r S (2S - 1) per direction,
+    section "Spectral Operations", counted as 2 flops per multiply-add).
+    """
+    f = 0
+    for (_, n_r, L, _, _) in shells:
+        S = 2 * (L + 1) ** 2
+        f += 2 * 50 * n_r * 2 * S * S
+    return f
+
+
+def cpu_baseline(wl, n_rhs):
+    """Time the CPU oracle on n_rhs RHS evaluations of the same workload."""
+    from oracle import domain
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    d = domain.Domain([domain.Shell(*s) for s in wl.shells], filter_params=wl.filter_params)
+    u0, ubg, H, dH = wl.initial_data(d.xyz(), d.offsets)
+    d.rhs(u0, H, dH, ubg, wl.gamma)       # warm the transform tables
+    t0 = time.perf_counter()
+    for _ in range(n_rhs):
+        d.rhs(u0, H, dH, ubg, wl.gamma)
+    t = time.perf_counter() - t0
+    return {"value": d.P * n_rhs / t, "unit": "grid-point RHS evals/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{n_rhs} RHS evaluations of the full 8-shell workload ({d.P} points), "
+                      f"NumPy oracle, {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-rhs", type=int, default=3, help="oracle RHS evaluations for cpu_baseline (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the path shards by instance or by "
+                                   "shell across GPUs (see DESIGN.md) but no multi-GPU run is provided",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_1804_09101_amd import configs, ghmi
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    wl = configs.pulse_8shell()
+    xyz = ghmi.grid_coords(wl.shells)
+    offs = np.concatenate([[0], np.cumsum([s[1] * 2 * (s[2] + 1) ** 2 for s in wl.shells])])
+    u0, ubg, H, dH = wl.initial_data(xyz, offs)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    solver = ghmi.GHSolver(wl.shells, wl.n_inst, wl.filter_params)
+    solver.set_background(dev(H), dev(dH), dev(ubg))
+    solver.set_params(wl.gamma, wl.dt)
+    u = dev(u0)
+
+    solver.step(u, args.warmup)
+    torch.cuda.synchronize()
+    solver.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.step(u, args.steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    stats = {k: solver.kernel_stats(k) for k in ghmi.KERNEL_KINDS}
+    solver.set_timing(False)
+    if not bool(torch.isfinite(u).all()):
+        print(json.dumps({"error": "non-finite state after the timed steps"}))
+        sys.exit(3)
+
+    P = solver.P
+    value = P * 3 * args.steps / t
+    n_g, ms_g = stats["deriv_gemm"]
+    avg_s = ms_g / n_g / 1e3
+    flops = deriv_gemm_flops(wl.shells)
+    achieved = flops / avg_s / 1e12
+    kernels = {k: {"launches": n, "avg_us": (ms / n * 1e3 if n else None),
+                   "share": ms / (t * 1e3)} for k, (n, ms) in stats.items()}
+    out = {
+        "metric": "grid-point GH RHS evals/s (FP64, 1 GPU)",
+        "value": value,
+        "unit": "grid-point RHS evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded Kerr-Schild hole + Gaussian pulse)",
+        "config": {"workload": "pulse_8shell", "shells": len(wl.shells), "n_r": 21, "L": 15,
+                   "angular_grid": "16x32", "points": P, "rhs_per_step": 3, "filter": "exp angular",
+                   "dt": float(wl.dt[0]), "parallelism": "single GPU"},
+        "roofline": {"kernel": "angular derivative GEMM (FP64 MFMA)", "bound": "mfma",
+                     "achieved": achieved, "peak": MI355X_FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / MI355X_FP64_PEAK_TFLOPS, "traffic": None,
+                     "flops_per_launch": flops, "avg_launch_us": avg_s * 1e6},
+        "kernels": kernels,
+    }
+    if args.cpu_rhs > 0:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_rhs)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

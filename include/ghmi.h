@@ -1,0 +1,162 @@
+/*
+ * ghmi.h -- C interface of the MI355X generalized-harmonic shell evolution.
+ *
+ * Evolves the 50 first-order generalized-harmonic (GH) fields psi_ab, Pi_ab,
+ * Phi_iab of an isolated black hole on stacks of spherical shells (topology
+ * I1 x S2), as in Lewis & Pfeiffer, arXiv:1804.09101 ("Details of our port":
+ * modules Deriv, Trans/DiffJac, GHEqns, ApplyBCs, Filter).  One right-hand-side
+ * (RHS) evaluation is
+ *   1. spectral derivatives of every field along r (Chebyshev) and theta, phi
+ *      (Y_lm), applied as cached dense matrices traced from the transforms
+ *      (section "Spectral Operations", eqs. Differentiation and
+ *      DifferentiatorI1S2);
+ *   2. the Jacobian to Cartesian derivatives (section "Jacobian
+ *      multiplication", eq. DiffJac);
+ *   3. the pointwise GH algebra ("GHEqns"; equations of the first-order GH
+ *      system of Lindblom et al. 2006, which the paper does not print);
+ *   4. boundary treatment ("Apply BCs"): characteristic upwinding at shell
+ *      interfaces, Dirichlet d_t u = 0 at the outer boundary, nothing at the
+ *      excision (inner) boundary.
+ * A step is one SSP-RK3 step (three RHS evaluations) followed, if enabled, by
+ * the angular exponential filter ("Filter" module).
+ *
+ * Conventions for every function:
+ *  - Return value: GH_OK (0) or a negative GH_ERR_* code; gh_last_error()
+ *    then holds a message.  No C++ exception crosses this interface.
+ *  - Field buffers are DEVICE pointers owned by the caller: FP64, contiguous,
+ *    in the layout below.  The library owns operators, tables and work space,
+ *    allocated in gh_set_domain and freed by gh_destroy / the next
+ *    gh_set_domain.
+ *  - Setup calls (gh_set_domain, gh_set_background, gh_set_params) are
+ *    synchronous.  Compute calls (gh_rhs, gh_step, gh_constraints) are queued
+ *    on the context's HIP stream and return before the work completes.
+ *  - Calls on one context must not overlap (one host thread at a time).
+ *
+ * Layout: shells are concatenated in the order given to gh_set_domain
+ * (grouped by instance, inner to outer).  Shell k holds n_r * S points,
+ * S = N_theta * N_phi = (L+1) * 2(L+1), and a per-point quantity with C
+ * components occupies C * n_r * S doubles starting at C * offset_k, ordered
+ * [component][r][theta][phi] (phi fastest).  Radial points are
+ * Chebyshev-Gauss-Lobatto, r_j = (r_in+r_out)/2 - cos(pi j/(n_r-1))(r_out-r_in)/2;
+ * theta_i = arccos(x_i) with x_i the L+1 Gauss-Legendre nodes in increasing
+ * order; phi_k = 2 pi k / N_phi.
+ * Field components (50): psi_ab, Pi_ab, Phi_xab, Phi_yab, Phi_zab, each over
+ * the symmetric pairs 00,01,02,03,11,12,13,22,23,33.
+ */
+#ifndef GHMI_H
+#define GHMI_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GH_OK 0
+#define GH_ERR_ARG (-1)          /* null pointer, bad count or value            */
+#define GH_ERR_SHAPE (-2)        /* inconsistent shells (see gh_set_domain)      */
+#define GH_ERR_ORDER (-3)        /* call made before the setup it needs          */
+#define GH_ERR_OOM (-4)          /* device allocation failed                     */
+#define GH_ERR_NOT_OUTFLOW (-5)  /* an excision boundary point has inflow        */
+#define GH_ERR_NONFINITE (-6)    /* NaN/Inf found in an input or result          */
+#define GH_ERR_DEVICE (-7)       /* HIP runtime error                            */
+
+typedef struct gh_ctx gh_ctx;
+
+/* One spherical shell.  n_r >= 3 radial points, 1 <= L <= 63. */
+typedef struct {
+  int instance;   /* index of the black hole (0 .. n_inst-1) it belongs to */
+  int n_r;        /* radial (Chebyshev-Gauss-Lobatto) points               */
+  int L;          /* highest Y_lm degree; N_theta = L+1, N_phi = 2(L+1)     */
+  double r_in;    /* inner radius (> 0)                                     */
+  double r_out;   /* outer radius (> r_in)                                  */
+} gh_shell;
+
+/* Create a context on HIP device `device` that queues work on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  *out receives the handle. */
+int gh_create(gh_ctx** out, int device, void* hip_stream);
+int gh_destroy(gh_ctx* ctx);
+/* Change the HIP stream used by later compute calls. */
+int gh_set_stream(gh_ctx* ctx, void* hip_stream);
+
+/* Describe the domain: n_shells shells of n_inst independent instances.
+ * Shells must be grouped by instance (instances in increasing order) and
+ * ordered inner to outer; consecutive shells of one instance must share L and
+ * satisfy r_out(k) == r_in(k+1) exactly (GH_ERR_SHAPE otherwise).
+ * filter_kind 0: no filter; 1: angular exponential filter after every step,
+ * sigma_l = 1 for l/L <= eta_c else exp(-alpha ((l/L - eta_c)/(1 - eta_c))^order),
+ * filter_params = {eta_c, alpha, order} (host pointer, ignored for kind 0).
+ * Builds and uploads the derivative and filter operators (cached per L and
+ * per n_r) and allocates all work space.  Invalidates background and params. */
+int gh_set_domain(gh_ctx* ctx, int n_inst, int n_shells, const gh_shell* shells,
+                  int filter_kind, const double* filter_params);
+
+/* Total number of collocation points, and (if shell_offsets != NULL) the
+ * first point of every shell, n_shells+1 entries (host pointers). */
+int gh_num_points(const gh_ctx* ctx, long long* total_points, long long* shell_offsets);
+
+/* Background data, DEVICE pointers in the shell layout (copied; the caller
+ * may free them afterwards):
+ *   H    [4 components]  gauge source H_a;
+ *   dH   [16 components] d_a H_b at component a*4+b (a = 0: time derivative);
+ *   u_bg [50 components] background state.  At shell interfaces it fixes the
+ *        unit normal and the characteristic speeds used for upwinding.  At
+ *        excision boundaries every speed of u^0, u^+ and u^- along the inward
+ *        normal must be >= 0 (pure outflow), else GH_ERR_NOT_OUTFLOW.
+ * Non-finite values give GH_ERR_NONFINITE. */
+int gh_set_background(gh_ctx* ctx, const double* H, const double* dH, const double* u_bg);
+
+/* Constraint-damping parameters gamma [n_inst][3] = (gamma0, gamma1, gamma2)
+ * and time steps dt [n_inst] (HOST pointers; dt may be NULL if only gh_rhs
+ * and gh_constraints are used). */
+int gh_set_params(gh_ctx* ctx, const double* gamma, const double* dt);
+
+/* dudt = d_t u including boundary treatment.  u, dudt: device [50] layout;
+ * they must not overlap. */
+int gh_rhs(gh_ctx* ctx, const double* u, double* dudt);
+
+/* n_steps SSP-RK3 steps in place on u (device [50] layout):
+ *   u1 = u + dt L(u); u2 = 3/4 u + 1/4 (u1 + dt L(u1));
+ *   u <- 1/3 u + 2/3 (u2 + dt L(u2)), then the filter if enabled. */
+int gh_step(gh_ctx* ctx, double* u, int n_steps);
+
+/* Constraints of u.  C (device [64] layout, may be NULL) receives per point
+ * C_a (4), C_iab = d_i psi_ab - Phi_iab (30, i = x,y,z) and
+ * C_ijab = d_i Phi_jab - d_j Phi_iab (30, ij = xy, xz, yz).
+ * norm (device [n_inst], may be NULL) receives per instance
+ * sqrt(sum_p w_p sum_c C_c^2 / sum_p w_p) with w_p the volume quadrature
+ * weight (Clenshaw-Curtis x r^2 (r_out-r_in)/2 x Gauss-Legendre x 2pi/N_phi). */
+int gh_constraints(gh_ctx* ctx, const double* u, double* C, double* norm);
+
+/* Kernel timing.  While enabled, every launch of the kernels named below is
+ * bracketed by HIP events on the context's stream (a small overhead).
+ * gh_kernel_stats waits for the recorded work, returns the number of launches
+ * and their summed duration in milliseconds since timing was enabled or last
+ * queried, and clears that kind's record.
+ * kind 0: angular derivative GEMM; 1: filter GEMM; 2: radial derivative;
+ *      3: pointwise GH RHS; 4: boundary; 5: RK3 stage update. */
+#define GH_NUM_KERNEL_KINDS 6
+int gh_set_timing(gh_ctx* ctx, int enable);
+int gh_kernel_stats(gh_ctx* ctx, int kind, long long* launches, double* total_ms);
+
+/* Message of the last error on this context (never NULL). */
+const char* gh_last_error(const gh_ctx* ctx);
+
+/* ---- host-only helpers (no device needed) ------------------------------- */
+
+/* Cartesian coordinates of every collocation point, HOST xyz[3][P]. */
+int gh_grid_coords(int n_shells, const gh_shell* shells, double* xyz);
+
+/* The dense operators exactly as uploaded to the device (HOST out, row-major,
+ * acting on column vectors of collocation values):
+ *  kind 0: Chebyshev-Gauss-Lobatto d/dxi, n x n (n = n_r);
+ *  kind 1: d/dtheta on the sphere, S x S (n = L);
+ *  kind 2: d/dphi on the sphere, S x S (n = L);
+ *  kind 3: angular filter, S x S (n = L, params = {eta_c, alpha, order});
+ *  kind 4: Clenshaw-Curtis weights on [-1,1], n (n = n_r);
+ *  kind 5: Gauss-Legendre nodes then weights, 2(L+1) (n = L). */
+int gh_host_operator(int kind, int n, const double* params, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GHMI_H */

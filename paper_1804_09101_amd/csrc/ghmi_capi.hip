@@ -1,0 +1,691 @@
+// C interface (include/ghmi.h): context, domain setup, operator cache,
+// GEMM tile lists with autotuned tile shape, and the RHS / RK3 / constraint
+// drivers that queue the kernels of ghmi_kernels.hip on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "ghmi.h"
+#include "ghmi_internal.h"
+#include "ghmi_setup.h"
+
+namespace {
+
+// The GEMM work of one operation over the whole domain: groups of consecutive
+// shells sharing an angular operator, cut into tiles of one tile shape.
+struct GemmPlan {
+  int shape = ghk::T64x64;
+  std::vector<GemmGroup> groups;          // host copy (operator pointers resolved)
+  GemmGroup* d_groups = nullptr;
+  GemmTile* d_tiles = nullptr;
+  int n_tiles = 0;
+};
+
+}  // namespace
+
+struct gh_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err = "";
+
+  // domain
+  int n_inst = 0, n_shells = 0;
+  std::vector<gh_shell> shells;
+  std::vector<long long> offs;   // n_shells + 1
+  long long P = 0;
+  int max_S = 0;
+  int filter_kind = 0;
+  double filt[3] = {0, 0, 0};
+  bool have_domain = false, have_bg = false, have_gamma = false, have_dt = false;
+
+  // tables
+  std::vector<ShellDev> h_sh;
+  std::vector<PtBlock> h_blk;
+  ShellDev* d_sh = nullptr;
+  PtBlock* d_blk = nullptr;
+  int n_blk = 0;
+  double *d_dtab = nullptr, *d_angtab = nullptr, *d_radtab = nullptr, *d_bctab = nullptr;
+  std::map<int, double*> d_angop;   // per L: [S][2S], B operand (Theta^T | Phi^T)
+  std::map<int, double*> d_filtop;  // per L: [S][S], B operand F^T
+  GemmPlan deriv, filter;
+
+  // reductions
+  int* d_inst_range = nullptr;
+  double *d_wsum = nullptr, *d_partial = nullptr;
+
+  // work space and state
+  double *d_dR = nullptr, *d_dA = nullptr, *d_W = nullptr, *d_ua = nullptr, *d_ub = nullptr;
+  double *d_H = nullptr, *d_dH = nullptr;
+  double *d_gamma = nullptr, *d_dt = nullptr;
+  std::vector<void*> allocs;
+
+  // kernel timing (gh_set_timing)
+  bool timing = false;
+  struct Rec { hipEvent_t a, b; int kind; };
+  std::vector<Rec> recs;
+};
+
+namespace {
+
+int fail(gh_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                            \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(ctx, GH_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Bracket one launch with events when timing is on.
+struct Timed {
+  gh_ctx* c;
+  int kind;
+  hipEvent_t a = nullptr, b = nullptr;
+  Timed(gh_ctx* c_, int k) : c(c_), kind(k) {
+    if (c->timing && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+      (void)hipEventRecord(a, c->stream);
+  }
+  ~Timed() {
+    if (a && b) {
+      (void)hipEventRecord(b, c->stream);
+      c->recs.push_back(gh_ctx::Rec{a, b, kind});
+    }
+  }
+};
+
+void clear_timing(gh_ctx* c) {
+  for (auto& r : c->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  c->recs.clear();
+}
+
+void free_domain(gh_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  clear_timing(c);
+  for (void* p : c->allocs) (void)hipFree(p);
+  c->allocs.clear();
+  c->d_angop.clear();
+  c->d_filtop.clear();
+  c->deriv = GemmPlan();
+  c->filter = GemmPlan();
+  c->d_sh = nullptr; c->d_blk = nullptr;
+  c->d_dtab = c->d_angtab = c->d_radtab = c->d_bctab = nullptr;
+  c->d_inst_range = nullptr; c->d_wsum = c->d_partial = nullptr;
+  c->d_dR = c->d_dA = c->d_W = c->d_ua = c->d_ub = nullptr;
+  c->d_H = c->d_dH = nullptr;
+  c->d_gamma = c->d_dt = nullptr;
+  c->have_domain = c->have_bg = c->have_gamma = c->have_dt = false;
+}
+
+template <class T>
+int dalloc(gh_ctx* c, T** p, size_t count) {
+  void* q = nullptr;
+  size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(c, GH_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  c->allocs.push_back(q);
+  *p = static_cast<T*>(q);
+  return GH_OK;
+}
+
+template <class T>
+int upload(gh_ctx* c, T** p, const std::vector<T>& h) {
+  int rc = dalloc(c, p, h.size());
+  if (rc) return rc;
+  if (!h.empty()) HIPCHK(c, hipMemcpy(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return GH_OK;
+}
+
+// Order tiles so that, with workgroups dispatched round-robin over the 8 XCDs,
+// all tiles of one n-column block land on one XCD (its L2 then holds that
+// slice of the operator while the field rows stream past).
+std::vector<GemmTile> build_tiles(const std::vector<GemmGroup>& groups, int shape) {
+  int bm, bn;
+  ghk::tile_dims(shape, &bm, &bn);
+  const int NX = 8;
+  std::vector<std::vector<GemmTile>> per(NX);
+  int col_block = 0;
+  for (size_t g = 0; g < groups.size(); ++g) {
+    int mt = (groups[g].M + bm - 1) / bm, nt = (groups[g].N + bn - 1) / bn;
+    for (int j = 0; j < nt; ++j, ++col_block)
+      for (int i = 0; i < mt; ++i) per[col_block % NX].push_back(GemmTile{int(g), i * bm, j * bn, 0});
+  }
+  std::vector<GemmTile> out;
+  size_t longest = 0;
+  for (auto& v : per) longest = std::max(longest, v.size());
+  for (size_t q = 0; q < longest; ++q)
+    for (int x = 0; x < NX; ++x)
+      if (q < per[x].size()) out.push_back(per[x][q]);
+  return out;
+}
+
+int plan_upload(gh_ctx* c, GemmPlan& pl, int shape) {
+  std::vector<GemmTile> tiles = build_tiles(pl.groups, shape);
+  pl.shape = shape;
+  pl.n_tiles = int(tiles.size());
+  int rc;
+  if (!pl.d_groups) {
+    if ((rc = upload(c, &pl.d_groups, pl.groups))) return rc;
+  }
+  if ((rc = upload(c, &pl.d_tiles, tiles))) return rc;
+  return GH_OK;
+}
+
+// Time every tile shape on the plan (A = src, C = dst work space) and keep the fastest.
+int autotune(gh_ctx* c, GemmPlan& pl, const double* src, double* dst) {
+  float best = 1e30f;
+  int best_shape = ghk::T64x64;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  for (int sh = 0; sh < ghk::NUM_TILE_SHAPES; ++sh) {
+    int rc = plan_upload(c, pl, sh);
+    if (rc) return rc;
+    HIPCHK(c, ghk::gemm(sh, pl.d_tiles, pl.n_tiles, pl.d_groups, src, dst, c->stream));
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    for (int it = 0; it < 3; ++it)
+      HIPCHK(c, ghk::gemm(sh, pl.d_tiles, pl.n_tiles, pl.d_groups, src, dst, c->stream));
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) { best = ms; best_shape = sh; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return plan_upload(c, pl, best_shape);
+}
+
+int check_ready(gh_ctx* c, bool need_dt) {
+  if (!c) return GH_ERR_ARG;
+  if (!c->have_domain) return fail(c, GH_ERR_ORDER, "gh_set_domain has not been called");
+  if (!c->have_bg) return fail(c, GH_ERR_ORDER, "gh_set_background has not been called");
+  if (!c->have_gamma) return fail(c, GH_ERR_ORDER, "gh_set_params has not been called");
+  if (need_dt && !c->have_dt) return fail(c, GH_ERR_ORDER, "no time step set (gh_set_params dt)");
+  return GH_OK;
+}
+
+int validate_shells(int n_inst, int n_shells, const gh_shell* s, std::string& why) {
+  if (n_inst <= 0 || n_shells <= 0 || !s) { why = "need n_inst > 0, n_shells > 0, shells != NULL"; return GH_ERR_ARG; }
+  for (int k = 0; k < n_shells; ++k) {
+    if (s[k].n_r < 3 || s[k].n_r > 256 || s[k].L < 1 || s[k].L > 63) {
+      why = "shell " + std::to_string(k) + ": need 3 <= n_r <= 256 and 1 <= L <= 63";
+      return GH_ERR_ARG;
+    }
+    if (!(s[k].r_in > 0.0) || !(s[k].r_out > s[k].r_in) || !std::isfinite(s[k].r_out)) {
+      why = "shell " + std::to_string(k) + ": need 0 < r_in < r_out";
+      return GH_ERR_ARG;
+    }
+    if (s[k].instance < 0 || s[k].instance >= n_inst) {
+      why = "shell " + std::to_string(k) + ": instance out of range";
+      return GH_ERR_ARG;
+    }
+    if (k > 0) {
+      if (s[k].instance < s[k - 1].instance) { why = "shells must be grouped by increasing instance"; return GH_ERR_SHAPE; }
+      if (s[k].instance == s[k - 1].instance) {
+        if (s[k].L != s[k - 1].L) { why = "adjacent shells of one instance must share L"; return GH_ERR_SHAPE; }
+        if (s[k].r_in != s[k - 1].r_out) { why = "adjacent shells must satisfy r_out(k) == r_in(k+1)"; return GH_ERR_SHAPE; }
+      } else if (s[k].instance != s[k - 1].instance + 1) {
+        why = "every instance needs at least one shell"; return GH_ERR_SHAPE;
+      }
+    }
+  }
+  if (s[0].instance != 0 || s[n_shells - 1].instance != n_inst - 1) { why = "every instance needs at least one shell"; return GH_ERR_SHAPE; }
+  return GH_OK;
+}
+
+// All derivative work of one RHS: the angular GEMM and the radial derivative.
+int queue_derivs(gh_ctx* c, const double* u) {
+  {
+    Timed t(c, 0);
+    HIPCHK(c, ghk::gemm(c->deriv.shape, c->deriv.d_tiles, c->deriv.n_tiles, c->deriv.d_groups, u, c->d_dA,
+                        c->stream));
+  }
+  {
+    Timed t(c, 2);
+    HIPCHK(c, ghk::radial(c->d_sh, c->d_blk, c->n_blk, c->d_dtab, u, c->d_dR, 0, 50, c->stream));
+  }
+  return GH_OK;
+}
+
+int queue_rhs(gh_ctx* c, const double* u, double* out) {
+  int rc = queue_derivs(c, u);
+  if (rc) return rc;
+  {
+    Timed t(c, 3);
+    HIPCHK(c, ghk::pointwise_rhs(c->d_sh, c->d_blk, c->n_blk, c->d_angtab, c->d_radtab, u, c->d_dR, c->d_dA,
+                                 c->d_H, c->d_dH, c->d_gamma, out, c->stream));
+  }
+  {
+    Timed t(c, 4);
+    HIPCHK(c, ghk::boundary(c->d_sh, c->n_shells, c->max_S, c->d_bctab, c->d_gamma, out, c->stream));
+  }
+  return GH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gh_create(gh_ctx** out, int device, void* hip_stream) {
+  if (!out) return GH_ERR_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return GH_ERR_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return GH_ERR_DEVICE;
+  gh_ctx* c = new gh_ctx();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  *out = c;
+  return GH_OK;
+}
+
+int gh_destroy(gh_ctx* c) {
+  if (!c) return GH_ERR_ARG;
+  free_domain(c);
+  delete c;
+  return GH_OK;
+}
+
+int gh_set_stream(gh_ctx* c, void* hip_stream) {
+  if (!c) return GH_ERR_ARG;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  return GH_OK;
+}
+
+const char* gh_last_error(const gh_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int gh_set_domain(gh_ctx* c, int n_inst, int n_shells, const gh_shell* shells, int filter_kind,
+                  const double* filter_params) {
+  if (!c) return GH_ERR_ARG;
+  std::string why;
+  int rc = validate_shells(n_inst, n_shells, shells, why);
+  if (rc) return fail(c, rc, why);
+  if (filter_kind != 0 && filter_kind != 1) return fail(c, GH_ERR_ARG, "filter_kind must be 0 or 1");
+  if (filter_kind == 1) {
+    if (!filter_params) return fail(c, GH_ERR_ARG, "filter_params required for filter_kind 1");
+    if (!(filter_params[0] >= 0.0 && filter_params[0] < 1.0) || !(filter_params[1] >= 0.0) ||
+        !(filter_params[2] > 0.0))
+      return fail(c, GH_ERR_ARG, "filter_params: need 0 <= eta_c < 1, alpha >= 0, order > 0");
+  }
+  HIPCHK(c, hipSetDevice(c->device));
+  free_domain(c);
+  c->n_inst = n_inst;
+  c->n_shells = n_shells;
+  c->shells.assign(shells, shells + n_shells);
+  c->filter_kind = filter_kind;
+  if (filter_kind == 1) std::memcpy(c->filt, filter_params, 3 * sizeof(double));
+
+  // layout
+  c->offs.assign(n_shells + 1, 0);
+  c->max_S = 0;
+  for (int k = 0; k < n_shells; ++k) {
+    long long S = 2LL * (shells[k].L + 1) * (shells[k].L + 1);
+    c->offs[k + 1] = c->offs[k] + shells[k].n_r * S;
+    c->max_S = std::max<int>(c->max_S, int(S));
+  }
+  c->P = c->offs[n_shells];
+
+  // operator caches and tables: radial per n_r, angular per L
+  std::map<int, int> d_off, ang_off;
+  std::vector<double> dtab, angtab, radtab;
+  for (int k = 0; k < n_shells; ++k) {
+    int n = shells[k].n_r, L = shells[k].L;
+    if (!d_off.count(n)) {
+      d_off[n] = int(dtab.size());
+      auto D = ghsetup::cgl_diff_matrix(n);
+      dtab.insert(dtab.end(), D.begin(), D.end());
+    }
+    if (!ang_off.count(L)) {
+      ang_off[L] = int(angtab.size() / 5);
+      auto t = ghsetup::angular_table(L);
+      angtab.insert(angtab.end(), t.begin(), t.end());
+    }
+  }
+  std::vector<double> wsum(n_inst, 0.0);
+  c->h_sh.assign(n_shells, ShellDev());
+  int bc_total = 0;
+  for (int k = 0; k < n_shells; ++k) {
+    const gh_shell& s = shells[k];
+    ShellDev& d = c->h_sh[k];
+    d.pt_off = c->offs[k];
+    d.n_r = s.n_r;
+    d.L = s.L;
+    d.n_ph = 2 * (s.L + 1);
+    d.S = (s.L + 1) * d.n_ph;
+    d.instance = s.instance;
+    d.d_off = d_off[s.n_r];
+    d.ang_off = ang_off[s.L];
+    d.rad_off = int(radtab.size() / 2);
+    d.dscale = 2.0 / (s.r_out - s.r_in);
+    bool last = (k == n_shells - 1) || shells[k + 1].instance != s.instance;
+    bool first = (k == 0) || shells[k - 1].instance != s.instance;
+    d.outer = last ? 1 : 0;
+    d.inner = first ? 1 : 0;
+    d.bc_off = last ? -1 : bc_total;
+    if (!last) bc_total += 9 * d.S;
+    auto xi = ghsetup::cgl_nodes(s.n_r);
+    auto cc = ghsetup::clenshaw_curtis(s.n_r);
+    double wang = 0.0;
+    {
+      std::vector<double> x, w;
+      ghsetup::gauss_legendre(s.L, x, w);
+      for (double wi : w) wang += wi * 2.0 * 3.14159265358979323846;   // sum over theta, phi
+    }
+    for (int j = 0; j < s.n_r; ++j) {
+      double r = 0.5 * (s.r_in + s.r_out) + 0.5 * (s.r_out - s.r_in) * xi[j];
+      double wr = cc[j] * 0.5 * (s.r_out - s.r_in) * r * r;
+      radtab.push_back(r);
+      radtab.push_back(wr);
+      wsum[s.instance] += wr * wang;
+    }
+  }
+  // point blocks (256 points, never straddling shells) and per-instance block ranges
+  c->h_blk.clear();
+  std::vector<int> range(2 * n_inst, 0);
+  for (int k = 0; k < n_shells; ++k) {
+    int Pk = int(c->offs[k + 1] - c->offs[k]);
+    if (k == 0 || shells[k].instance != shells[k - 1].instance) range[2 * shells[k].instance] = int(c->h_blk.size());
+    for (int q0 = 0; q0 < Pk; q0 += 256) c->h_blk.push_back(PtBlock{k, q0});
+    range[2 * shells[k].instance + 1] = int(c->h_blk.size());
+  }
+  c->n_blk = int(c->h_blk.size());
+
+  if ((rc = upload(c, &c->d_sh, c->h_sh))) return rc;
+  if ((rc = upload(c, &c->d_blk, c->h_blk))) return rc;
+  if ((rc = upload(c, &c->d_dtab, dtab))) return rc;
+  if ((rc = upload(c, &c->d_angtab, angtab))) return rc;
+  if ((rc = upload(c, &c->d_radtab, radtab))) return rc;
+  if ((rc = upload(c, &c->d_inst_range, range))) return rc;
+  if ((rc = upload(c, &c->d_wsum, wsum))) return rc;
+  if ((rc = dalloc(c, &c->d_bctab, size_t(std::max(bc_total, 1))))) return rc;
+  if ((rc = dalloc(c, &c->d_partial, size_t(c->n_blk)))) return rc;
+
+  // angular operators (and filters), uploaded once per L
+  for (auto& kv : ang_off) {
+    int L = kv.first, S = 2 * (L + 1) * (L + 1);
+    std::vector<double> none;
+    auto Th = ghsetup::sphere_operator(L, 0, none);
+    auto Ph = ghsetup::sphere_operator(L, 1, none);
+    std::vector<double> Bop(size_t(S) * 2 * S);
+    for (int a = 0; a < S; ++a)
+      for (int j = 0; j < S; ++j) {
+        Bop[size_t(a) * 2 * S + j] = Th[size_t(j) * S + a];
+        Bop[size_t(a) * 2 * S + S + j] = Ph[size_t(j) * S + a];
+      }
+    double* d = nullptr;
+    if ((rc = upload(c, &d, Bop))) return rc;
+    c->d_angop[L] = d;
+    if (filter_kind == 1) {
+      auto sig = ghsetup::exp_filter_sigma(L, c->filt[0], c->filt[1], c->filt[2]);
+      auto F = ghsetup::sphere_operator(L, 2, sig);
+      std::vector<double> FT(size_t(S) * S);
+      for (int a = 0; a < S; ++a)
+        for (int j = 0; j < S; ++j) FT[size_t(a) * S + j] = F[size_t(j) * S + a];
+      double* f = nullptr;
+      if ((rc = upload(c, &f, FT))) return rc;
+      c->d_filtop[L] = f;
+    }
+  }
+
+  // GEMM groups: maximal runs of consecutive shells with the same L
+  c->deriv.groups.clear();
+  c->filter.groups.clear();
+  for (int k = 0; k < n_shells;) {
+    int L = shells[k].L, S = 2 * (L + 1) * (L + 1);
+    int k1 = k, rows = 0;
+    while (k1 < n_shells && shells[k1].L == L) { rows += 50 * shells[k1].n_r; ++k1; }
+    GemmGroup gd;
+    gd.a_off = 50LL * c->offs[k];
+    gd.c_off = 100LL * c->offs[k];
+    gd.B = c->d_angop[L];
+    gd.M = rows; gd.N = 2 * S; gd.K = S;
+    gd.lda = S; gd.ldb = 2 * S; gd.ldc = 2 * S;
+    c->deriv.groups.push_back(gd);
+    if (filter_kind == 1) {
+      GemmGroup gf = gd;
+      gf.c_off = 50LL * c->offs[k];
+      gf.B = c->d_filtop[L];
+      gf.N = S; gf.ldb = S; gf.ldc = S;
+      c->filter.groups.push_back(gf);
+    }
+    k = k1;
+  }
+
+  // work space
+  size_t F50 = size_t(50) * c->P;
+  if ((rc = dalloc(c, &c->d_dR, F50))) return rc;
+  if ((rc = dalloc(c, &c->d_dA, 2 * F50))) return rc;
+  if ((rc = dalloc(c, &c->d_W, F50))) return rc;
+  if ((rc = dalloc(c, &c->d_ua, F50))) return rc;
+  if ((rc = dalloc(c, &c->d_ub, F50))) return rc;
+  if ((rc = dalloc(c, &c->d_H, size_t(4) * c->P))) return rc;
+  if ((rc = dalloc(c, &c->d_dH, size_t(16) * c->P))) return rc;
+  if ((rc = dalloc(c, &c->d_gamma, size_t(3) * n_inst))) return rc;
+  if ((rc = dalloc(c, &c->d_dt, size_t(n_inst)))) return rc;
+  HIPCHK(c, hipMemset(c->d_ua, 0, F50 * sizeof(double)));
+
+  // tile shapes: pick the fastest for this domain
+  if ((rc = autotune(c, c->deriv, c->d_ua, c->d_dA))) return rc;
+  if (filter_kind == 1)
+    if ((rc = autotune(c, c->filter, c->d_ua, c->d_ub))) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->have_domain = true;
+  return GH_OK;
+}
+
+int gh_num_points(const gh_ctx* c, long long* total, long long* offsets) {
+  if (!c || !total) return GH_ERR_ARG;
+  if (!c->have_domain) return GH_ERR_ORDER;
+  *total = c->P;
+  if (offsets)
+    for (int k = 0; k <= c->n_shells; ++k) offsets[k] = c->offs[k];
+  return GH_OK;
+}
+
+int gh_set_background(gh_ctx* c, const double* H, const double* dH, const double* u_bg) {
+  if (!c) return GH_ERR_ARG;
+  if (!c->have_domain) return fail(c, GH_ERR_ORDER, "gh_set_domain has not been called");
+  if (!H || !dH || !u_bg) return fail(c, GH_ERR_ARG, "H, dH and u_bg must be device pointers");
+  HIPCHK(c, hipSetDevice(c->device));
+  c->have_bg = false;
+  // scratch for the checks lives in the work space (d_partial holds >= 1 double,
+  // d_W >= 50 P doubles); nothing is queued on them concurrently in setup
+  int* d_cnt = reinterpret_cast<int*>(c->d_partial);
+  HIPCHK(c, hipMemsetAsync(d_cnt, 0, sizeof(int), c->stream));
+  HIPCHK(c, ghk::nonfinite_count(H, 4 * c->P, d_cnt, c->stream));
+  HIPCHK(c, ghk::nonfinite_count(dH, 16 * c->P, d_cnt, c->stream));
+  HIPCHK(c, ghk::nonfinite_count(u_bg, 50 * c->P, d_cnt, c->stream));
+  int cnt = 0;
+  HIPCHK(c, hipMemcpyAsync(&cnt, d_cnt, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (cnt) return fail(c, GH_ERR_NONFINITE, std::to_string(cnt) + " non-finite background values");
+  HIPCHK(c, hipMemcpyAsync(c->d_H, H, 4 * c->P * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_dH, dH, 16 * c->P * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  size_t nex = size_t(c->n_shells) * c->max_S;
+  if (nex > size_t(50) * c->P) return fail(c, GH_ERR_ARG, "internal: excision scratch too small");
+  double* d_ex = c->d_W;
+  HIPCHK(c, ghk::bc_setup(c->d_sh, c->n_shells, c->max_S, c->d_angtab, u_bg, c->d_bctab, d_ex, c->stream));
+  std::vector<double> ex(nex);
+  HIPCHK(c, hipMemcpyAsync(ex.data(), d_ex, nex * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double mn = INFINITY;
+  for (double v : ex) mn = std::min(mn, v);
+  if (!(mn >= 0.0)) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "excision boundary is not pure outflow (min characteristic speed %.6g)", mn);
+    return fail(c, GH_ERR_NOT_OUTFLOW, buf);
+  }
+  c->have_bg = true;
+  return GH_OK;
+}
+
+int gh_set_params(gh_ctx* c, const double* gamma, const double* dt) {
+  if (!c) return GH_ERR_ARG;
+  if (!c->have_domain) return fail(c, GH_ERR_ORDER, "gh_set_domain has not been called");
+  if (!gamma) return fail(c, GH_ERR_ARG, "gamma must be a host pointer [n_inst][3]");
+  for (int i = 0; i < 3 * c->n_inst; ++i)
+    if (!std::isfinite(gamma[i])) return fail(c, GH_ERR_NONFINITE, "non-finite gamma");
+  if (dt)
+    for (int i = 0; i < c->n_inst; ++i)
+      if (!std::isfinite(dt[i]) || !(dt[i] > 0.0)) return fail(c, GH_ERR_ARG, "dt must be finite and > 0");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipMemcpy(c->d_gamma, gamma, 3 * c->n_inst * sizeof(double), hipMemcpyHostToDevice));
+  c->have_gamma = true;
+  if (dt) {
+    HIPCHK(c, hipMemcpy(c->d_dt, dt, c->n_inst * sizeof(double), hipMemcpyHostToDevice));
+    c->have_dt = true;
+  }
+  return GH_OK;
+}
+
+int gh_rhs(gh_ctx* c, const double* u, double* dudt) {
+  int rc = check_ready(c, false);
+  if (rc) return rc;
+  if (!u || !dudt || u == dudt) return fail(c, GH_ERR_ARG, "u and dudt must be distinct device pointers");
+  HIPCHK(c, hipSetDevice(c->device));
+  return queue_rhs(c, u, dudt);
+}
+
+int gh_step(gh_ctx* c, double* u, int n_steps) {
+  int rc = check_ready(c, true);
+  if (rc) return rc;
+  if (!u || n_steps < 0) return fail(c, GH_ERR_ARG, "need u != NULL and n_steps >= 0");
+  HIPCHK(c, hipSetDevice(c->device));
+  const bool filt = c->filter_kind == 1;
+  auto stage = [&](double c0, const double* u0, double c1, const double* us, double* out) -> int {
+    Timed t(c, 5);
+    HIPCHK(c, ghk::rk_stage(c->d_sh, c->d_blk, c->n_blk, c->d_dt, c0, u0, c1, us, c->d_W, out, c->stream));
+    return GH_OK;
+  };
+  for (int n = 0; n < n_steps; ++n) {
+    if ((rc = queue_rhs(c, u, c->d_W))) return rc;
+    if ((rc = stage(0.0, nullptr, 1.0, u, c->d_ua))) return rc;
+    if ((rc = queue_rhs(c, c->d_ua, c->d_W))) return rc;
+    if ((rc = stage(0.75, u, 0.25, c->d_ua, c->d_ub))) return rc;
+    if ((rc = queue_rhs(c, c->d_ub, c->d_W))) return rc;
+    double* dst = filt ? c->d_ua : u;
+    if ((rc = stage(1.0 / 3.0, u, 2.0 / 3.0, c->d_ub, dst))) return rc;
+    if (filt) {
+      Timed t(c, 1);
+      HIPCHK(c, ghk::gemm(c->filter.shape, c->filter.d_tiles, c->filter.n_tiles, c->filter.d_groups, c->d_ua, u,
+                          c->stream));
+    }
+  }
+  return GH_OK;
+}
+
+int gh_constraints(gh_ctx* c, const double* u, double* C, double* norm) {
+  if (!c) return GH_ERR_ARG;
+  if (!c->have_domain) return fail(c, GH_ERR_ORDER, "gh_set_domain has not been called");
+  if (!c->have_bg) return fail(c, GH_ERR_ORDER, "gh_set_background has not been called");
+  if (!u) return fail(c, GH_ERR_ARG, "u must be a device pointer");
+  HIPCHK(c, hipSetDevice(c->device));
+  int rc = queue_derivs(c, u);
+  if (rc) return rc;
+  HIPCHK(c, ghk::constraints(c->d_sh, c->d_blk, c->n_blk, c->d_angtab, c->d_radtab, u, c->d_dR, c->d_dA, c->d_H,
+                             C, c->d_partial, c->stream));
+  if (norm) HIPCHK(c, ghk::reduce_norm(c->d_inst_range, c->n_inst, c->d_partial, c->d_wsum, norm, c->stream));
+  return GH_OK;
+}
+
+int gh_set_timing(gh_ctx* c, int enable) {
+  if (!c) return GH_ERR_ARG;
+  HIPCHK(c, hipSetDevice(c->device));
+  if (c->stream) HIPCHK(c, hipStreamSynchronize(c->stream));
+  clear_timing(c);
+  c->timing = enable != 0;
+  return GH_OK;
+}
+
+int gh_kernel_stats(gh_ctx* c, int kind, long long* launches, double* total_ms) {
+  if (!c || !launches || !total_ms || kind < 0 || kind >= GH_NUM_KERNEL_KINDS) return GH_ERR_ARG;
+  HIPCHK(c, hipSetDevice(c->device));
+  long long n = 0;
+  double ms = 0.0;
+  std::vector<gh_ctx::Rec> keep;
+  for (auto& r : c->recs) {
+    if (r.kind != kind) { keep.push_back(r); continue; }
+    HIPCHK(c, hipEventSynchronize(r.b));
+    float t = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&t, r.a, r.b));
+    ms += t;
+    ++n;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  c->recs.swap(keep);
+  *launches = n;
+  *total_ms = ms;
+  return GH_OK;
+}
+
+int gh_grid_coords(int n_shells, const gh_shell* shells, double* xyz) {
+  if (n_shells <= 0 || !shells || !xyz) return GH_ERR_ARG;
+  long long P = 0;
+  for (int k = 0; k < n_shells; ++k) {
+    if (shells[k].n_r < 2 || shells[k].L < 0) return GH_ERR_ARG;
+    P += (long long)shells[k].n_r * 2 * (shells[k].L + 1) * (shells[k].L + 1);
+  }
+  long long p = 0;
+  for (int k = 0; k < n_shells; ++k) {
+    const gh_shell& s = shells[k];
+    auto xi = ghsetup::cgl_nodes(s.n_r);
+    auto ang = ghsetup::angular_table(s.L);
+    int S = 2 * (s.L + 1) * (s.L + 1);
+    for (int j = 0; j < s.n_r; ++j) {
+      double r = 0.5 * (s.r_in + s.r_out) + 0.5 * (s.r_out - s.r_in) * xi[j];
+      for (int a = 0; a < S; ++a, ++p) {
+        const double* t = &ang[size_t(a) * 5];
+        xyz[p] = r * t[0] * t[3];
+        xyz[P + p] = r * t[0] * t[2];
+        xyz[2 * P + p] = r * t[1];
+      }
+    }
+  }
+  return GH_OK;
+}
+
+int gh_host_operator(int kind, int n, const double* params, double* out) {
+  if (!out) return GH_ERR_ARG;
+  std::vector<double> v;
+  switch (kind) {
+    case 0: if (n < 2) return GH_ERR_ARG; v = ghsetup::cgl_diff_matrix(n); break;
+    case 1: if (n < 1) return GH_ERR_ARG; v = ghsetup::sphere_operator(n, 0, {}); break;
+    case 2: if (n < 1) return GH_ERR_ARG; v = ghsetup::sphere_operator(n, 1, {}); break;
+    case 3:
+      if (n < 1 || !params) return GH_ERR_ARG;
+      v = ghsetup::sphere_operator(n, 2, ghsetup::exp_filter_sigma(n, params[0], params[1], params[2]));
+      break;
+    case 4: if (n < 2) return GH_ERR_ARG; v = ghsetup::clenshaw_curtis(n); break;
+    case 5: {
+      if (n < 0) return GH_ERR_ARG;
+      std::vector<double> x, w;
+      ghsetup::gauss_legendre(n, x, w);
+      v = x;
+      v.insert(v.end(), w.begin(), w.end());
+      break;
+    }
+    default: return GH_ERR_ARG;
+  }
+  std::memcpy(out, v.data(), v.size() * sizeof(double));
+  return GH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// Device-side data structures shared by the kernels and the C interface.
+#pragma once
+#include <hip/hip_runtime.h>
+
+// One shell as the kernels see it.
+struct ShellDev {
+  long long pt_off;   // first collocation point of the shell
+  int n_r, L, S, n_ph;
+  int instance;
+  int d_off;          // offset of this n_r's CGL d/dxi matrix in the radial table
+  int ang_off;        // offset (in 5-double records) of this L's angular table
+  int rad_off;        // offset of this shell's radial records (r_j, quadrature weight) x n_r
+  int bc_off;         // interface at the outer face: offset of its records (9 doubles x S), else -1
+  int outer;          // 1: outer face is the outer boundary of its instance
+  int inner;          // 1: inner face is an excision boundary
+  double dscale;      // d/dr = dscale * d/dxi, dscale = 2/(r_out - r_in)
+};
+
+// A block of up to 256 consecutive points inside one shell.
+struct PtBlock {
+  int shell;
+  int q0;             // first local point index (r*S + a)
+};
+
+// One GEMM problem of a grouped launch: C[M x N] = A[M x K] * B[K x N], row-major,
+// with A = Abase + a_off and C = Cbase + c_off (the bases are launch arguments,
+// so one tile list serves any state / work-space pair).
+struct GemmGroup {
+  long long a_off;
+  long long c_off;
+  const double* B;
+  int M, N, K;
+  int lda, ldb, ldc;
+};
+
+// One output tile of a grouped GEMM launch.
+struct GemmTile {
+  int g;              // group index
+  int m0, n0;         // tile origin
+  int pad;
+};
+
+// Kernel launchers (ghmi_kernels.hip).  All are asynchronous on `st`.
+namespace ghk {
+
+enum TileShape { T64x64 = 0, T64x128 = 1, T128x64 = 2, T128x128 = 3, NUM_TILE_SHAPES = 4 };
+void tile_dims(int shape, int* bm, int* bn);
+
+hipError_t gemm(int shape, const GemmTile* tiles, int n_tiles, const GemmGroup* groups,
+                const double* Abase, double* Cbase, hipStream_t st);
+
+hipError_t radial(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* dtab,
+                  const double* u, double* dR, int ncomp_lo, int ncomp_hi, hipStream_t st);
+
+hipError_t pointwise_rhs(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* angtab,
+                         const double* radtab, const double* u, const double* dR, const double* dA,
+                         const double* H, const double* dH, const double* gamma, double* rhs,
+                         hipStream_t st);
+
+hipError_t boundary(const ShellDev* sh, int n_shells, int max_S, const double* bctab,
+                    const double* gamma, double* rhs, hipStream_t st);
+
+hipError_t rk_stage(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* dt,
+                    double c0, const double* u0, double c1, const double* u, const double* L,
+                    double* out, hipStream_t st);
+
+hipError_t constraints(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* angtab,
+                       const double* radtab, const double* u, const double* dR, const double* dA,
+                       const double* H, double* C, double* partial, hipStream_t st);
+
+hipError_t reduce_norm(const int* inst_blk_range, int n_inst, const double* partial,
+                       const double* wsum, double* norm, hipStream_t st);
+
+hipError_t bc_setup(const ShellDev* sh, int n_shells, int max_S, const double* angtab,
+                    const double* u_bg, double* bctab, double* excision_min, hipStream_t st);
+
+hipError_t nonfinite_count(const double* x, long long n, int* count, hipStream_t st);
+
+}  // namespace ghk

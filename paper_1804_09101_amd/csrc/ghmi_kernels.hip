@@ -1,0 +1,821 @@
+// HIP kernels for gfx950 (MI355X): spectral derivatives, pointwise GH algebra,
+// boundary treatment, SSP-RK3 stages, constraints.  All arithmetic is FP64.
+#include <hip/hip_runtime.h>
+#include <cmath>
+
+#include "ghmi_internal.h"
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Symmetric pair index of (a, b), pairs ordered 00,01,02,03,11,12,13,22,23,33.
+__host__ __device__ constexpr int SYM(int a, int b) {
+  return a <= b ? (a * 4 - a * (a - 1) / 2 + b - a) : (b * 4 - b * (b - 1) / 2 + a - b);
+}
+// Symmetric 3x3 index of (i, j), i,j in 0..2: 11,12,13,22,23,33.
+__host__ __device__ constexpr int SYM3(int i, int j) {
+  return i <= j ? (i * 3 - i * (i - 1) / 2 + j - i) : (j * 3 - j * (j - 1) / 2 + i - j);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped FP64 GEMM on the matrix cores: C = A * B for every group of a tile
+// list.  One workgroup (4 waves, 2x2) computes a BM x BN tile; each wave owns a
+// (BM/2) x (BN/2) sub-tile made of 16x16 blocks of v_mfma_f64_16x16x4_f64.
+// A and B k-slices (BK = 16) are staged through LDS, double buffered; A is
+// stored k-major in LDS so that both operand fragments are read as 16
+// consecutive doubles per k row.
+//
+// Fragment layout of v_mfma_f64_16x16x4_f64 (64 lanes):
+//   A (16x4): lane l holds A[l % 16][l / 16]
+//   B (4x16): lane l holds B[l / 16][l % 16]
+//   C (16x16): lane l holds C[l/16 + 4*v][l % 16], v = 0..3 (checked on gfx950)
+// ---------------------------------------------------------------------------
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void k_gemm(const GemmTile* __restrict__ tiles,
+                                              const GemmGroup* __restrict__ groups,
+                                              const double* __restrict__ Abase,
+                                              double* __restrict__ Cbase) {
+  constexpr int BK = 16;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int APASS = BM / 64;        // A loads: 4 doubles per thread per pass
+  constexpr int BPASS = BN / 64;        // B loads: 4 doubles per thread per pass
+  __shared__ double As[2][BK][BM];
+  __shared__ double Bs[2][BK][BN];
+
+  const GemmTile t = tiles[blockIdx.x];
+  const GemmGroup G = groups[t.g];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+  const int M = G.M, N = G.N, K = G.K;
+  const double* __restrict__ Ag = Abase + G.a_off;
+  double* __restrict__ Cg = Cbase + G.c_off;
+
+  d4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  double ra[APASS][4], rb[BPASS][4];
+
+  auto load_global = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < APASS; ++p) {
+      int idx = p * 256 + tid;
+      int row = t.m0 + idx / 4, kq = k0 + (idx % 4) * 4;
+      const double* src = Ag + (long long)row * G.lda + kq;
+      if (row < M && kq + 3 < K) {
+        double2 v0 = *reinterpret_cast<const double2*>(src);
+        double2 v1 = *reinterpret_cast<const double2*>(src + 2);
+        ra[p][0] = v0.x; ra[p][1] = v0.y; ra[p][2] = v1.x; ra[p][3] = v1.y;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ra[p][e] = (row < M && kq + e < K) ? src[e] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < BPASS; ++p) {
+      int idx = p * 256 + tid;
+      int krow = k0 + idx / (BN / 4), col = t.n0 + (idx % (BN / 4)) * 4;
+      const double* src = G.B + (long long)krow * G.ldb + col;
+      if (krow < K && col + 3 < N) {
+        double2 v0 = *reinterpret_cast<const double2*>(src);
+        double2 v1 = *reinterpret_cast<const double2*>(src + 2);
+        rb[p][0] = v0.x; rb[p][1] = v0.y; rb[p][2] = v1.x; rb[p][3] = v1.y;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rb[p][e] = (krow < K && col + e < N) ? src[e] : 0.0;
+      }
+    }
+  };
+  auto store_lds = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < APASS; ++p) {
+      int idx = p * 256 + tid;
+      int row = idx / 4, kq = (idx % 4) * 4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) As[buf][kq + e][row] = ra[p][e];
+    }
+#pragma unroll
+    for (int p = 0; p < BPASS; ++p) {
+      int idx = p * 256 + tid;
+      int krow = idx / (BN / 4), col = (idx % (BN / 4)) * 4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) Bs[buf][krow][col + e] = rb[p][e];
+    }
+  };
+
+  const int nk = (K + BK - 1) / BK;
+  load_global(0);
+  store_lds(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load_global((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      const int kr = kk * 4 + lane / 16;
+      double af[TM], bf[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) af[i] = As[buf][kr][wm + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bf[j] = Bs[buf][kr][wn + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) store_lds(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int col = t.n0 + wn + j * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = t.m0 + wm + i * 16 + (lane / 16) + 4 * v;
+        if (row < M && col < N) Cg[(long long)row * G.ldc + col] = acc[i][j][v];
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Radial derivative: dR[f][r][a] = dscale * sum_r' D[r][r'] u[f][r'][a].
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_radial(const ShellDev* __restrict__ sh,
+                                                const PtBlock* __restrict__ blk,
+                                                const double* __restrict__ dtab,
+                                                const double* __restrict__ u,
+                                                double* __restrict__ dR, int f0) {
+  const PtBlock b = blk[blockIdx.x];
+  const ShellDev s = sh[b.shell];
+  const int P = s.n_r * s.S;
+  const int q = b.q0 + threadIdx.x;
+  if (q >= P) return;
+  const int f = f0 + blockIdx.y;
+  const int r = q / s.S, a = q - r * s.S;
+  const long long base = 50LL * s.pt_off + (long long)f * P;
+  const double* D = dtab + s.d_off + r * s.n_r;
+  const double* col = u + base + a;
+  double acc = 0.0;
+  for (int rp = 0; rp < s.n_r; ++rp) acc += D[rp] * col[(long long)rp * s.S];
+  dR[base + q] = s.dscale * acc;
+}
+
+// ---------------------------------------------------------------------------
+// Pointwise generalized-harmonic algebra.
+// ---------------------------------------------------------------------------
+
+// 3+1 quantities from psi_ab.
+struct Geo {
+  double gi[6];     // g^ij
+  double Nu[3];     // N^i
+  double N;         // lapse
+  double tu[4];     // t^a
+  double pinv[10];  // psi^ab
+};
+
+__device__ __forceinline__ void geometry(const double* psi, Geo& G) {
+  const double g11 = psi[SYM(1, 1)], g12 = psi[SYM(1, 2)], g13 = psi[SYM(1, 3)];
+  const double g22 = psi[SYM(2, 2)], g23 = psi[SYM(2, 3)], g33 = psi[SYM(3, 3)];
+  const double A = g22 * g33 - g23 * g23, B = g13 * g23 - g12 * g33, C = g12 * g23 - g13 * g22;
+  const double D = g11 * g33 - g13 * g13, E = g12 * g13 - g11 * g23, F = g11 * g22 - g12 * g12;
+  const double idet = 1.0 / (g11 * A + g12 * B + g13 * C);
+  G.gi[0] = A * idet; G.gi[1] = B * idet; G.gi[2] = C * idet;
+  G.gi[3] = D * idet; G.gi[4] = E * idet; G.gi[5] = F * idet;
+  const double s1 = psi[SYM(0, 1)], s2 = psi[SYM(0, 2)], s3 = psi[SYM(0, 3)];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    G.Nu[i] = G.gi[SYM3(i, 0)] * s1 + G.gi[SYM3(i, 1)] * s2 + G.gi[SYM3(i, 2)] * s3;
+  G.N = sqrt(G.Nu[0] * s1 + G.Nu[1] * s2 + G.Nu[2] * s3 - psi[SYM(0, 0)]);
+  const double iN = 1.0 / G.N;
+  G.tu[0] = iN;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) G.tu[i + 1] = -G.Nu[i] * iN;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = a; b < 4; ++b) {
+      double g4 = (a > 0 && b > 0) ? G.gi[SYM3(a - 1, b - 1)] : 0.0;
+      G.pinv[SYM(a, b)] = g4 - G.tu[a] * G.tu[b];
+    }
+}
+
+// Gamma_cab = 1/2 (d_a psi_cb + d_b psi_ca - d_c psi_ab), with d_0 psi = -N Pi + N^i Phi_i
+// and d_i psi = Phi_i; stored Gm[c][SYM(a,b)].
+__device__ __forceinline__ void christoffel(const Geo& G, const double* Pi, const double* Phi,
+                                            double Gm[4][10]) {
+  double d0[10];
+#pragma unroll
+  for (int n = 0; n < 10; ++n)
+    d0[n] = -G.N * Pi[n] + G.Nu[0] * Phi[n] + G.Nu[1] * Phi[10 + n] + G.Nu[2] * Phi[20 + n];
+  auto dpsi = [&](int a, int n) -> double { return a == 0 ? d0[n] : Phi[(a - 1) * 10 + n]; };
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = a; b < 4; ++b)
+        Gm[c][SYM(a, b)] = 0.5 * (dpsi(a, SYM(c, b)) + dpsi(b, SYM(c, a)) - dpsi(c, SYM(a, b)));
+}
+
+// Frobenius product of two symmetric 4x4 matrices in pair storage.
+__device__ __forceinline__ double sym_dot(const double* X, const double* Y) {
+  double s = 0.0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = a; b < 4; ++b) s += (a == b ? 1.0 : 2.0) * X[SYM(a, b)] * Y[SYM(a, b)];
+  return s;
+}
+
+// Y = P X P for symmetric X, P (pair storage): raises both indices of X with P = psi^ab.
+__device__ __forceinline__ void raise2(const double* P, const double* X, double* Y) {
+  double T[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) s += P[SYM(a, c)] * X[SYM(c, d)];
+      T[a][d] = s;
+    }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = a; b < 4; ++b) {
+      double s = 0.0;
+#pragma unroll
+      for (int d = 0; d < 4; ++d) s += T[a][d] * P[SYM(d, b)];
+      Y[SYM(a, b)] = s;
+    }
+}
+
+// out_ab += coef * (X P Y)_ab, symmetrised over pairs (X, Y symmetric, P symmetric).
+__device__ __forceinline__ void add_xpy(const double* X, const double* P, const double* Y,
+                                        double coef, double* out) {
+  double T[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) s += X[SYM(a, c)] * P[SYM(c, d)];
+      T[a][d] = s;
+    }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = a; b < 4; ++b) {
+      double s = 0.0;
+#pragma unroll
+      for (int d = 0; d < 4; ++d) s += T[a][d] * Y[SYM(d, b)];
+      out[SYM(a, b)] += coef * s;
+    }
+}
+
+struct Jac {   // d_x, d_y, d_z in terms of d_r, d_theta, d_phi
+  double xr, xt, xp, yr, yt, yp, zr, zt;
+};
+
+__device__ __forceinline__ Jac jacobian(const double* ang, double r) {
+  const double st = ang[0], ct = ang[1], sp = ang[2], cp = ang[3];
+  const double ir = 1.0 / r, irs = 1.0 / (r * st);
+  Jac J;
+  J.xr = st * cp; J.xt = ct * cp * ir; J.xp = -sp * irs;
+  J.yr = st * sp; J.yt = ct * sp * ir; J.yp = cp * irs;
+  J.zr = ct; J.zt = -st * ir;
+  return J;
+}
+
+__device__ __forceinline__ void cart(const Jac& J, double dr, double dt, double dp, double* d) {
+  d[0] = J.xr * dr + J.xt * dt + J.xp * dp;
+  d[1] = J.yr * dr + J.yt * dt + J.yp * dp;
+  d[2] = J.zr * dr + J.zt * dt;
+}
+
+__global__ __launch_bounds__(256) void k_pointwise_rhs(
+    const ShellDev* __restrict__ sh, const PtBlock* __restrict__ blk,
+    const double* __restrict__ angtab, const double* __restrict__ radtab,
+    const double* __restrict__ u, const double* __restrict__ dR, const double* __restrict__ dA,
+    const double* __restrict__ Hin, const double* __restrict__ dHin,
+    const double* __restrict__ gamma, double* __restrict__ rhs) {
+  const PtBlock b = blk[blockIdx.x];
+  const ShellDev s = sh[b.shell];
+  const int P = s.n_r * s.S;
+  const int q = b.q0 + threadIdx.x;
+  if (q >= P) return;
+  const int r = q / s.S, a = q - r * s.S;
+  const long long ub = 50LL * s.pt_off + q;                       // field f at ub + f*P
+  const long long ab = 100LL * s.pt_off + (long long)r * 2 * s.S + a;   // d_theta of f at ab + f*n_r*2S
+  const long long astride = (long long)s.n_r * 2 * s.S;
+  const double g0 = gamma[3 * s.instance + 0];
+  const double g1 = gamma[3 * s.instance + 1];
+  const double g2 = gamma[3 * s.instance + 2];
+  const Jac J = jacobian(angtab + 5LL * (s.ang_off + a), radtab[2 * (s.rad_off + r)]);
+
+  double psi[10], Pi[10], Phi[30];
+#pragma unroll
+  for (int n = 0; n < 10; ++n) psi[n] = u[ub + (long long)n * P];
+#pragma unroll
+  for (int n = 0; n < 10; ++n) Pi[n] = u[ub + (long long)(10 + n) * P];
+#pragma unroll
+  for (int n = 0; n < 30; ++n) Phi[n] = u[ub + (long long)(20 + n) * P];
+  Geo G;
+  geometry(psi, G);
+  const double N = G.N;
+
+  // --- d_t psi and d_t Phi: principal part + algebraic part, stored at once;
+  //     principal part of d_t Pi kept for later.
+  double dtPi[10];
+  // t^c t^d Phi_icd and G_ik = g^jk t^c Phi_ijc
+  double ttPhi[3], tPhi[3][3], Gt[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    double s2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int d = 0; d < 4; ++d) s2 += G.tu[c] * G.tu[d] * Phi[i * 10 + SYM(c, d)];
+    ttPhi[i] = s2;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double s1 = 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) s1 += G.tu[c] * Phi[i * 10 + SYM(j + 1, c)];
+      tPhi[i][j] = s1;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double s1 = 0.0;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) s1 += G.gi[SYM3(j, k)] * tPhi[i][j];
+      Gt[i][k] = s1;
+    }
+
+  const long long ob = ub;
+#pragma unroll
+  for (int n = 0; n < 10; ++n) {
+    double dpsi[3], dPi[3], dPhi[3][3];   // dPhi[k][i] = d_k Phi_i
+    {
+      const long long fo = (long long)n * P, fa = (long long)n * astride;
+      cart(J, dR[ub + fo], dA[ab + fa], dA[ab + fa + s.S], dpsi);
+    }
+    {
+      const long long fo = (long long)(10 + n) * P, fa = (long long)(10 + n) * astride;
+      cart(J, dR[ub + fo], dA[ab + fa], dA[ab + fa + s.S], dPi);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const long long fo = (long long)(20 + 10 * i + n) * P, fa = (long long)(20 + 10 * i + n) * astride;
+      double d[3];
+      cart(J, dR[ub + fo], dA[ab + fa], dA[ab + fa + s.S], d);
+      dPhi[0][i] = d[0]; dPhi[1][i] = d[1]; dPhi[2][i] = d[2];
+    }
+    const double adv_psi = G.Nu[0] * dpsi[0] + G.Nu[1] * dpsi[1] + G.Nu[2] * dpsi[2];
+    const double adv_Pi = G.Nu[0] * dPi[0] + G.Nu[1] * dPi[1] + G.Nu[2] * dPi[2];
+    double divPhi = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) divPhi += G.gi[SYM3(k, i)] * dPhi[k][i];
+    const double NPhi = G.Nu[0] * Phi[n] + G.Nu[1] * Phi[10 + n] + G.Nu[2] * Phi[20 + n];
+
+    rhs[ob + (long long)n * P] = (1.0 + g1) * adv_psi - N * Pi[n] - g1 * NPhi;
+    dtPi[n] = adv_Pi - N * divPhi + g1 * g2 * adv_psi - g1 * g2 * NPhi;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double adv = G.Nu[0] * dPhi[0][i] + G.Nu[1] * dPhi[1][i] + G.Nu[2] * dPhi[2][i];
+      double alg = 0.5 * N * ttPhi[i] * Pi[n] - g2 * N * Phi[i * 10 + n];
+      alg += N * (Gt[i][0] * Phi[n] + Gt[i][1] * Phi[10 + n] + Gt[i][2] * Phi[20 + n]);
+      rhs[ob + (long long)(20 + 10 * i + n) * P] = adv - N * dPi[i] + g2 * N * dpsi[i] + alg;
+    }
+  }
+
+  // --- algebraic part of d_t Pi
+  double Gm[4][10];
+  christoffel(G, Pi, Phi, Gm);
+  double H[4], Hup[4], C[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) H[c] = Hin[4LL * s.pt_off + (long long)c * P + q];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    double s1 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s1 += G.pinv[SYM(d, c)] * H[c];
+    Hup[d] = s1;
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) C[c] = H[c] + sym_dot(G.pinv, Gm[c]);
+  const double tC = G.tu[0] * C[0] + G.tu[1] * C[1] + G.tu[2] * C[2] + G.tu[3] * C[3];
+
+  // quad_ab = psi^cd (g^ij Phi_ica Phi_jdb - Pi_ca Pi_db - psi^ef Gamma_ace Gamma_bdf)
+  double quad[10];
+#pragma unroll
+  for (int n = 0; n < 10; ++n) quad[n] = 0.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    double Rj[10];    // Phi^j_ab = g^ji Phi_iab
+#pragma unroll
+    for (int n = 0; n < 10; ++n)
+      Rj[n] = G.gi[SYM3(j, 0)] * Phi[n] + G.gi[SYM3(j, 1)] * Phi[10 + n] + G.gi[SYM3(j, 2)] * Phi[20 + n];
+    add_xpy(Rj, G.pinv, Phi + 10 * j, 1.0, quad);
+  }
+  add_xpy(Pi, G.pinv, Pi, -1.0, quad);
+#pragma unroll
+  for (int bb = 0; bb < 4; ++bb) {
+    double Gh[10];
+    raise2(G.pinv, Gm[bb], Gh);
+#pragma unroll
+    for (int aa = 0; aa <= bb; ++aa) quad[SYM(aa, bb)] -= sym_dot(Gm[aa], Gh);
+  }
+
+  double ttPi = 0.0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int d = 0; d < 4; ++d) ttPi += G.tu[c] * G.tu[d] * Pi[SYM(c, d)];
+  double v[3];    // v_j = (t^c Pi_ci) g^ij
+  {
+    double tPi[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double s1 = 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) s1 += G.tu[c] * Pi[SYM(c, i + 1)];
+      tPi[i] = s1;
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      v[j] = tPi[0] * G.gi[SYM3(0, j)] + tPi[1] * G.gi[SYM3(1, j)] + tPi[2] * G.gi[SYM3(2, j)];
+  }
+  const long long hb = 16LL * s.pt_off + q;
+#pragma unroll
+  for (int aa = 0; aa < 4; ++aa)
+#pragma unroll
+    for (int bb = aa; bb < 4; ++bb) {
+      const int n = SYM(aa, bb);
+      const double dHs = dHin[hb + (long long)(aa * 4 + bb) * P] + dHin[hb + (long long)(bb * 4 + aa) * P];
+      const double GH = Hup[0] * Gm[0][n] + Hup[1] * Gm[1][n] + Hup[2] * Gm[2][n] + Hup[3] * Gm[3][n];
+      const double vPhi = v[0] * Phi[n] + v[1] * Phi[10 + n] + v[2] * Phi[20 + n];
+      // t_a = (-N, 0, 0, 0)
+      const double tCsym = -N * ((aa == 0 ? C[bb] : 0.0) + (bb == 0 ? C[aa] : 0.0));
+      const double damp = tCsym - psi[n] * tC;
+      const double val = dtPi[n] + 2.0 * N * quad[n] - N * dHs + 2.0 * N * GH
+                         - 0.5 * N * ttPi * Pi[n] - N * vPhi + g0 * N * damp;
+      rhs[ob + (long long)(10 + n) * P] = val;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Boundary treatment: characteristic upwinding at interfaces, Dirichlet at the
+// outer boundary.  blockIdx.y = shell; threads over angular points.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_boundary(const ShellDev* __restrict__ sh,
+                                                  const double* __restrict__ bctab,
+                                                  const double* __restrict__ gamma,
+                                                  double* __restrict__ rhs) {
+  const int k = blockIdx.y;
+  const ShellDev s = sh[k];
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= s.S) return;
+  const int P = s.n_r * s.S;
+  const long long ia = 50LL * s.pt_off + (long long)(s.n_r - 1) * s.S + a;
+  if (s.outer) {
+#pragma unroll 10
+    for (int f = 0; f < 50; ++f) rhs[ia + (long long)f * P] = 0.0;
+    return;
+  }
+  if (s.bc_off < 0) return;
+  const ShellDev t = sh[k + 1];
+  const int Pt = t.n_r * t.S;
+  const long long ib = 50LL * t.pt_off + a;
+  const double* T = bctab + s.bc_off + 9LL * a;
+  const double sl[3] = {T[0], T[1], T[2]}, su[3] = {T[3], T[4], T[5]};
+  const double w0 = T[6], wp = T[7], wm = T[8];
+  const double g2 = gamma[3 * s.instance + 2];
+#pragma unroll 2
+  for (int n = 0; n < 10; ++n) {
+    double A[5], B[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      A[c] = rhs[ia + (long long)(10 * c + n) * P];
+      B[c] = rhs[ib + (long long)(10 * c + n) * Pt];
+    }
+    const double sPa = su[0] * A[2] + su[1] * A[3] + su[2] * A[4];
+    const double sPb = su[0] * B[2] + su[1] * B[3] + su[2] * B[4];
+    const double upsi = 0.5 * (A[0] + B[0]);
+    const double up = wp * (A[1] + sPa - g2 * A[0]) + (1.0 - wp) * (B[1] + sPb - g2 * B[0]);
+    const double um = wm * (A[1] - sPa - g2 * A[0]) + (1.0 - wm) * (B[1] - sPb - g2 * B[0]);
+    double out[5];
+    out[0] = upsi;
+    out[1] = 0.5 * (up + um) + g2 * upsi;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double u0 = w0 * (A[2 + i] - sl[i] * sPa) + (1.0 - w0) * (B[2 + i] - sl[i] * sPb);
+      out[2 + i] = u0 + 0.5 * sl[i] * (up - um);
+    }
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      rhs[ia + (long long)(10 * c + n) * P] = out[c];
+      rhs[ib + (long long)(10 * c + n) * Pt] = out[c];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// SSP-RK3 stage: out = c0 u0 + c1 (u + dt L), dt per instance; blockIdx.y = field.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_rk_stage(const ShellDev* __restrict__ sh,
+                                                  const PtBlock* __restrict__ blk,
+                                                  const double* __restrict__ dt, double c0,
+                                                  const double* u0, double c1,
+                                                  const double* __restrict__ u,
+                                                  const double* __restrict__ L,
+                                                  double* out) {
+  const PtBlock b = blk[blockIdx.x];
+  const ShellDev s = sh[b.shell];
+  const int P = s.n_r * s.S;
+  const int q = b.q0 + threadIdx.x;
+  if (q >= P) return;
+  const long long e = 50LL * s.pt_off + (long long)blockIdx.y * P + q;
+  const double h = dt[s.instance];
+  double v = c1 * (u[e] + h * L[e]);
+  if (c0 != 0.0) v += c0 * u0[e];
+  out[e] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Constraints: 64 components per point and the weighted sum of squares per block.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_constraints(
+    const ShellDev* __restrict__ sh, const PtBlock* __restrict__ blk,
+    const double* __restrict__ angtab, const double* __restrict__ radtab,
+    const double* __restrict__ u, const double* __restrict__ dR, const double* __restrict__ dA,
+    const double* __restrict__ Hin, double* __restrict__ Cout, double* __restrict__ partial) {
+  __shared__ double red[256];
+  const PtBlock b = blk[blockIdx.x];
+  const ShellDev s = sh[b.shell];
+  const int P = s.n_r * s.S;
+  const int q = b.q0 + threadIdx.x;
+  double ssq = 0.0;
+  if (q < P) {
+    const int r = q / s.S, a = q - r * s.S;
+    const long long ub = 50LL * s.pt_off + q;
+    const long long ab = 100LL * s.pt_off + (long long)r * 2 * s.S + a;
+    const long long astride = (long long)s.n_r * 2 * s.S;
+    const double* ang = angtab + 5LL * (s.ang_off + a);
+    const Jac J = jacobian(ang, radtab[2 * (s.rad_off + r)]);
+    const double w = ang[4] * radtab[2 * (s.rad_off + r) + 1];
+    const long long cb = 64LL * s.pt_off + q;
+    double psi[10], Pi[10], Phi[30];
+#pragma unroll
+    for (int n = 0; n < 10; ++n) psi[n] = u[ub + (long long)n * P];
+#pragma unroll
+    for (int n = 0; n < 10; ++n) Pi[n] = u[ub + (long long)(10 + n) * P];
+#pragma unroll
+    for (int n = 0; n < 30; ++n) Phi[n] = u[ub + (long long)(20 + n) * P];
+    Geo G;
+    geometry(psi, G);
+    double Gm[4][10];
+    christoffel(G, Pi, Phi, Gm);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double Ca = Hin[4LL * s.pt_off + (long long)c * P + q] + sym_dot(G.pinv, Gm[c]);
+      ssq += Ca * Ca;
+      if (Cout) Cout[cb + (long long)c * P] = Ca;
+    }
+    // C_iab = d_i psi_ab - Phi_iab
+#pragma unroll 2
+    for (int n = 0; n < 10; ++n) {
+      const long long fo = (long long)n * P, fa = (long long)n * astride;
+      double d[3];
+      cart(J, dR[ub + fo], dA[ab + fa], dA[ab + fa + s.S], d);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const double c3 = d[i] - Phi[10 * i + n];
+        ssq += c3 * c3;
+        if (Cout) Cout[cb + (long long)(4 + 10 * i + n) * P] = c3;
+      }
+    }
+    // C_ijab = d_i Phi_jab - d_j Phi_iab, (i,j) = (x,y), (x,z), (y,z)
+#pragma unroll 2
+    for (int n = 0; n < 10; ++n) {
+      double dPhi[3][3];   // dPhi[k][i] = d_k Phi_i
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const long long fo = (long long)(20 + 10 * i + n) * P;
+        const long long fa = (long long)(20 + 10 * i + n) * astride;
+        double d[3];
+        cart(J, dR[ub + fo], dA[ab + fa], dA[ab + fa + s.S], d);
+        dPhi[0][i] = d[0]; dPhi[1][i] = d[1]; dPhi[2][i] = d[2];
+      }
+      const double c01 = dPhi[0][1] - dPhi[1][0];
+      const double c02 = dPhi[0][2] - dPhi[2][0];
+      const double c12 = dPhi[1][2] - dPhi[2][1];
+      ssq += c01 * c01 + c02 * c02 + c12 * c12;
+      if (Cout) {
+        Cout[cb + (long long)(34 + n) * P] = c01;
+        Cout[cb + (long long)(44 + n) * P] = c02;
+        Cout[cb + (long long)(54 + n) * P] = c12;
+      }
+    }
+    ssq *= w;
+  }
+  red[threadIdx.x] = ssq;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// norm[i] = sqrt(sum_{blocks of instance i} partial / wsum[i]); one block per instance.
+__global__ __launch_bounds__(256) void k_reduce_norm(const int* __restrict__ range,
+                                                     const double* __restrict__ partial,
+                                                     const double* __restrict__ wsum,
+                                                     double* __restrict__ norm) {
+  __shared__ double red[256];
+  const int i = blockIdx.x;
+  const int b0 = range[2 * i], b1 = range[2 * i + 1];
+  double s = 0.0;
+  for (int b = b0 + threadIdx.x; b < b1; b += 256) s += partial[b];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) norm[i] = sqrt(red[0] / wsum[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Setup: frozen interface projections from u_bg, and excision outflow speeds.
+// bctab record per interface point: s_i (3), s^i (3), upwind weights of the
+// inner side for u^0, u^+, u^- (1, 0 or 1/2 by the sign of the speed).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void face_normal(const double* u_bg, long long ib, int P, const double* ang,
+                                            double sign, double* sl, double* su, double* v0,
+                                            double* vp, double* vm) {
+  double psi[10];
+#pragma unroll
+  for (int n = 0; n < 10; ++n) psi[n] = u_bg[ib + (long long)n * P];
+  Geo G;
+  geometry(psi, G);
+  const double nh[3] = {sign * ang[0] * ang[3], sign * ang[0] * ang[2], sign * ang[1]};
+  double nrm2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) nrm2 += G.gi[SYM3(i, j)] * nh[i] * nh[j];
+  const double inrm = 1.0 / sqrt(nrm2);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) sl[i] = nh[i] * inrm;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    su[i] = G.gi[SYM3(i, 0)] * sl[0] + G.gi[SYM3(i, 1)] * sl[1] + G.gi[SYM3(i, 2)] * sl[2];
+  const double sN = sl[0] * G.Nu[0] + sl[1] * G.Nu[1] + sl[2] * G.Nu[2];
+  *v0 = -sN;
+  *vp = -sN + G.N;
+  *vm = -sN - G.N;
+}
+
+__device__ __forceinline__ double upwind_weight(double v) { return v > 0.0 ? 1.0 : (v < 0.0 ? 0.0 : 0.5); }
+
+__global__ __launch_bounds__(256) void k_bc_setup(const ShellDev* __restrict__ sh, int max_S,
+                                                  const double* __restrict__ angtab,
+                                                  const double* __restrict__ u_bg,
+                                                  double* __restrict__ bctab,
+                                                  double* __restrict__ exmin) {
+  const int k = blockIdx.y;
+  const ShellDev s = sh[k];
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= s.S) return;
+  const int P = s.n_r * s.S;
+  const double* ang = angtab + 5LL * (s.ang_off + a);
+  double sl[3], su[3], v0, vp, vm;
+  if (s.bc_off >= 0) {
+    const long long ib = 50LL * s.pt_off + (long long)(s.n_r - 1) * s.S + a;
+    face_normal(u_bg, ib, P, ang, 1.0, sl, su, &v0, &vp, &vm);
+    double* T = bctab + s.bc_off + 9LL * a;
+    T[0] = sl[0]; T[1] = sl[1]; T[2] = sl[2];
+    T[3] = su[0]; T[4] = su[1]; T[5] = su[2];
+    T[6] = upwind_weight(v0); T[7] = upwind_weight(vp); T[8] = upwind_weight(vm);
+  }
+  double mn = INFINITY;
+  if (s.inner) {
+    const long long ib = 50LL * s.pt_off + a;
+    face_normal(u_bg, ib, P, ang, -1.0, sl, su, &v0, &vp, &vm);
+    mn = fmin(v0, fmin(vp, vm));
+    if (mn != mn) mn = -INFINITY;   // NaN speed: report as inflow
+  }
+  exmin[(long long)k * max_S + a] = mn;
+}
+
+__global__ __launch_bounds__(256) void k_nonfinite(const double* __restrict__ x, long long n,
+                                                   int* __restrict__ count) {
+  int c = 0;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    c += isfinite(x[i]) ? 0 : 1;
+  if (c) atomicAdd(count, c);
+}
+
+}  // namespace
+
+namespace ghk {
+
+void tile_dims(int shape, int* bm, int* bn) {
+  switch (shape) {
+    case T64x64: *bm = 64; *bn = 64; break;
+    case T64x128: *bm = 64; *bn = 128; break;
+    case T128x64: *bm = 128; *bn = 64; break;
+    default: *bm = 128; *bn = 128; break;
+  }
+}
+
+hipError_t gemm(int shape, const GemmTile* tiles, int n_tiles, const GemmGroup* groups,
+                const double* Abase, double* Cbase, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  dim3 grid(n_tiles), block(256);
+  switch (shape) {
+    case T64x64: hipLaunchKernelGGL((k_gemm<64, 64>), grid, block, 0, st, tiles, groups, Abase, Cbase); break;
+    case T64x128: hipLaunchKernelGGL((k_gemm<64, 128>), grid, block, 0, st, tiles, groups, Abase, Cbase); break;
+    case T128x64: hipLaunchKernelGGL((k_gemm<128, 64>), grid, block, 0, st, tiles, groups, Abase, Cbase); break;
+    default: hipLaunchKernelGGL((k_gemm<128, 128>), grid, block, 0, st, tiles, groups, Abase, Cbase); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t radial(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* dtab,
+                  const double* u, double* dR, int ncomp_lo, int ncomp_hi, hipStream_t st) {
+  dim3 grid(n_blk, ncomp_hi - ncomp_lo), block(256);
+  hipLaunchKernelGGL(k_radial, grid, block, 0, st, sh, blk, dtab, u, dR, ncomp_lo);
+  return hipGetLastError();
+}
+
+hipError_t pointwise_rhs(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* angtab,
+                         const double* radtab, const double* u, const double* dR, const double* dA,
+                         const double* H, const double* dH, const double* gamma, double* rhs,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_pointwise_rhs, dim3(n_blk), dim3(256), 0, st, sh, blk, angtab, radtab, u, dR,
+                     dA, H, dH, gamma, rhs);
+  return hipGetLastError();
+}
+
+hipError_t boundary(const ShellDev* sh, int n_shells, int max_S, const double* bctab,
+                    const double* gamma, double* rhs, hipStream_t st) {
+  dim3 grid((max_S + 255) / 256, n_shells), block(256);
+  hipLaunchKernelGGL(k_boundary, grid, block, 0, st, sh, bctab, gamma, rhs);
+  return hipGetLastError();
+}
+
+hipError_t rk_stage(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* dt,
+                    double c0, const double* u0, double c1, const double* u, const double* L,
+                    double* out, hipStream_t st) {
+  dim3 grid(n_blk, 50), block(256);
+  hipLaunchKernelGGL(k_rk_stage, grid, block, 0, st, sh, blk, dt, c0, u0, c1, u, L, out);
+  return hipGetLastError();
+}
+
+hipError_t constraints(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* angtab,
+                       const double* radtab, const double* u, const double* dR, const double* dA,
+                       const double* H, double* C, double* partial, hipStream_t st) {
+  hipLaunchKernelGGL(k_constraints, dim3(n_blk), dim3(256), 0, st, sh, blk, angtab, radtab, u, dR,
+                     dA, H, C, partial);
+  return hipGetLastError();
+}
+
+hipError_t reduce_norm(const int* range, int n_inst, const double* partial, const double* wsum,
+                       double* norm, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_norm, dim3(n_inst), dim3(256), 0, st, range, partial, wsum, norm);
+  return hipGetLastError();
+}
+
+hipError_t bc_setup(const ShellDev* sh, int n_shells, int max_S, const double* angtab,
+                    const double* u_bg, double* bctab, double* exmin, hipStream_t st) {
+  dim3 grid((max_S + 255) / 256, n_shells), block(256);
+  hipLaunchKernelGGL(k_bc_setup, grid, block, 0, st, sh, max_S, angtab, u_bg, bctab, exmin);
+  return hipGetLastError();
+}
+
+hipError_t nonfinite_count(const double* x, long long n, int* count, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  long long nb = (n + 255) / 256;
+  int grid = (int)(nb < 4096 ? nb : 4096);
+  hipLaunchKernelGGL(k_nonfinite, dim3(grid), dim3(256), 0, st, x, n, count);
+  return hipGetLastError();
+}
+
+}  // namespace ghk

@@ -1,0 +1,253 @@
+// Host-side construction of grids and dense spectral operators.
+//
+// The paper traces each linear spectral operation into an explicit matrix and
+// keeps it in a dictionary keyed by what makes it unique (section "Spectral
+// Operations", eq. Differentiation; the dictionary paragraph that follows).
+// Here the matrices are built directly from closed forms:
+//  * radial: the Chebyshev-Gauss-Lobatto differentiation matrix;
+//  * angular: Theta = Syn_dtheta * Ana and Phi = Syn_dphi * Ana, with Ana the
+//    Gauss-Legendre x trapezoid quadrature onto the (L+1)^2 real orthonormal
+//    Y_lm and Syn_d* the derivatives of the Y_lm at the nodes
+//    (eq. DifferentiatorI1S2: both angular operators are full S x S matrices);
+//  * filter: Syn * diag(sigma_l) * Ana.
+// Normalised associated Legendre functions come from the standard normalised
+// three-term recurrences (no factorials), their theta-derivative from
+// dP_l^m/dtheta = (l x P_l^m - sqrt((2l+1)(l^2-m^2)/(2l-1)) P_{l-1}^m) / sin(theta).
+#include "ghmi_setup.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace ghsetup {
+
+static const double kPi = 3.14159265358979323846;
+
+std::vector<double> cgl_nodes(int n) {
+  std::vector<double> xi(n);
+  for (int j = 0; j < n; ++j) xi[j] = -std::cos(kPi * j / (n - 1));
+  return xi;
+}
+
+std::vector<double> cgl_diff_matrix(int n) {
+  // Off-diagonal entries use xi_i - xi_j = 2 sin(pi (i+j)/(2N)) sin(pi (i-j)/(2N)), N = n-1,
+  // which avoids the cancellation of subtracting clustered end nodes (the
+  // trigonometric-identity form of Don & Solomonoff, SIAM J. Sci. Comput. 18, 1997);
+  // the diagonal is minus the off-diagonal row sum, so D annihilates constants.
+  const int N = n - 1;
+  std::vector<double> D(size_t(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double ci = (i == 0 || i == N) ? 2.0 : 1.0;
+    double rowsum = 0.0;
+    for (int j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double cj = (j == 0 || j == N) ? 2.0 : 1.0;
+      double sgn = ((i + j) & 1) ? -1.0 : 1.0;
+      double diff = 2.0 * std::sin(kPi * (i + j) / (2.0 * N)) * std::sin(kPi * (i - j) / (2.0 * N));
+      double v = (ci / cj) * sgn / diff;
+      D[size_t(i) * n + j] = v;
+      rowsum += v;
+    }
+    D[size_t(i) * n + i] = -rowsum;
+  }
+  return D;
+}
+
+std::vector<double> clenshaw_curtis(int n) {
+  // N = n-1 intervals, nodes cos(j pi / N); symmetric under j -> N-j, so the
+  // increasing ordering of the nodes does not matter.
+  int N = n - 1;
+  std::vector<double> w(n, 0.0);
+  if (N == 0) { w[0] = 2.0; return w; }
+  for (int j = 0; j <= N; ++j) {
+    double th = kPi * j / N;
+    if (j == 0 || j == N) {
+      w[j] = (N % 2 == 0) ? 1.0 / (double(N) * N - 1.0) : 1.0 / (double(N) * N);
+      continue;
+    }
+    double v = 1.0;
+    if (N % 2 == 0) {
+      for (int k = 1; k <= N / 2 - 1; ++k) v -= 2.0 * std::cos(2.0 * k * th) / (4.0 * k * k - 1.0);
+      v -= std::cos(N * th) / (double(N) * N - 1.0);
+    } else {
+      for (int k = 1; k <= (N - 1) / 2; ++k) v -= 2.0 * std::cos(2.0 * k * th) / (4.0 * k * k - 1.0);
+    }
+    w[j] = 2.0 * v / N;
+  }
+  return w;
+}
+
+void gauss_legendre(int L, std::vector<double>& x, std::vector<double>& w) {
+  int n = L + 1;
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      double pn = (n == 1) ? z : p1;
+      double pm = (n == 1) ? 1.0 : p0;
+      dp = n * (z * pn - pm) / (z * z - 1.0);
+      double dz = pn / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) {
+        // one more update of the derivative at the converged node
+        p0 = 1.0; p1 = z;
+        for (int k = 2; k <= n; ++k) {
+          double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        pn = (n == 1) ? z : p1;
+        pm = (n == 1) ? 1.0 : p0;
+        dp = n * (z * pn - pm) / (z * z - 1.0);
+        break;
+      }
+    }
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+  // sort increasing in x
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return x[a] < x[b]; });
+  std::vector<double> xs(n), ws(n);
+  for (int i = 0; i < n; ++i) { xs[i] = x[idx[i]]; ws[i] = w[idx[i]]; }
+  // enforce exact antisymmetry of the nodes (they come in +- pairs)
+  for (int i = 0; i < n / 2; ++i) {
+    double a = 0.5 * (xs[n - 1 - i] - xs[i]);
+    double b = 0.5 * (ws[n - 1 - i] + ws[i]);
+    xs[i] = -a; xs[n - 1 - i] = a;
+    ws[i] = b; ws[n - 1 - i] = b;
+  }
+  if (n % 2 == 1) xs[n / 2] = 0.0;
+  x = xs;
+  w = ws;
+}
+
+// Normalised P_l^m(x) (including 1/sqrt(4 pi), no Condon-Shortley phase) and
+// d/dtheta of it, for 0 <= m <= l <= L at one node: arrays [(L+1)*(L+1)], index l*(L+1)+m.
+static void legendre_normalised(int L, double x, std::vector<double>& P, std::vector<double>& dP) {
+  int n = L + 1;
+  P.assign(size_t(n) * n, 0.0);
+  dP.assign(size_t(n) * n, 0.0);
+  double s = std::sqrt(1.0 - x * x);
+  double pmm = 1.0 / std::sqrt(4.0 * kPi);
+  for (int m = 0; m <= L; ++m) {
+    if (m > 0) pmm *= std::sqrt((2.0 * m + 1.0) / (2.0 * m)) * s;
+    P[size_t(m) * n + m] = pmm;
+    if (m + 1 <= L) P[size_t(m + 1) * n + m] = std::sqrt(2.0 * m + 3.0) * x * pmm;
+    for (int l = m + 2; l <= L; ++l) {
+      double a = std::sqrt((4.0 * l * l - 1.0) / (double(l) * l - double(m) * m));
+      double b = std::sqrt((double(l - 1) * (l - 1) - double(m) * m) / (4.0 * (l - 1) * (l - 1) - 1.0));
+      P[size_t(l) * n + m] = a * (x * P[size_t(l - 1) * n + m] - b * P[size_t(l - 2) * n + m]);
+    }
+  }
+  for (int m = 0; m <= L; ++m)
+    for (int l = m; l <= L; ++l) {
+      double prev = (l - 1 >= m) ? P[size_t(l - 1) * n + m] : 0.0;
+      double c = std::sqrt((2.0 * l + 1.0) * (double(l) * l - double(m) * m) / (2.0 * l - 1.0));
+      dP[size_t(l) * n + m] = (l * x * P[size_t(l) * n + m] - c * prev) / s;
+    }
+}
+
+std::vector<double> exp_filter_sigma(int L, double eta_c, double alpha, double order) {
+  std::vector<double> sig(L + 1, 1.0);
+  if (L == 0) return sig;
+  for (int l = 0; l <= L; ++l) {
+    double q = double(l) / double(L);
+    if (q > eta_c) sig[l] = std::exp(-alpha * std::pow((q - eta_c) / (1.0 - eta_c), order));
+  }
+  return sig;
+}
+
+// Tables of the real Y_lm and their derivatives at all S nodes.
+// mode index = l*l + l + m; returns Y, dY/dtheta, dY/dphi as [(L+1)^2][S].
+static void ylm_node_tables(int L, std::vector<double>& Y, std::vector<double>& Yt,
+                            std::vector<double>& Yp, std::vector<double>& W) {
+  std::vector<double> x, w;
+  gauss_legendre(L, x, w);
+  int nth = L + 1, nph = 2 * (L + 1), S = nth * nph, nm = (L + 1) * (L + 1), n = L + 1;
+  Y.assign(size_t(nm) * S, 0.0);
+  Yt.assign(size_t(nm) * S, 0.0);
+  Yp.assign(size_t(nm) * S, 0.0);
+  W.assign(S, 0.0);
+  const double r2 = std::sqrt(2.0);
+  std::vector<double> P, dP;
+  for (int i = 0; i < nth; ++i) {
+    legendre_normalised(L, x[i], P, dP);
+    for (int k = 0; k < nph; ++k) {
+      int a = i * nph + k;
+      double ph = 2.0 * kPi * k / nph;
+      W[a] = w[i] * 2.0 * kPi / nph;
+      for (int l = 0; l <= L; ++l) {
+        Y[size_t(l * l + l) * S + a] = P[size_t(l) * n + 0];
+        Yt[size_t(l * l + l) * S + a] = dP[size_t(l) * n + 0];
+        for (int m = 1; m <= l; ++m) {
+          double c = std::cos(m * ph), sn = std::sin(m * ph);
+          double p = r2 * P[size_t(l) * n + m], dp = r2 * dP[size_t(l) * n + m];
+          size_t ip = size_t(l * l + l + m) * S + a, im = size_t(l * l + l - m) * S + a;
+          Y[ip] = p * c;
+          Y[im] = p * sn;
+          Yt[ip] = dp * c;
+          Yt[im] = dp * sn;
+          Yp[ip] = -m * p * sn;
+          Yp[im] = m * p * c;
+        }
+      }
+    }
+  }
+}
+
+std::vector<double> sphere_operator(int L, int which, const std::vector<double>& sigma) {
+  std::vector<double> Y, Yt, Yp, W;
+  ylm_node_tables(L, Y, Yt, Yp, W);
+  int S = 2 * (L + 1) * (L + 1), nm = (L + 1) * (L + 1);
+  const std::vector<double>& Syn = (which == 0) ? Yt : (which == 1) ? Yp : Y;
+  // Ana[lm][a] = W_a Y_lm(a), scaled by sigma_l for the filter
+  std::vector<double> Ana(size_t(nm) * S);
+  for (int l = 0; l <= L; ++l)
+    for (int m = -l; m <= l; ++m) {
+      int lm = l * l + l + m;
+      double f = (which == 2) ? sigma[l] : 1.0;
+      for (int a = 0; a < S; ++a) Ana[size_t(lm) * S + a] = f * W[a] * Y[size_t(lm) * S + a];
+    }
+  std::vector<double> M(size_t(S) * S, 0.0);
+  for (int j = 0; j < S; ++j) {
+    double* row = &M[size_t(j) * S];
+    for (int lm = 0; lm < nm; ++lm) {
+      double c = Syn[size_t(lm) * S + j];
+      if (c == 0.0) continue;
+      const double* ar = &Ana[size_t(lm) * S];
+      for (int a = 0; a < S; ++a) row[a] += c * ar[a];
+    }
+  }
+  return M;
+}
+
+std::vector<double> angular_table(int L) {
+  std::vector<double> x, w;
+  gauss_legendre(L, x, w);
+  int nth = L + 1, nph = 2 * (L + 1), S = nth * nph;
+  std::vector<double> t(size_t(S) * 5);
+  for (int i = 0; i < nth; ++i) {
+    double st = std::sqrt(1.0 - x[i] * x[i]);
+    for (int k = 0; k < nph; ++k) {
+      double ph = 2.0 * kPi * k / nph;
+      size_t a = size_t(i * nph + k) * 5;
+      t[a + 0] = st;
+      t[a + 1] = x[i];
+      t[a + 2] = std::sin(ph);
+      t[a + 3] = std::cos(ph);
+      t[a + 4] = w[i] * 2.0 * kPi / nph;
+    }
+  }
+  return t;
+}
+
+}  // namespace ghsetup

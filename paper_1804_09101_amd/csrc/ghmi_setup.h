@@ -1,0 +1,33 @@
+// Host-side construction of the collocation grid and of the dense spectral
+// operators (the paper's traced matrices, section "Spectral Operations",
+// eqs. Differentiation and DifferentiatorI1S2).  Pure C++, no HIP.
+#pragma once
+#include <vector>
+
+namespace ghsetup {
+
+// Chebyshev-Gauss-Lobatto nodes xi_j = -cos(pi j/(n-1)), increasing.
+std::vector<double> cgl_nodes(int n);
+
+// CGL first-derivative matrix D[i*n+j] (d/dxi), barycentric closed form
+// D_ij = (c_i/c_j) (-1)^(i+j) / (xi_i - xi_j), diagonal = minus the row sum.
+std::vector<double> cgl_diff_matrix(int n);
+
+// Clenshaw-Curtis weights on the CGL nodes (Trefethen's closed form).
+std::vector<double> clenshaw_curtis(int n);
+
+// Gauss-Legendre nodes (increasing) and weights for L+1 points (Newton on P_{L+1}).
+void gauss_legendre(int L, std::vector<double>& x, std::vector<double>& w);
+
+// Dense S x S operators on one sphere, row-major (out_j = sum_a M[j*S+a] u_a):
+//   which 0: d/dtheta, 1: d/dphi, 2: filter with factors sigma_l (sigma has L+1 entries).
+std::vector<double> sphere_operator(int L, int which, const std::vector<double>& sigma);
+
+// Filter factors sigma_l = 1 (l/L <= eta_c), else exp(-alpha((l/L-eta_c)/(1-eta_c))^order).
+std::vector<double> exp_filter_sigma(int L, double eta_c, double alpha, double order);
+
+// Per angular point (i, k): sin(theta), cos(theta), sin(phi), cos(phi), and the
+// angular quadrature weight w_i * 2 pi / N_phi; 5 doubles each, S entries.
+std::vector<double> angular_table(int L);
+
+}  // namespace ghsetup

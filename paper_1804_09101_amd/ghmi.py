@@ -1,0 +1,238 @@
+"""Python binding of libghmi.so (the C interface in include/ghmi.h).
+
+Argument marshalling only: every step of the evolution runs in the HIP
+library.  PyTorch supplies device memory (float64 CUDA tensors) and the
+current HIP stream.  If the library has not been built, importing the
+binding's entry points raises -- there is no CPU fallback.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libghmi.so")
+
+GH_ERRORS = {
+    -1: "GH_ERR_ARG", -2: "GH_ERR_SHAPE", -3: "GH_ERR_ORDER", -4: "GH_ERR_OOM",
+    -5: "GH_ERR_NOT_OUTFLOW", -6: "GH_ERR_NONFINITE", -7: "GH_ERR_DEVICE",
+}
+
+# Every symbol declared in include/ghmi.h.
+EXPORTS = [
+    "gh_create", "gh_destroy", "gh_set_stream", "gh_set_domain", "gh_num_points",
+    "gh_set_background", "gh_set_params", "gh_rhs", "gh_step", "gh_constraints",
+    "gh_last_error", "gh_grid_coords", "gh_host_operator", "gh_set_timing", "gh_kernel_stats",
+]
+
+KERNEL_KINDS = {"deriv_gemm": 0, "filter_gemm": 1, "radial": 2, "pointwise": 3, "boundary": 4,
+                "rk_stage": 5}
+
+
+class GHError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{GH_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class gh_shell(ctypes.Structure):
+    _fields_ = [("instance", ctypes.c_int), ("n_r", ctypes.c_int), ("L", ctypes.c_int),
+                ("r_in", ctypes.c_double), ("r_out", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libghmi.so (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError(f"{path} not found: build it with __graft_entry__.build() "
+                      "(paper_1804_09101_amd/_build.py); there is no fallback path")
+    lib = ctypes.CDLL(path)
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    pd = ctypes.POINTER(ctypes.c_double)
+    pll = ctypes.POINTER(ctypes.c_longlong)
+    psh = ctypes.POINTER(gh_shell)
+    sig = {
+        "gh_create": (i, [ctypes.POINTER(vp), i, vp]),
+        "gh_destroy": (i, [vp]),
+        "gh_set_stream": (i, [vp, vp]),
+        "gh_set_domain": (i, [vp, i, i, psh, i, pd]),
+        "gh_num_points": (i, [vp, pll, pll]),
+        "gh_set_background": (i, [vp, vp, vp, vp]),
+        "gh_set_params": (i, [vp, pd, pd]),
+        "gh_rhs": (i, [vp, vp, vp]),
+        "gh_step": (i, [vp, vp, i]),
+        "gh_constraints": (i, [vp, vp, vp, vp]),
+        "gh_last_error": (ctypes.c_char_p, [vp]),
+        "gh_grid_coords": (i, [i, psh, pd]),
+        "gh_host_operator": (i, [i, i, pd, pd]),
+        "gh_set_timing": (i, [vp, i]),
+        "gh_kernel_stats": (i, [vp, i, pll, pd]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _shell_array(shells):
+    arr = (gh_shell * len(shells))()
+    for k, s in enumerate(shells):
+        inst, n_r, L, r_in, r_out = s
+        arr[k] = gh_shell(int(inst), int(n_r), int(L), float(r_in), float(r_out))
+    return arr
+
+
+def _dptr(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def grid_coords(shells):
+    """Cartesian coordinates [3, P] of the collocation points (host-only call)."""
+    lib = load_library()
+    arr = _shell_array(shells)
+    P = sum(int(s[1]) * 2 * (int(s[2]) + 1) ** 2 for s in shells)
+    out = np.zeros((3, P))
+    rc = lib.gh_grid_coords(len(shells), arr, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc:
+        raise GHError(rc, "gh_grid_coords")
+    return out
+
+
+def host_operator(kind, n, params=None):
+    """Dense operator as the library builds it (host-only call); see include/ghmi.h."""
+    lib = load_library()
+    if kind == 0:
+        shape = (n, n)
+    elif kind in (1, 2, 3):
+        S = 2 * (n + 1) ** 2
+        shape = (S, S)
+    elif kind == 4:
+        shape = (n,)
+    elif kind == 5:
+        shape = (2, n + 1)
+    else:
+        raise ValueError("unknown operator kind")
+    out = np.zeros(shape)
+    keep, pp = _dptr(params if params is not None else [0.0, 0.0, 0.0])
+    rc = lib.gh_host_operator(kind, n, pp, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc:
+        raise GHError(rc, "gh_host_operator")
+    return out
+
+
+class GHSolver:
+    """One context of the library: a domain, its background and parameters.
+
+    shells: sequence of (instance, n_r, L, r_in, r_out).
+    filter_params: None, or (eta_c, alpha, order) for the angular exponential filter.
+    """
+
+    def __init__(self, shells, n_inst=None, filter_params=None, device=0):
+        import torch
+        self._torch = torch
+        self.lib = load_library()
+        self.shells = [tuple(s) for s in shells]
+        self.n_inst = n_inst if n_inst is not None else 1 + max(int(s[0]) for s in self.shells)
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        rc = self.lib.gh_create(ctypes.byref(h), device, ctypes.c_void_p(self._stream()))
+        if rc:
+            raise GHError(rc, "gh_create failed (no HIP device?)")
+        self.h = h
+        arr = _shell_array(self.shells)
+        kind = 0 if filter_params is None else 1
+        self._fp, fpp = _dptr(filter_params if filter_params is not None else [0.0, 0.0, 0.0])
+        self._check(self.lib.gh_set_domain(self.h, self.n_inst, len(self.shells), arr, kind, fpp))
+        tot = ctypes.c_longlong()
+        offs = (ctypes.c_longlong * (len(self.shells) + 1))()
+        self._check(self.lib.gh_num_points(self.h, ctypes.byref(tot), offs))
+        self.P = int(tot.value)
+        self.offsets = np.array(list(offs), dtype=np.int64)
+
+    # -- helpers -------------------------------------------------------------
+    def _stream(self):
+        return self._torch.cuda.current_stream().cuda_stream
+
+    def _check(self, rc):
+        if rc:
+            msg = self.lib.gh_last_error(self.h)
+            raise GHError(rc, msg.decode() if msg else "")
+
+    def _sync_stream(self):
+        self._check(self.lib.gh_set_stream(self.h, ctypes.c_void_p(self._stream())))
+
+    def _dev(self, t, ncomp, name):
+        torch = self._torch
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+            raise TypeError(f"{name} must be a float64 CUDA tensor")
+        if not t.is_contiguous() or t.numel() != ncomp * self.P:
+            raise ValueError(f"{name} must be contiguous with {ncomp}*P = {ncomp * self.P} elements")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def new_field(self, ncomp=50):
+        return self._torch.zeros(ncomp * self.P, dtype=self._torch.float64, device=self.device)
+
+    # -- API ---------------------------------------------------------------------
+    def set_background(self, H, dH, u_bg):
+        self._sync_stream()
+        self._check(self.lib.gh_set_background(self.h, self._dev(H, 4, "H"), self._dev(dH, 16, "dH"),
+                                               self._dev(u_bg, 50, "u_bg")))
+
+    def set_params(self, gamma, dt=None):
+        g, gp = _dptr(np.asarray(gamma, dtype=float).reshape(self.n_inst, 3))
+        if dt is None:
+            self._check(self.lib.gh_set_params(self.h, gp, None))
+        else:
+            d, dp = _dptr(np.asarray(dt, dtype=float).reshape(self.n_inst))
+            self._check(self.lib.gh_set_params(self.h, gp, dp))
+
+    def rhs(self, u, out=None):
+        out = self.new_field() if out is None else out
+        self._sync_stream()
+        self._check(self.lib.gh_rhs(self.h, self._dev(u, 50, "u"), self._dev(out, 50, "dudt")))
+        return out
+
+    def step(self, u, n_steps=1):
+        self._sync_stream()
+        self._check(self.lib.gh_step(self.h, self._dev(u, 50, "u"), int(n_steps)))
+        return u
+
+    def constraints(self, u, want_C=True):
+        torch = self._torch
+        C = self.new_field(64) if want_C else None
+        norm = torch.zeros(self.n_inst, dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        self._check(self.lib.gh_constraints(self.h, self._dev(u, 50, "u"),
+                                            self._dev(C, 64, "C") if want_C else None,
+                                            ctypes.c_void_p(norm.data_ptr())))
+        return C, norm
+
+    def set_timing(self, enable=True):
+        self._check(self.lib.gh_set_timing(self.h, 1 if enable else 0))
+
+    def kernel_stats(self, kind):
+        """(launches, total_ms) of one kernel kind since timing was enabled or last queried."""
+        n = ctypes.c_longlong()
+        ms = ctypes.c_double()
+        self._check(self.lib.gh_kernel_stats(self.h, KERNEL_KINDS[kind], ctypes.byref(n), ctypes.byref(ms)))
+        return int(n.value), float(ms.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.gh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
