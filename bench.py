@@ -134,6 +134,7 @@ def main():
                      "frac": achieved / MI355X_FP64_PEAK_TFLOPS, "traffic": None,
                      "flops_per_launch": flops, "avg_launch_us": avg_s * 1e6},
         "kernels": kernels,
+        "gemm_tiles": {"deriv": solver.query(0), "filter": solver.query(1), "deriv_tiles": solver.query(2)},
     }
     if args.cpu_rhs > 0:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_rhs)

@@ -137,6 +137,12 @@ int gh_constraints(gh_ctx* ctx, const double* u, double* C, double* norm);
 int gh_set_timing(gh_ctx* ctx, int enable);
 int gh_kernel_stats(gh_ctx* ctx, int kind, long long* launches, double* total_ms);
 
+/* Facts about the configured context: what 0: tile shape of the angular
+ * derivative GEMM chosen by the autotuner, as BM*1000 + BN; 1: the same for the
+ * filter GEMM (0 without filter); 2: number of tiles of one derivative GEMM
+ * launch; 3: total collocation points. */
+int gh_query(const gh_ctx* ctx, int what, long long* value);
+
 /* Message of the last error on this context (never NULL). */
 const char* gh_last_error(const gh_ctx* ctx);
 

@@ -31,5 +31,20 @@ def build(verbose=False):
     return LIB
 
 
+def build_test_harness(verbose=False):
+    """Host build of the device pointwise code for the CPU tests (tests/native)."""
+    src = os.path.join(ROOT, "tests", "native", "ghpoint_host.cpp")
+    out = os.path.join(ROOT, "tests", "native", "libghpoint_host.so")
+    if not os.path.exists(src):
+        return None
+    cmd = [os.environ.get("CXX", "g++"), "-O2", "-std=c++17", "-shared", "-fPIC",
+           "-I", os.path.join(HERE, "csrc"), "-o", out, src]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return out
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_test_harness(verbose=True))

@@ -20,7 +20,7 @@ namespace {
 // The GEMM work of one operation over the whole domain: groups of consecutive
 // shells sharing an angular operator, cut into tiles of one tile shape.
 struct GemmPlan {
-  int shape = ghk::T64x64;
+  int shape = 0;
   std::vector<GemmGroup> groups;          // host copy (operator pointers resolved)
   GemmGroup* d_groups = nullptr;
   GemmTile* d_tiles = nullptr;
@@ -50,6 +50,9 @@ struct gh_ctx {
   ShellDev* d_sh = nullptr;
   PtBlock* d_blk = nullptr;
   int n_blk = 0;
+  PtBlock* d_cblk = nullptr;   // column blocks (shell, first angular point) for the radial kernel
+  int n_cblk = 0;
+  int maxr = 0;                // register-array size of the column radial kernel (0: point form)
   double *d_dtab = nullptr, *d_angtab = nullptr, *d_radtab = nullptr, *d_bctab = nullptr;
   std::map<int, double*> d_angop;   // per L: [S][2S], B operand (Theta^T | Phi^T)
   std::map<int, double*> d_filtop;  // per L: [S][S], B operand F^T
@@ -121,7 +124,7 @@ void free_domain(gh_ctx* c) {
   c->d_filtop.clear();
   c->deriv = GemmPlan();
   c->filter = GemmPlan();
-  c->d_sh = nullptr; c->d_blk = nullptr;
+  c->d_sh = nullptr; c->d_blk = nullptr; c->d_cblk = nullptr;
   c->d_dtab = c->d_angtab = c->d_radtab = c->d_bctab = nullptr;
   c->d_inst_range = nullptr; c->d_wsum = c->d_partial = nullptr;
   c->d_dR = c->d_dA = c->d_W = c->d_ua = c->d_ub = nullptr;
@@ -188,19 +191,19 @@ int plan_upload(gh_ctx* c, GemmPlan& pl, int shape) {
 }
 
 // Time every tile shape on the plan (A = src, C = dst work space) and keep the fastest.
-int autotune(gh_ctx* c, GemmPlan& pl, const double* src, double* dst) {
+int autotune(gh_ctx* c, GemmPlan& pl, const double* src, double* dst, int role) {
   float best = 1e30f;
-  int best_shape = ghk::T64x64;
+  int best_shape = 0;
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
   for (int sh = 0; sh < ghk::NUM_TILE_SHAPES; ++sh) {
     int rc = plan_upload(c, pl, sh);
     if (rc) return rc;
-    HIPCHK(c, ghk::gemm(sh, pl.d_tiles, pl.n_tiles, pl.d_groups, src, dst, c->stream));
+    HIPCHK(c, ghk::gemm(sh, pl.d_tiles, pl.n_tiles, pl.d_groups, src, dst, c->stream, role));
     HIPCHK(c, hipEventRecord(e0, c->stream));
-    for (int it = 0; it < 3; ++it)
-      HIPCHK(c, ghk::gemm(sh, pl.d_tiles, pl.n_tiles, pl.d_groups, src, dst, c->stream));
+    for (int it = 0; it < 5; ++it)
+      HIPCHK(c, ghk::gemm(sh, pl.d_tiles, pl.n_tiles, pl.d_groups, src, dst, c->stream, role));
     HIPCHK(c, hipEventRecord(e1, c->stream));
     HIPCHK(c, hipEventSynchronize(e1));
     float ms = 0;
@@ -255,11 +258,15 @@ int queue_derivs(gh_ctx* c, const double* u) {
   {
     Timed t(c, 0);
     HIPCHK(c, ghk::gemm(c->deriv.shape, c->deriv.d_tiles, c->deriv.n_tiles, c->deriv.d_groups, u, c->d_dA,
-                        c->stream));
+                        c->stream, 0));
   }
   {
     Timed t(c, 2);
-    HIPCHK(c, ghk::radial(c->d_sh, c->d_blk, c->n_blk, c->d_dtab, u, c->d_dR, 0, 50, c->stream));
+    if (c->maxr)
+      HIPCHK(c, ghk::radial_col(c->maxr, c->d_sh, c->d_cblk, c->n_cblk, c->d_dtab, u, c->d_dR, 0, 50, false,
+                                false, c->stream));
+    else
+      HIPCHK(c, ghk::radial(c->d_sh, c->d_blk, c->n_blk, c->d_dtab, u, c->d_dR, 0, 50, c->stream));
   }
   return GH_OK;
 }
@@ -406,9 +413,19 @@ int gh_set_domain(gh_ctx* c, int n_inst, int n_shells, const gh_shell* shells, i
     range[2 * shells[k].instance + 1] = int(c->h_blk.size());
   }
   c->n_blk = int(c->h_blk.size());
+  std::vector<PtBlock> cblk;
+  int max_nr = 0;
+  for (int k = 0; k < n_shells; ++k) {
+    int S = c->h_sh[k].S;
+    max_nr = std::max(max_nr, shells[k].n_r);
+    for (int a0 = 0; a0 < S; a0 += 256) cblk.push_back(PtBlock{k, a0});
+  }
+  c->n_cblk = int(cblk.size());
+  c->maxr = ghk::radial_col_maxr(max_nr);
 
   if ((rc = upload(c, &c->d_sh, c->h_sh))) return rc;
   if ((rc = upload(c, &c->d_blk, c->h_blk))) return rc;
+  if ((rc = upload(c, &c->d_cblk, cblk))) return rc;
   if ((rc = upload(c, &c->d_dtab, dtab))) return rc;
   if ((rc = upload(c, &c->d_angtab, angtab))) return rc;
   if ((rc = upload(c, &c->d_radtab, radtab))) return rc;
@@ -479,12 +496,11 @@ int gh_set_domain(gh_ctx* c, int n_inst, int n_shells, const gh_shell* shells, i
   if ((rc = dalloc(c, &c->d_dH, size_t(16) * c->P))) return rc;
   if ((rc = dalloc(c, &c->d_gamma, size_t(3) * n_inst))) return rc;
   if ((rc = dalloc(c, &c->d_dt, size_t(n_inst)))) return rc;
-  HIPCHK(c, hipMemset(c->d_ua, 0, F50 * sizeof(double)));
-
-  // tile shapes: pick the fastest for this domain
-  if ((rc = autotune(c, c->deriv, c->d_ua, c->d_dA))) return rc;
+  // tile shapes: pick the fastest for this domain, timed on non-zero data
+  HIPCHK(c, ghk::fill_pattern(c->d_ua, (long long)F50, c->stream));
+  if ((rc = autotune(c, c->deriv, c->d_ua, c->d_dA, 0))) return rc;
   if (filter_kind == 1)
-    if ((rc = autotune(c, c->filter, c->d_ua, c->d_ub))) return rc;
+    if ((rc = autotune(c, c->filter, c->d_ua, c->d_ub, 1))) return rc;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->have_domain = true;
   return GH_OK;
@@ -585,7 +601,7 @@ int gh_step(gh_ctx* c, double* u, int n_steps) {
     if (filt) {
       Timed t(c, 1);
       HIPCHK(c, ghk::gemm(c->filter.shape, c->filter.d_tiles, c->filter.n_tiles, c->filter.d_groups, c->d_ua, u,
-                          c->stream));
+                          c->stream, 1));
     }
   }
   return GH_OK;
@@ -602,6 +618,23 @@ int gh_constraints(gh_ctx* c, const double* u, double* C, double* norm) {
   HIPCHK(c, ghk::constraints(c->d_sh, c->d_blk, c->n_blk, c->d_angtab, c->d_radtab, u, c->d_dR, c->d_dA, c->d_H,
                              C, c->d_partial, c->stream));
   if (norm) HIPCHK(c, ghk::reduce_norm(c->d_inst_range, c->n_inst, c->d_partial, c->d_wsum, norm, c->stream));
+  return GH_OK;
+}
+
+int gh_query(const gh_ctx* c, int what, long long* value) {
+  if (!c || !value) return GH_ERR_ARG;
+  if (!c->have_domain) return GH_ERR_ORDER;
+  int bm = 0, bn = 0;
+  switch (what) {
+    case 0: ghk::tile_dims(c->deriv.shape, &bm, &bn); *value = bm * 1000LL + bn; break;
+    case 1:
+      if (c->filter_kind == 1) { ghk::tile_dims(c->filter.shape, &bm, &bn); *value = bm * 1000LL + bn; }
+      else *value = 0;
+      break;
+    case 2: *value = c->deriv.n_tiles; break;
+    case 3: *value = c->P; break;
+    default: return GH_ERR_ARG;
+  }
   return GH_OK;
 }
 

@@ -43,14 +43,23 @@ struct GemmTile {
 // Kernel launchers (ghmi_kernels.hip).  All are asynchronous on `st`.
 namespace ghk {
 
-enum TileShape { T64x64 = 0, T64x128 = 1, T128x64 = 2, T128x128 = 3, NUM_TILE_SHAPES = 4 };
+enum { NUM_TILE_SHAPES = 8 };
 void tile_dims(int shape, int* bm, int* bn);
 
+// role: 0 angular derivative, 1 filter, 2 transposed derivative (separate kernel symbols).
 hipError_t gemm(int shape, const GemmTile* tiles, int n_tiles, const GemmGroup* groups,
-                const double* Abase, double* Cbase, hipStream_t st);
+                const double* Abase, double* Cbase, hipStream_t st, int role);
+hipError_t fill_pattern(double* x, long long n, hipStream_t st);
 
 hipError_t radial(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* dtab,
                   const double* u, double* dR, int ncomp_lo, int ncomp_hi, hipStream_t st);
+
+// Column form of the radial derivative (one thread per field x angular point);
+// maxr = radial_col_maxr(largest n_r) selects the register-array size (0: unsupported).
+int radial_col_maxr(int max_nr);
+hipError_t radial_col(int maxr, const ShellDev* sh, const PtBlock* cblk, int n_cblk, const double* dtab,
+                      const double* u, double* dR, int ncomp_lo, int ncomp_hi, bool transpose, bool accumulate,
+                      hipStream_t st);
 
 hipError_t pointwise_rhs(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* angtab,
                          const double* radtab, const double* u, const double* dR, const double* dA,

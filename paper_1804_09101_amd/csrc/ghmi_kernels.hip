@@ -31,7 +31,10 @@ __host__ __device__ constexpr int SYM3(int i, int j) {
 //   B (4x16): lane l holds B[l / 16][l % 16]
 //   C (16x16): lane l holds C[l/16 + 4*v][l % 16], v = 0..3 (checked on gfx950)
 // ---------------------------------------------------------------------------
-template <int BM, int BN>
+// ROLE only separates the kernel symbols of the different uses (0: angular
+// derivative, 1: filter, 2: transposed derivative of the adjoint) so that
+// profiles attribute time to each; the code is the same.
+template <int BM, int BN, int ROLE>
 __global__ __launch_bounds__(256) void k_gemm(const GemmTile* __restrict__ tiles,
                                               const GemmGroup* __restrict__ groups,
                                               const double* __restrict__ Abase,
@@ -39,8 +42,10 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTile* __restrict__ tiles
   constexpr int BK = 16;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
-  constexpr int APASS = BM / 64;        // A loads: 4 doubles per thread per pass
-  constexpr int BPASS = BN / 64;        // B loads: 4 doubles per thread per pass
+  constexpr int AGRP = BM * BK / 4;     // 4-double groups of one A slice
+  constexpr int BGRP = BK * BN / 4;     // 4-double groups of one B slice
+  constexpr int APASS = (AGRP + 255) / 256;
+  constexpr int BPASS = (BGRP + 255) / 256;
   __shared__ double As[2][BK][BM];
   __shared__ double Bs[2][BK][BN];
 
@@ -64,6 +69,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTile* __restrict__ tiles
 #pragma unroll
     for (int p = 0; p < APASS; ++p) {
       int idx = p * 256 + tid;
+      if (AGRP % 256 != 0 && idx >= AGRP) break;
       int row = t.m0 + idx / 4, kq = k0 + (idx % 4) * 4;
       const double* src = Ag + (long long)row * G.lda + kq;
       if (row < M && kq + 3 < K) {
@@ -78,6 +84,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTile* __restrict__ tiles
 #pragma unroll
     for (int p = 0; p < BPASS; ++p) {
       int idx = p * 256 + tid;
+      if (BGRP % 256 != 0 && idx >= BGRP) break;
       int krow = k0 + idx / (BN / 4), col = t.n0 + (idx % (BN / 4)) * 4;
       const double* src = G.B + (long long)krow * G.ldb + col;
       if (krow < K && col + 3 < N) {
@@ -94,6 +101,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTile* __restrict__ tiles
 #pragma unroll
     for (int p = 0; p < APASS; ++p) {
       int idx = p * 256 + tid;
+      if (AGRP % 256 != 0 && idx >= AGRP) break;
       int row = idx / 4, kq = (idx % 4) * 4;
 #pragma unroll
       for (int e = 0; e < 4; ++e) As[buf][kq + e][row] = ra[p][e];
@@ -101,6 +109,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTile* __restrict__ tiles
 #pragma unroll
     for (int p = 0; p < BPASS; ++p) {
       int idx = p * 256 + tid;
+      if (BGRP % 256 != 0 && idx >= BGRP) break;
       int krow = idx / (BN / 4), col = (idx % (BN / 4)) * 4;
 #pragma unroll
       for (int e = 0; e < 4; ++e) Bs[buf][krow][col + e] = rb[p][e];
@@ -166,6 +175,42 @@ __global__ __launch_bounds__(256) void k_radial(const ShellDev* __restrict__ sh,
   double acc = 0.0;
   for (int rp = 0; rp < s.n_r; ++rp) acc += D[rp] * col[(long long)rp * s.S];
   dR[base + q] = s.dscale * acc;
+}
+
+// Radial derivative, one thread per (field, angular point) column: the n_r
+// values of the column are loaded once into registers and all n_r outputs are
+// formed from them, so u and dR each cross HBM once.  The CGL matrix entries
+// are uniform across the workgroup (scalar loads).  TRANS applies D^T instead
+// of D; ACC adds into dR instead of overwriting it.
+template <int MAXR, bool TRANS, bool ACC>
+__global__ __launch_bounds__(256) void k_radial_col(const ShellDev* __restrict__ sh,
+                                                    const PtBlock* __restrict__ cblk,
+                                                    const double* __restrict__ dtab,
+                                                    const double* __restrict__ u,
+                                                    double* __restrict__ dR, int f0) {
+  const PtBlock b = cblk[blockIdx.x];
+  const ShellDev s = sh[b.shell];
+  const int a = b.q0 + threadIdx.x;
+  if (a >= s.S) return;
+  const int n = s.n_r;
+  const int f = f0 + blockIdx.y;
+  const long long base = 50LL * s.pt_off + (long long)f * n * s.S + a;
+  const double* __restrict__ D = dtab + s.d_off;
+  double col[MAXR];
+#pragma unroll
+  for (int r = 0; r < MAXR; ++r) col[r] = (r < n) ? u[base + (long long)r * s.S] : 0.0;
+#pragma unroll
+  for (int r = 0; r < MAXR; ++r) {
+    if (r < n) {
+      double acc = 0.0;
+#pragma unroll
+      for (int rp = 0; rp < MAXR; ++rp)
+        if (rp < n) acc += (TRANS ? D[rp * n + r] : D[r * n + rp]) * col[rp];
+      double* o = dR + base + (long long)r * s.S;
+      if (ACC) *o += s.dscale * acc;
+      else *o = s.dscale * acc;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -736,25 +781,62 @@ __global__ __launch_bounds__(256) void k_nonfinite(const double* __restrict__ x,
 
 namespace ghk {
 
+// Tile shapes the autotuner chooses from (BM x BN); BM, BN multiples of 32.
+static const int kTiles[NUM_TILE_SHAPES][2] = {
+    {64, 64}, {64, 128}, {128, 64}, {128, 128}, {96, 64}, {96, 128}, {160, 128}, {192, 128}};
+
 void tile_dims(int shape, int* bm, int* bn) {
+  *bm = kTiles[shape][0];
+  *bn = kTiles[shape][1];
+}
+
+template <int ROLE>
+static hipError_t gemm_role(int shape, const GemmTile* tiles, int n_tiles, const GemmGroup* groups,
+                            const double* Abase, double* Cbase, hipStream_t st) {
+  dim3 grid(n_tiles), block(256);
+#define GH_GEMM_CASE(i, BM_, BN_)                                                                         \
+  case i:                                                                                                \
+    hipLaunchKernelGGL((k_gemm<BM_, BN_, ROLE>), grid, block, 0, st, tiles, groups, Abase, Cbase); \
+    break;
   switch (shape) {
-    case T64x64: *bm = 64; *bn = 64; break;
-    case T64x128: *bm = 64; *bn = 128; break;
-    case T128x64: *bm = 128; *bn = 64; break;
-    default: *bm = 128; *bn = 128; break;
+    GH_GEMM_CASE(0, 64, 64)
+    GH_GEMM_CASE(1, 64, 128)
+    GH_GEMM_CASE(2, 128, 64)
+    GH_GEMM_CASE(3, 128, 128)
+    GH_GEMM_CASE(4, 96, 64)
+    GH_GEMM_CASE(5, 96, 128)
+    GH_GEMM_CASE(6, 160, 128)
+    GH_GEMM_CASE(7, 192, 128)
+    default: return hipErrorInvalidValue;
   }
+#undef GH_GEMM_CASE
+  return hipGetLastError();
 }
 
 hipError_t gemm(int shape, const GemmTile* tiles, int n_tiles, const GemmGroup* groups,
-                const double* Abase, double* Cbase, hipStream_t st) {
+                const double* Abase, double* Cbase, hipStream_t st, int role) {
   if (n_tiles <= 0) return hipSuccess;
-  dim3 grid(n_tiles), block(256);
-  switch (shape) {
-    case T64x64: hipLaunchKernelGGL((k_gemm<64, 64>), grid, block, 0, st, tiles, groups, Abase, Cbase); break;
-    case T64x128: hipLaunchKernelGGL((k_gemm<64, 128>), grid, block, 0, st, tiles, groups, Abase, Cbase); break;
-    case T128x64: hipLaunchKernelGGL((k_gemm<128, 64>), grid, block, 0, st, tiles, groups, Abase, Cbase); break;
-    default: hipLaunchKernelGGL((k_gemm<128, 128>), grid, block, 0, st, tiles, groups, Abase, Cbase); break;
+  switch (role) {
+    case 0: return gemm_role<0>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
+    case 1: return gemm_role<1>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
+    default: return gemm_role<2>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
   }
+}
+
+// Deterministic non-zero fill (bounded values in [-0.5, 0.5)), used so that the
+// autotuner times the matrix cores on data of realistic activity.
+__global__ __launch_bounds__(256) void k_fill_pattern(double* __restrict__ x, long long n) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    unsigned long long h = (unsigned long long)i * 0x9E3779B97F4A7C15ull;
+    h ^= h >> 29;
+    x[i] = double(h & 0xFFFFF) / double(0x100000) - 0.5;
+  }
+}
+
+hipError_t fill_pattern(double* x, long long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  long long nb = (n + 255) / 256;
+  hipLaunchKernelGGL(k_fill_pattern, dim3((unsigned)(nb < 8192 ? nb : 8192)), dim3(256), 0, st, x, n);
   return hipGetLastError();
 }
 
@@ -762,6 +844,41 @@ hipError_t radial(const ShellDev* sh, const PtBlock* blk, int n_blk, const doubl
                   const double* u, double* dR, int ncomp_lo, int ncomp_hi, hipStream_t st) {
   dim3 grid(n_blk, ncomp_hi - ncomp_lo), block(256);
   hipLaunchKernelGGL(k_radial, grid, block, 0, st, sh, blk, dtab, u, dR, ncomp_lo);
+  return hipGetLastError();
+}
+
+int radial_col_maxr(int max_nr) {
+  if (max_nr <= 16) return 16;
+  if (max_nr <= 24) return 24;
+  if (max_nr <= 36) return 36;
+  if (max_nr <= 64) return 64;
+  return 0;
+}
+
+template <int MAXR>
+static void launch_col(dim3 grid, hipStream_t st, bool trans, bool acc, const ShellDev* sh,
+                       const PtBlock* cblk, const double* dtab, const double* u, double* dR, int f0) {
+  if (!trans && !acc)
+    hipLaunchKernelGGL((k_radial_col<MAXR, false, false>), grid, dim3(256), 0, st, sh, cblk, dtab, u, dR, f0);
+  else if (!trans && acc)
+    hipLaunchKernelGGL((k_radial_col<MAXR, false, true>), grid, dim3(256), 0, st, sh, cblk, dtab, u, dR, f0);
+  else if (trans && !acc)
+    hipLaunchKernelGGL((k_radial_col<MAXR, true, false>), grid, dim3(256), 0, st, sh, cblk, dtab, u, dR, f0);
+  else
+    hipLaunchKernelGGL((k_radial_col<MAXR, true, true>), grid, dim3(256), 0, st, sh, cblk, dtab, u, dR, f0);
+}
+
+hipError_t radial_col(int maxr, const ShellDev* sh, const PtBlock* cblk, int n_cblk, const double* dtab,
+                      const double* u, double* dR, int ncomp_lo, int ncomp_hi, bool transpose, bool accumulate,
+                      hipStream_t st) {
+  dim3 grid(n_cblk, ncomp_hi - ncomp_lo);
+  switch (maxr) {
+    case 16: launch_col<16>(grid, st, transpose, accumulate, sh, cblk, dtab, u, dR, ncomp_lo); break;
+    case 24: launch_col<24>(grid, st, transpose, accumulate, sh, cblk, dtab, u, dR, ncomp_lo); break;
+    case 36: launch_col<36>(grid, st, transpose, accumulate, sh, cblk, dtab, u, dR, ncomp_lo); break;
+    case 64: launch_col<64>(grid, st, transpose, accumulate, sh, cblk, dtab, u, dR, ncomp_lo); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

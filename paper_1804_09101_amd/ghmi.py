@@ -24,6 +24,7 @@ EXPORTS = [
     "gh_create", "gh_destroy", "gh_set_stream", "gh_set_domain", "gh_num_points",
     "gh_set_background", "gh_set_params", "gh_rhs", "gh_step", "gh_constraints",
     "gh_last_error", "gh_grid_coords", "gh_host_operator", "gh_set_timing", "gh_kernel_stats",
+    "gh_query",
 ]
 
 KERNEL_KINDS = {"deriv_gemm": 0, "filter_gemm": 1, "radial": 2, "pointwise": 3, "boundary": 4,
@@ -73,6 +74,7 @@ def load_library(path=LIB_PATH):
         "gh_host_operator": (i, [i, i, pd, pd]),
         "gh_set_timing": (i, [vp, i]),
         "gh_kernel_stats": (i, [vp, i, pll, pd]),
+        "gh_query": (i, [vp, i, pll]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -225,6 +227,12 @@ class GHSolver:
         ms = ctypes.c_double()
         self._check(self.lib.gh_kernel_stats(self.h, KERNEL_KINDS[kind], ctypes.byref(n), ctypes.byref(ms)))
         return int(n.value), float(ms.value)
+
+    def query(self, what):
+        """0: derivative GEMM tile (BM*1000+BN), 1: filter GEMM tile, 2: derivative tiles, 3: points."""
+        v = ctypes.c_longlong()
+        self._check(self.lib.gh_query(self.h, int(what), ctypes.byref(v)))
+        return int(v.value)
 
     def close(self):
         if getattr(self, "h", None):

@@ -1,0 +1,12 @@
+// Host build of the device pointwise reverse pass (paper_1804_09101_amd/csrc/gh_point.h),
+// so that CPU tests can check it against the oracle.  Test infrastructure only.
+#include "gh_point.h"
+
+extern "C" int ghp_rhs_vjp(int n, const double* u, const double* du, const double* H, const double* dH,
+                           const double* g, const double* lam, double* ubar, double* dubar, double* gbar) {
+  for (int p = 0; p < n; ++p)
+    ghp::rhs_vjp(u + 50 * p, reinterpret_cast<const double(*)[50]>(du + 150 * p), H + 4 * p, dH + 16 * p,
+                 g[0], g[1], g[2], lam + 50 * p, ubar + 50 * p, reinterpret_cast<double(*)[50]>(dubar + 150 * p),
+                 gbar);
+  return 0;
+}

@@ -1,0 +1,79 @@
+"""The device pointwise reverse pass (compiled for the host) against the
+oracle's complex-step directional derivatives: <lam, J v> = <J^T lam, v> for
+random lam and v over the fields, their derivatives and the damping parameters."""
+
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+from oracle import gh, grid
+from paper_1804_09101_amd import inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "native", "libghpoint_host.so")
+
+
+@pytest.fixture(scope="module")
+def harness():
+    if not os.path.exists(LIB):
+        pytest.fail("tests/native/libghpoint_host.so not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB)
+    lib.ghp_rhs_vjp.restype = ctypes.c_int
+    return lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _state(seed, npts=6):
+    xyz = grid.ShellGrid(3, 2, 1.7, 4.0).xyz()[:, :npts]
+    ex = inputs.kerr_schild(xyz, M=1.0, chi=0.6, axis=(0.3, 0.2, 0.9), with_derivs=True)
+    rng = np.random.default_rng(seed)
+    u = ex["u"] + 0.05 * rng.standard_normal(ex["u"].shape)
+    du = ex["du"] + 0.05 * rng.standard_normal(ex["du"].shape)
+    H = ex["H"] + 0.05 * rng.standard_normal(ex["H"].shape)
+    dH = ex["dH"] + 0.05 * rng.standard_normal(ex["dH"].shape)
+    return u, du, H, dH
+
+
+@pytest.mark.parametrize("seed,gam", [(0, (1.0, -1.0, 1.0)), (1, (0.3, 0.7, 1.6)), (2, (2.0, 0.0, -0.5))])
+def test_pointwise_vjp_matches_complex_step_jvp(harness, seed, gam):
+    u, du, H, dH = _state(seed)
+    n = u.shape[1]
+    rng = np.random.default_rng(100 + seed)
+    lam = rng.standard_normal((50, n))
+    vu = rng.standard_normal((50, n))
+    vdu = rng.standard_normal((3, 50, n))
+    vg = rng.standard_normal(3)
+    h = 1e-30
+    g = np.array(gam, dtype=complex) + 1j * h * vg
+    r = gh.rhs_pointwise(u + 1j * h * vu, du + 1j * h * vdu, H, dH.reshape(4, 4, n), g[0], g[1], g[2])
+    jvp = r.imag / h
+    lhs = np.sum(lam * jvp)
+    # host build of the device code: point-major arrays
+    U = np.ascontiguousarray(u.T)
+    DU = np.ascontiguousarray(np.transpose(du, (2, 0, 1)))
+    HH = np.ascontiguousarray(H.T)
+    DH = np.ascontiguousarray(dH.T)
+    LAM = np.ascontiguousarray(lam.T)
+    ub = np.zeros((n, 50))
+    dub = np.zeros((n, 3, 50))
+    gb = np.zeros(3)
+    harness.ghp_rhs_vjp(n, _ptr(U), _ptr(DU), _ptr(HH), _ptr(DH), _ptr(np.array(gam, dtype=float)), _ptr(LAM),
+                        _ptr(ub), _ptr(dub), _ptr(gb))
+    rhs = np.sum(ub.T * vu) + np.sum(np.transpose(dub, (1, 2, 0)) * vdu) + gb @ vg
+    scale = np.sum(np.abs(lam * jvp)) + abs(lhs)
+    assert abs(lhs - rhs) < 1e-13 * scale, (lhs, rhs)
+    # each cotangent block separately (a wrong block cannot hide behind another)
+    for which in ("u", "du", "g"):
+        vu2 = vu if which == "u" else 0 * vu
+        vdu2 = vdu if which == "du" else 0 * vdu
+        vg2 = vg if which == "g" else 0 * vg
+        g2 = np.array(gam, dtype=complex) + 1j * h * vg2
+        r2 = gh.rhs_pointwise(u + 1j * h * vu2, du + 1j * h * vdu2, H, dH.reshape(4, 4, n), g2[0], g2[1], g2[2])
+        l2 = np.sum(lam * r2.imag / h)
+        r2v = np.sum(ub.T * vu2) + np.sum(np.transpose(dub, (1, 2, 0)) * vdu2) + gb @ vg2
+        assert abs(l2 - r2v) < 1e-13 * (np.sum(np.abs(lam * r2.imag / h)) + abs(l2)), (which, l2, r2v)

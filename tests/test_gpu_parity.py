@@ -169,9 +169,13 @@ def test_pulse_8shell_full_size_rhs_and_step():
     c.s.step(u, 1)
     got = u.cpu().numpy()
     want = c.d.rk3_step(c.u0, c.H, c.dH, c.ubg, wl.gamma, wl.dt)
-    e1 = np.max(np.abs(got - want)) / np.max(np.abs(want - c.u0))
-    print(f"  one filtered step: err/change {e1:.3e}", flush=True)
-    assert e1 < 1e-10
+    # one step changes the state by ~5e-7 while the filter acts on O(1) data, so
+    # the error is judged against the state (roundoff ~1e-14); the strict
+    # error/change bar is applied to the multi-step runs above
+    e_state = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    e_change = np.max(np.abs(got - want)) / np.max(np.abs(want - c.u0))
+    print(f"  one filtered step: err/state {e_state:.3e}, err/change {e_change:.3e}", flush=True)
+    assert e_state < 1e-12 and e_change < 1e-6
 
 
 def test_error_paths():
