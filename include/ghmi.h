@@ -126,14 +126,39 @@ int gh_step(gh_ctx* ctx, double* u, int n_steps);
  * weight (Clenshaw-Curtis x r^2 (r_out-r_in)/2 x Gauss-Legendre x 2pi/N_phi). */
 int gh_constraints(gh_ctx* ctx, const double* u, double* C, double* norm);
 
+/* ---- adjoint (reverse mode) ---------------------------------------------
+ * The paper has no adjoint; these are the transposes of the linearised
+ * operations above, for gradients of a loss of the final state with respect
+ * to the initial state and the damping parameters.  The background (H, dH,
+ * frozen boundary projections) and dt are constants.  The first call of
+ * either function allocates ~9 further [50] work arrays and tunes the
+ * transposed GEMMs (synchronous); later calls are queued on the stream. */
+
+/* lam_u = (d rhs(u)/d u)^T lam, i.e. the transpose of the linearised gh_rhs
+ * (boundary treatment included) at state u.  g_gamma (device [n_inst][3], may
+ * be NULL) is INCREMENTED by (d rhs/d gamma)^T lam.  lam_u must not alias u or lam. */
+int gh_rhs_vjp(gh_ctx* ctx, const double* u, const double* lam, double* lam_u, double* g_gamma);
+
+/* Transpose of one gh_step (SSP-RK3 + filter) linearised at u_n:
+ * lam_n = (d u_{n+1}/d u_n)^T lam_np1, and g_gamma (device, may be NULL) is
+ * INCREMENTED by (d u_{n+1}/d gamma)^T lam_np1.  The stages are recomputed
+ * from u_n.  lam_n may alias lam_np1 but not u_n. */
+int gh_step_vjp(gh_ctx* ctx, const double* u_n, const double* lam_np1, double* lam_n, double* g_gamma);
+
+/* Transpose of the constraint norm: lam_u = sum_i lam_norm[i] d||C||_i / d u
+ * at state u (lam_norm: device [n_inst]; lam_u: device [50], overwritten,
+ * not aliasing u).  A zero norm contributes nothing. */
+int gh_constraints_vjp(gh_ctx* ctx, const double* u, const double* lam_norm, double* lam_u);
+
 /* Kernel timing.  While enabled, every launch of the kernels named below is
  * bracketed by HIP events on the context's stream (a small overhead).
  * gh_kernel_stats waits for the recorded work, returns the number of launches
  * and their summed duration in milliseconds since timing was enabled or last
  * queried, and clears that kind's record.
  * kind 0: angular derivative GEMM; 1: filter GEMM; 2: radial derivative;
- *      3: pointwise GH RHS; 4: boundary; 5: RK3 stage update. */
-#define GH_NUM_KERNEL_KINDS 6
+ *      3: pointwise GH RHS; 4: boundary; 5: RK3 stage update;
+ *      6: pointwise reverse pass; 7: transposed angular derivative GEMM. */
+#define GH_NUM_KERNEL_KINDS 8
 int gh_set_timing(gh_ctx* ctx, int enable);
 int gh_kernel_stats(gh_ctx* ctx, int kind, long long* launches, double* total_ms);
 

@@ -1,0 +1,83 @@
+"""torch.autograd wrappers of the evolution and of the constraint norm.
+
+GHEvolve runs n SSP-RK3 steps with the HIP library and, in backward, walks the
+steps in reverse with gh_step_vjp.  It keeps a copy of the state every
+`checkpoint_every` steps during the forward pass; backward re-runs each segment
+forward from its checkpoint (storing that segment's states) and then applies
+the step transposes in reverse order.  Memory: n/k checkpoints plus k segment
+states of 50 P doubles each.
+
+GHConstraintNorm returns the per-instance constraint norm of a state; its
+backward is gh_constraints_vjp.
+
+The damping parameters enter as a CPU float64 tensor [n_inst, 3]; they are
+pushed to the library with gh_set_params before the forward and backward
+passes, and their gradient is accumulated on the device by the library.
+Every computation runs in the library; this module only orders the calls.
+"""
+
+import numpy as np
+import torch
+
+
+def _push_params(solver, gamma, dt):
+    solver.set_params(gamma.detach().cpu().numpy().astype(np.float64), dt)
+
+
+class GHEvolve(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, u0, gamma, solver, dt, n_steps, checkpoint_every):
+        _push_params(solver, gamma, dt)
+        k = max(1, int(checkpoint_every))
+        u = u0.detach().clone().contiguous()
+        ckpts = []
+        for s in range(n_steps):
+            if s % k == 0:
+                ckpts.append(u.clone())
+            solver.step(u, 1)
+        ctx.solver, ctx.dt, ctx.n_steps, ctx.k = solver, dt, n_steps, k
+        ctx.gamma = gamma.detach().clone()
+        ctx.ckpts = ckpts
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        solver, n, k = ctx.solver, ctx.n_steps, ctx.k
+        _push_params(solver, ctx.gamma, ctx.dt)
+        lam = grad_u.detach().contiguous().clone()
+        g = torch.zeros(solver.n_inst * 3, dtype=torch.float64, device=lam.device)
+        for seg in reversed(range(len(ctx.ckpts))):
+            s0 = seg * k
+            s1 = min(n, s0 + k)
+            states = [ctx.ckpts[seg].clone()]
+            for _ in range(s0, s1 - 1):
+                nxt = states[-1].clone()
+                solver.step(nxt, 1)
+                states.append(nxt)
+            for j in reversed(range(s1 - s0)):
+                solver.step_vjp(states[j], lam, g_gamma=g, out=lam)
+            del states
+        return lam, g.view(solver.n_inst, 3).cpu(), None, None, None, None
+
+
+class GHConstraintNorm(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, u, solver):
+        _, norm = solver.constraints(u.detach().contiguous(), want_C=False)
+        ctx.solver = solver
+        ctx.save_for_backward(u)
+        return norm
+
+    @staticmethod
+    def backward(ctx, grad_norm):
+        (u,) = ctx.saved_tensors
+        lam = ctx.solver.constraints_vjp(u.detach().contiguous(), grad_norm.detach().contiguous())
+        return lam, None
+
+
+def evolve(u0, gamma, solver, dt, n_steps, checkpoint_every=20):
+    return GHEvolve.apply(u0, gamma, solver, dt, n_steps, checkpoint_every)
+
+
+def constraint_norm(u, solver):
+    return GHConstraintNorm.apply(u, solver)

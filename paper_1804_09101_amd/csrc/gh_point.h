@@ -113,6 +113,86 @@ GHP_HD void mmm(const double (*X)[4], const double (*Y)[4], const double (*W)[4]
   mm(T, W, Z);
 }
 
+// Shared end of the reverse pass: from the cotangents of C_a, Gamma_cab, psi^ab,
+// t^a, N, N^i and g^ij back to psi, Pi, Phi (full tensors, accumulated).
+GHP_HD void reverse_tail(const Fwd& F, const double* C_b, double (*G_b)[4][4], double (*P_b)[4],
+                         double* tu_b, double& N_b, double* Nu_b, double (*gi_b)[3], double (*psi_b)[4],
+                         double (*Pi_b)[4], double (*Phi_b)[4][4]) {
+  const double N = F.N;
+  // C_a = H_a + P^bc G_abc
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b)
+      for (int c = 0; c < 4; ++c) {
+        P_b[b][c] += C_b[a] * F.G[a][b][c];
+        G_b[a][b][c] += C_b[a] * F.P[b][c];
+      }
+  // Gamma_cab = (d4_acb + d4_bca - d4_cab)/2
+  double d4_b[4][4][4] = {};
+  for (int c = 0; c < 4; ++c)
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) {
+        const double g = 0.5 * G_b[c][a][b];
+        d4_b[a][c][b] += g;
+        d4_b[b][c][a] += g;
+        d4_b[c][a][b] -= g;
+      }
+  // d4_0 = -N Pi + N^i Phi_i ; d4_(i+1) = Phi_i
+  for (int b = 0; b < 4; ++b)
+    for (int c = 0; c < 4; ++c) {
+      const double g = d4_b[0][b][c];
+      N_b += -g * F.Pi[b][c];
+      Pi_b[b][c] += -N * g;
+      for (int i = 0; i < 3; ++i) {
+        Nu_b[i] += g * F.Phi[i][b][c];
+        Phi_b[i][b][c] += F.Nu[i] * g + d4_b[i + 1][b][c];
+      }
+    }
+  // P^ab = g^ab - t^a t^b
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      if (a > 0 && b > 0) gi_b[a - 1][b - 1] += P_b[a][b];
+      tu_b[a] += -P_b[a][b] * F.tu[b];
+      tu_b[b] += -P_b[a][b] * F.tu[a];
+    }
+  // t^a = (1/N, -N^i/N)
+  N_b += -tu_b[0] / (N * N);
+  for (int i = 0; i < 3; ++i) {
+    N_b += tu_b[i + 1] * F.Nu[i] / (N * N);
+    Nu_b[i] += -tu_b[i + 1] / N;
+  }
+  // N = sqrt(N^i beta_i - psi_00)
+  const double nsq_b = N_b / (2.0 * N);
+  double beta_b[3];
+  for (int i = 0; i < 3; ++i) {
+    Nu_b[i] += nsq_b * F.beta[i];
+    beta_b[i] = nsq_b * F.Nu[i];
+  }
+  psi_b[0][0] += -nsq_b;
+  // N^i = g^ij beta_j
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      gi_b[i][j] += Nu_b[i] * F.beta[j];
+      beta_b[j] += F.gi[i][j] * Nu_b[i];
+    }
+  for (int i = 0; i < 3; ++i) psi_b[0][i + 1] += beta_b[i];
+  // g^ij = inv(g_ij): gbar_ij = -(g^-1 gi_b g^-1)_ij
+  {
+    double T[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < 3; ++k) s += gi_b[i][k] * F.gi[k][j];
+        T[i][j] = s;
+      }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < 3; ++k) s += F.gi[i][k] * T[k][j];
+        psi_b[i + 1][j + 1] += -s;
+      }
+  }
+}
+
 // Reverse pass.  lam: cotangent of d_t u (50, pair form).  Writes ubar[50],
 // dubar[3][50] (cotangents of u and of its Cartesian derivatives) and adds to
 // gbar[3] (cotangents of gamma0, gamma1, gamma2).
@@ -385,78 +465,7 @@ GHP_HD void rhs_vjp(const double* u, const double (*du)[50], const double* H, co
         for (int e = 0; e < 4; ++e) P_b[c][e] += 2.0 * GPY[c][e];
     }
   }
-  // C_a = H_a + P^bc G_abc
-  for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b)
-      for (int c = 0; c < 4; ++c) {
-        P_b[b][c] += C_b[a] * F.G[a][b][c];
-        G_b[a][b][c] += C_b[a] * F.P[b][c];
-      }
-  // Gamma_cab = (d4_acb + d4_bca - d4_cab)/2
-  double d4_b[4][4][4] = {};
-  for (int c = 0; c < 4; ++c)
-    for (int a = 0; a < 4; ++a)
-      for (int b = 0; b < 4; ++b) {
-        const double g = 0.5 * G_b[c][a][b];
-        d4_b[a][c][b] += g;
-        d4_b[b][c][a] += g;
-        d4_b[c][a][b] -= g;
-      }
-  // d4_0 = -N Pi + N^i Phi_i ; d4_(i+1) = Phi_i
-  for (int b = 0; b < 4; ++b)
-    for (int c = 0; c < 4; ++c) {
-      const double g = d4_b[0][b][c];
-      N_b += -g * F.Pi[b][c];
-      Pi_b[b][c] += -N * g;
-      for (int i = 0; i < 3; ++i) {
-        Nu_b[i] += g * F.Phi[i][b][c];
-        Phi_b[i][b][c] += F.Nu[i] * g + d4_b[i + 1][b][c];
-      }
-    }
-  // P^ab = g^ab - t^a t^b
-  for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b) {
-      if (a > 0 && b > 0) gi_b[a - 1][b - 1] += P_b[a][b];
-      tu_b[a] += -P_b[a][b] * F.tu[b];
-      tu_b[b] += -P_b[a][b] * F.tu[a];
-    }
-  // t^a = (1/N, -N^i/N)
-  N_b += -tu_b[0] / (N * N);
-  for (int i = 0; i < 3; ++i) {
-    N_b += tu_b[i + 1] * F.Nu[i] / (N * N);
-    Nu_b[i] += -tu_b[i + 1] / N;
-  }
-  // N = sqrt(N^i beta_i - psi_00)
-  const double nsq_b = N_b / (2.0 * N);
-  double beta_b[3];
-  for (int i = 0; i < 3; ++i) {
-    Nu_b[i] += nsq_b * F.beta[i];
-    beta_b[i] = nsq_b * F.Nu[i];
-  }
-  psi_b[0][0] += -nsq_b;
-  // N^i = g^ij beta_j
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) {
-      gi_b[i][j] += Nu_b[i] * F.beta[j];
-      beta_b[j] += F.gi[i][j] * Nu_b[i];
-    }
-  for (int i = 0; i < 3; ++i) psi_b[0][i + 1] += beta_b[i];
-  // g^ij = inv(g_ij): gbar_ij = -(g^-1 gi_b g^-1)_ij
-  {
-    double T[3][3];
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) {
-        double s = 0.0;
-        for (int k = 0; k < 3; ++k) s += gi_b[i][k] * F.gi[k][j];
-        T[i][j] = s;
-      }
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) {
-        double s = 0.0;
-        for (int k = 0; k < 3; ++k) s += F.gi[i][k] * T[k][j];
-        psi_b[i + 1][j + 1] += -s;
-      }
-  }
+  reverse_tail(F, C_b, G_b, P_b, tu_b, N_b, Nu_b, gi_b, psi_b, Pi_b, Phi_b);
   // fold full-tensor adjoints onto pairs
   for (int a = 0; a < 4; ++a)
     for (int b = a; b < 4; ++b) {
@@ -475,6 +484,25 @@ GHP_HD void rhs_vjp(const double* u, const double (*du)[50], const double* H, co
   gbar[0] += gb0;
   gbar[1] += gb1;
   gbar[2] += gb2;
+}
+
+// Reverse of the gauge constraint C_a = H_a + psi^bc Gamma_abc: adds the
+// cotangent of u (pair form) for the cotangent Cbar[4] of C_a.
+GHP_HD void gauge_constraint_vjp(const double* u, const double* H, const double* Cbar, double* ubar) {
+  Fwd F;
+  forward(u, H, F);
+  double psi_b[4][4] = {}, Pi_b[4][4] = {}, Phi_b[3][4][4] = {};
+  double Nu_b[3] = {}, N_b = 0.0, gi_b[3][3] = {}, tu_b[4] = {}, P_b[4][4] = {};
+  double G_b[4][4][4] = {};
+  reverse_tail(F, Cbar, G_b, P_b, tu_b, N_b, Nu_b, gi_b, psi_b, Pi_b, Phi_b);
+  for (int a = 0; a < 4; ++a)
+    for (int b = a; b < 4; ++b) {
+      const int n = pair(a, b);
+      const bool off = a != b;
+      ubar[n] += psi_b[a][b] + (off ? psi_b[b][a] : 0.0);
+      ubar[10 + n] += Pi_b[a][b] + (off ? Pi_b[b][a] : 0.0);
+      for (int i = 0; i < 3; ++i) ubar[20 + 10 * i + n] += Phi_b[i][a][b] + (off ? Phi_b[i][b][a] : 0.0);
+    }
 }
 
 }  // namespace ghp

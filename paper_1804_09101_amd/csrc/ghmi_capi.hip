@@ -56,7 +56,17 @@ struct gh_ctx {
   double *d_dtab = nullptr, *d_angtab = nullptr, *d_radtab = nullptr, *d_bctab = nullptr;
   std::map<int, double*> d_angop;   // per L: [S][2S], B operand (Theta^T | Phi^T)
   std::map<int, double*> d_filtop;  // per L: [S][S], B operand F^T
-  GemmPlan deriv, filter;
+  std::map<int, double*> d_angopT;  // per L: [2S][S], B operand (Theta ; Phi) of the transposed derivative
+  std::map<int, double*> d_filtopT; // per L: [S][S], B operand F of the transposed filter
+  GemmPlan deriv, filter, derivT, filterT;
+  int* d_shell_range = nullptr;     // per instance: first and one-past-last shell
+
+  // adjoint work space (allocated on first use)
+  bool have_adj = false;
+  double *d_Lb = nullptr, *d_dRb = nullptr, *d_dAb = nullptr, *d_T = nullptr;
+  double *d_u1 = nullptr, *d_u2 = nullptr, *d_lam3 = nullptr, *d_mu1 = nullptr, *d_mu2 = nullptr;
+  double *d_gpart = nullptr, *d_bcg = nullptr;
+  double *d_C = nullptr, *d_norm = nullptr;   // constraint values and norms for gh_constraints_vjp
 
   // reductions
   int* d_inst_range = nullptr;
@@ -122,8 +132,18 @@ void free_domain(gh_ctx* c) {
   c->allocs.clear();
   c->d_angop.clear();
   c->d_filtop.clear();
+  c->d_angopT.clear();
+  c->d_filtopT.clear();
   c->deriv = GemmPlan();
   c->filter = GemmPlan();
+  c->derivT = GemmPlan();
+  c->filterT = GemmPlan();
+  c->d_shell_range = nullptr;
+  c->have_adj = false;
+  c->d_Lb = c->d_dRb = c->d_dAb = c->d_T = nullptr;
+  c->d_u1 = c->d_u2 = c->d_lam3 = c->d_mu1 = c->d_mu2 = nullptr;
+  c->d_gpart = c->d_bcg = nullptr;
+  c->d_C = c->d_norm = nullptr;
   c->d_sh = nullptr; c->d_blk = nullptr; c->d_cblk = nullptr;
   c->d_dtab = c->d_angtab = c->d_radtab = c->d_bctab = nullptr;
   c->d_inst_range = nullptr; c->d_wsum = c->d_partial = nullptr;
@@ -286,6 +306,68 @@ int queue_rhs(gh_ctx* c, const double* u, double* out) {
   return GH_OK;
 }
 
+// Allocate the adjoint work space and choose tile shapes of the transposed GEMMs.
+int ensure_adjoint(gh_ctx* c) {
+  if (c->have_adj) return GH_OK;
+  size_t F50 = size_t(50) * c->P;
+  int rc;
+  if ((rc = dalloc(c, &c->d_Lb, F50))) return rc;
+  if ((rc = dalloc(c, &c->d_dRb, F50))) return rc;
+  if ((rc = dalloc(c, &c->d_dAb, 2 * F50))) return rc;
+  if ((rc = dalloc(c, &c->d_T, F50))) return rc;
+  if ((rc = dalloc(c, &c->d_u1, F50))) return rc;
+  if ((rc = dalloc(c, &c->d_u2, F50))) return rc;
+  if ((rc = dalloc(c, &c->d_lam3, F50))) return rc;
+  if ((rc = dalloc(c, &c->d_mu1, F50))) return rc;
+  if ((rc = dalloc(c, &c->d_mu2, F50))) return rc;
+  if ((rc = dalloc(c, &c->d_gpart, size_t(3) * c->n_blk))) return rc;
+  if ((rc = dalloc(c, &c->d_bcg, size_t(c->n_shells) * c->max_S))) return rc;
+  if ((rc = dalloc(c, &c->d_C, size_t(64) * c->P))) return rc;
+  if ((rc = dalloc(c, &c->d_norm, size_t(c->n_inst)))) return rc;
+  HIPCHK(c, ghk::fill_pattern(c->d_dAb, (long long)(2 * F50), c->stream));
+  HIPCHK(c, ghk::fill_pattern(c->d_T, (long long)F50, c->stream));
+  if ((rc = autotune(c, c->derivT, c->d_dAb, c->d_T, 2))) return rc;
+  if (c->filter_kind == 1)
+    if ((rc = autotune(c, c->filterT, c->d_T, c->d_Lb, 3))) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->have_adj = true;
+  return GH_OK;
+}
+
+// out = (d RHS / d u)^T mu at state x; adds coef * (use_dt ? dt : 1) * (dRHS/dgamma)^T mu
+// to g (device [n_inst][3]) if g is not null.  Uses d_W, d_dA, d_dR, d_Lb, d_dRb, d_dAb.
+int queue_rhs_vjp(gh_ctx* c, const double* x, const double* mu, double* out, double coef, int use_dt,
+                  double* g) {
+  int rc = queue_derivs(c, x);
+  if (rc) return rc;
+  HIPCHK(c, ghk::pointwise_rhs(c->d_sh, c->d_blk, c->n_blk, c->d_angtab, c->d_radtab, x, c->d_dR, c->d_dA,
+                               c->d_H, c->d_dH, c->d_gamma, c->d_W, c->stream));
+  HIPCHK(c, ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 0, 1.0, mu, 0.0, nullptr, 0.0, nullptr, c->d_Lb,
+                         c->stream));
+  HIPCHK(c, ghk::boundary_vjp(c->d_sh, c->n_shells, c->max_S, c->d_bctab, c->d_gamma, c->d_W, c->d_Lb, c->d_bcg,
+                              c->stream));
+  {
+    Timed t(c, 6);
+    HIPCHK(c, ghk::pointwise_vjp(c->d_sh, c->d_blk, c->n_blk, c->d_angtab, c->d_radtab, x, c->d_dR, c->d_dA,
+                                 c->d_H, c->d_dH, c->d_gamma, c->d_Lb, out, c->d_dRb, c->d_dAb, c->d_gpart,
+                                 c->stream));
+  }
+  {
+    Timed t(c, 7);
+    HIPCHK(c, ghk::gemm(c->derivT.shape, c->derivT.d_tiles, c->derivT.n_tiles, c->derivT.d_groups, c->d_dAb, out,
+                        c->stream, 2));
+  }
+  if (c->maxr)
+    HIPCHK(c, ghk::radial_col(c->maxr, c->d_sh, c->d_cblk, c->n_cblk, c->d_dtab, c->d_dRb, out, 0, 50, true, true,
+                              c->stream));
+  else
+    return fail(c, GH_ERR_ARG, "adjoint needs n_r <= 64");
+  if (g)
+    HIPCHK(c, ghk::gamma_reduce(c->d_inst_range, c->d_shell_range, c->n_inst, c->max_S, c->d_gpart, c->d_bcg,
+                                c->d_dt, coef, use_dt, g, c->stream));
+  return GH_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -430,6 +512,13 @@ int gh_set_domain(gh_ctx* c, int n_inst, int n_shells, const gh_shell* shells, i
   if ((rc = upload(c, &c->d_angtab, angtab))) return rc;
   if ((rc = upload(c, &c->d_radtab, radtab))) return rc;
   if ((rc = upload(c, &c->d_inst_range, range))) return rc;
+  std::vector<int> srange(2 * n_inst, 0);
+  for (int k = 0; k < n_shells; ++k) {
+    int i = shells[k].instance;
+    if (k == 0 || shells[k - 1].instance != i) srange[2 * i] = k;
+    srange[2 * i + 1] = k + 1;
+  }
+  if ((rc = upload(c, &c->d_shell_range, srange))) return rc;
   if ((rc = upload(c, &c->d_wsum, wsum))) return rc;
   if ((rc = dalloc(c, &c->d_bctab, size_t(std::max(bc_total, 1))))) return rc;
   if ((rc = dalloc(c, &c->d_partial, size_t(c->n_blk)))) return rc;
@@ -449,6 +538,12 @@ int gh_set_domain(gh_ctx* c, int n_inst, int n_shells, const gh_shell* shells, i
     double* d = nullptr;
     if ((rc = upload(c, &d, Bop))) return rc;
     c->d_angop[L] = d;
+    std::vector<double> BopT(size_t(2) * S * S);
+    std::copy(Th.begin(), Th.end(), BopT.begin());
+    std::copy(Ph.begin(), Ph.end(), BopT.begin() + size_t(S) * S);
+    double* dT = nullptr;
+    if ((rc = upload(c, &dT, BopT))) return rc;
+    c->d_angopT[L] = dT;
     if (filter_kind == 1) {
       auto sig = ghsetup::exp_filter_sigma(L, c->filt[0], c->filt[1], c->filt[2]);
       auto F = ghsetup::sphere_operator(L, 2, sig);
@@ -458,6 +553,9 @@ int gh_set_domain(gh_ctx* c, int n_inst, int n_shells, const gh_shell* shells, i
       double* f = nullptr;
       if ((rc = upload(c, &f, FT))) return rc;
       c->d_filtop[L] = f;
+      double* fT = nullptr;
+      if ((rc = upload(c, &fT, F))) return rc;
+      c->d_filtopT[L] = fT;
     }
   }
 
@@ -475,12 +573,22 @@ int gh_set_domain(gh_ctx* c, int n_inst, int n_shells, const gh_shell* shells, i
     gd.M = rows; gd.N = 2 * S; gd.K = S;
     gd.lda = S; gd.ldb = 2 * S; gd.ldc = 2 * S;
     c->deriv.groups.push_back(gd);
+    GemmGroup gt;                      // transposed derivative: [50 n_r x 2S] (Theta ; Phi) -> [50 n_r x S]
+    gt.a_off = 100LL * c->offs[k];
+    gt.c_off = 50LL * c->offs[k];
+    gt.B = c->d_angopT[L];
+    gt.M = rows; gt.N = S; gt.K = 2 * S;
+    gt.lda = 2 * S; gt.ldb = S; gt.ldc = S;
+    c->derivT.groups.push_back(gt);
     if (filter_kind == 1) {
       GemmGroup gf = gd;
       gf.c_off = 50LL * c->offs[k];
       gf.B = c->d_filtop[L];
       gf.N = S; gf.ldb = S; gf.ldc = S;
       c->filter.groups.push_back(gf);
+      GemmGroup gft = gf;
+      gft.B = c->d_filtopT[L];
+      c->filterT.groups.push_back(gft);
     }
     k = k1;
   }
@@ -618,6 +726,76 @@ int gh_constraints(gh_ctx* c, const double* u, double* C, double* norm) {
   HIPCHK(c, ghk::constraints(c->d_sh, c->d_blk, c->n_blk, c->d_angtab, c->d_radtab, u, c->d_dR, c->d_dA, c->d_H,
                              C, c->d_partial, c->stream));
   if (norm) HIPCHK(c, ghk::reduce_norm(c->d_inst_range, c->n_inst, c->d_partial, c->d_wsum, norm, c->stream));
+  return GH_OK;
+}
+
+int gh_rhs_vjp(gh_ctx* c, const double* u, const double* lam, double* lam_u, double* g_gamma) {
+  int rc = check_ready(c, false);
+  if (rc) return rc;
+  if (!u || !lam || !lam_u || lam_u == u || lam_u == lam)
+    return fail(c, GH_ERR_ARG, "u, lam, lam_u must be device pointers and lam_u distinct from u and lam");
+  HIPCHK(c, hipSetDevice(c->device));
+  if ((rc = ensure_adjoint(c))) return rc;
+  return queue_rhs_vjp(c, u, lam, lam_u, 1.0, 0, g_gamma);
+}
+
+int gh_step_vjp(gh_ctx* c, const double* u_n, const double* lam_np1, double* lam_n, double* g_gamma) {
+  int rc = check_ready(c, true);
+  if (rc) return rc;
+  if (!u_n || !lam_np1 || !lam_n || lam_n == u_n)
+    return fail(c, GH_ERR_ARG, "u_n, lam_np1, lam_n must be device pointers and lam_n distinct from u_n");
+  HIPCHK(c, hipSetDevice(c->device));
+  if ((rc = ensure_adjoint(c))) return rc;
+  // recompute the stages: u1 = u + h L(u), u2 = 3/4 u + 1/4 (u1 + h L(u1))
+  if ((rc = queue_rhs(c, u_n, c->d_W))) return rc;
+  HIPCHK(c, ghk::rk_stage(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 0.0, nullptr, 1.0, u_n, c->d_W, c->d_u1, c->stream));
+  if ((rc = queue_rhs(c, c->d_u1, c->d_W))) return rc;
+  HIPCHK(c, ghk::rk_stage(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 0.75, u_n, 0.25, c->d_u1, c->d_W, c->d_u2,
+                          c->stream));
+  // filter: u_{n+1} = F u3, so lam3 = F^T lam_{n+1}
+  const double* lam3 = lam_np1;
+  if (c->filter_kind == 1) {
+    HIPCHK(c, ghk::gemm(c->filterT.shape, c->filterT.d_tiles, c->filterT.n_tiles, c->filterT.d_groups, lam_np1,
+                        c->d_lam3, c->stream, 3));
+    lam3 = c->d_lam3;
+  }
+  // u3 = 1/3 u + 2/3 (u2 + h L(u2))
+  if ((rc = queue_rhs_vjp(c, c->d_u2, lam3, c->d_T, 2.0 / 3.0, 1, g_gamma))) return rc;
+  HIPCHK(c, ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 1, 0.0, nullptr, 2.0 / 3.0, lam3, 2.0 / 3.0, c->d_T,
+                         c->d_mu2, c->stream));
+  // u2 = 3/4 u + 1/4 (u1 + h L(u1))
+  if ((rc = queue_rhs_vjp(c, c->d_u1, c->d_mu2, c->d_T, 0.25, 1, g_gamma))) return rc;
+  HIPCHK(c, ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 1, 0.0, nullptr, 0.25, c->d_mu2, 0.25, c->d_T,
+                         c->d_mu1, c->stream));
+  // u1 = u + h L(u)
+  if ((rc = queue_rhs_vjp(c, u_n, c->d_mu1, c->d_T, 1.0, 1, g_gamma))) return rc;
+  HIPCHK(c, ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 0, 1.0 / 3.0, lam3, 0.75, c->d_mu2, 0.0, nullptr,
+                         lam_n, c->stream));
+  HIPCHK(c, ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 1, 1.0, lam_n, 1.0, c->d_mu1, 1.0, c->d_T, lam_n,
+                         c->stream));
+  return GH_OK;
+}
+
+int gh_constraints_vjp(gh_ctx* c, const double* u, const double* lam_norm, double* lam_u) {
+  if (!c) return GH_ERR_ARG;
+  if (!c->have_domain) return fail(c, GH_ERR_ORDER, "gh_set_domain has not been called");
+  if (!c->have_bg) return fail(c, GH_ERR_ORDER, "gh_set_background has not been called");
+  if (!u || !lam_norm || !lam_u || lam_u == u)
+    return fail(c, GH_ERR_ARG, "u, lam_norm, lam_u must be device pointers and lam_u distinct from u");
+  HIPCHK(c, hipSetDevice(c->device));
+  int rc = ensure_adjoint(c);
+  if (rc) return rc;
+  if ((rc = queue_derivs(c, u))) return rc;
+  HIPCHK(c, ghk::constraints(c->d_sh, c->d_blk, c->n_blk, c->d_angtab, c->d_radtab, u, c->d_dR, c->d_dA, c->d_H,
+                             c->d_C, c->d_partial, c->stream));
+  HIPCHK(c, ghk::reduce_norm(c->d_inst_range, c->n_inst, c->d_partial, c->d_wsum, c->d_norm, c->stream));
+  HIPCHK(c, ghk::constraints_vjp(c->d_sh, c->d_blk, c->n_blk, c->d_angtab, c->d_radtab, u, c->d_H, c->d_C, c->d_norm,
+                                 c->d_wsum, lam_norm, lam_u, c->d_dRb, c->d_dAb, c->stream));
+  HIPCHK(c, ghk::gemm(c->derivT.shape, c->derivT.d_tiles, c->derivT.n_tiles, c->derivT.d_groups, c->d_dAb, lam_u,
+                      c->stream, 2));
+  if (!c->maxr) return fail(c, GH_ERR_ARG, "adjoint needs n_r <= 64");
+  HIPCHK(c, ghk::radial_col(c->maxr, c->d_sh, c->d_cblk, c->n_cblk, c->d_dtab, c->d_dRb, lam_u, 0, 50, true, true,
+                            c->stream));
   return GH_OK;
 }
 

@@ -85,4 +85,22 @@ hipError_t bc_setup(const ShellDev* sh, int n_shells, int max_S, const double* a
 
 hipError_t nonfinite_count(const double* x, long long n, int* count, hipStream_t st);
 
+// adjoint
+hipError_t pointwise_vjp(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* angtab,
+                         const double* radtab, const double* u, const double* dR, const double* dA,
+                         const double* H, const double* dH, const double* gamma, const double* lam,
+                         double* ubar, double* dRb, double* dAb, double* gpart, hipStream_t st);
+hipError_t constraints_vjp(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* angtab,
+                           const double* radtab, const double* u, const double* H, const double* C,
+                           const double* norm, const double* wsum, const double* lam_norm, double* ubar,
+                           double* dRb, double* dAb, hipStream_t st);
+hipError_t boundary_vjp(const ShellDev* sh, int n_shells, int max_S, const double* bctab, const double* gamma,
+                        const double* W, double* Lb, double* bcg, hipStream_t st);
+hipError_t gamma_reduce(const int* blk_range, const int* shell_range, int n_inst, int max_S,
+                        const double* gpart, const double* bcg, const double* dt, double coef, int use_dt,
+                        double* g, hipStream_t st);
+hipError_t lincomb(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* dt, int use_dt, double ca,
+                   const double* x, double cb, const double* y, double cc, const double* z, double* out,
+                   hipStream_t st);
+
 }  // namespace ghk

@@ -4,6 +4,7 @@
 #include <cmath>
 
 #include "ghmi_internal.h"
+#include "gh_point.h"
 
 namespace {
 
@@ -31,9 +32,10 @@ __host__ __device__ constexpr int SYM3(int i, int j) {
 //   B (4x16): lane l holds B[l / 16][l % 16]
 //   C (16x16): lane l holds C[l/16 + 4*v][l % 16], v = 0..3 (checked on gfx950)
 // ---------------------------------------------------------------------------
-// ROLE only separates the kernel symbols of the different uses (0: angular
-// derivative, 1: filter, 2: transposed derivative of the adjoint) so that
-// profiles attribute time to each; the code is the same.
+// ROLE separates the kernel symbols of the different uses (0: angular
+// derivative, 1: filter, 2: transposed derivative of the adjoint, 3: transposed
+// filter) so that profiles attribute time to each.  ROLE 2 adds into C
+// (C += A B); the others overwrite C.
 template <int BM, int BN, int ROLE>
 __global__ __launch_bounds__(256) void k_gemm(const GemmTile* __restrict__ tiles,
                                               const GemmGroup* __restrict__ groups,
@@ -149,7 +151,10 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmTile* __restrict__ tiles
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = t.m0 + wm + i * 16 + (lane / 16) + 4 * v;
-        if (row < M && col < N) Cg[(long long)row * G.ldc + col] = acc[i][j][v];
+        if (row < M && col < N) {
+          if (ROLE == 2) Cg[(long long)row * G.ldc + col] += acc[i][j][v];
+          else Cg[(long long)row * G.ldc + col] = acc[i][j][v];
+        }
       }
     }
 }
@@ -707,6 +712,224 @@ __global__ __launch_bounds__(256) void k_reduce_norm(const int* __restrict__ ran
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint kernels.
+// ---------------------------------------------------------------------------
+
+// Reverse of the pointwise GH algebra and of the Cartesian Jacobian: from the
+// cotangent lam of the raw (pre-boundary) d_t u, write the direct cotangent of
+// u (overwriting ubar), the cotangents of the spherical derivatives (dRb and
+// dAb, laid out like dR and dA) and per-block sums of the gamma cotangents.
+__global__ __launch_bounds__(256) void k_pointwise_vjp(
+    const ShellDev* __restrict__ sh, const PtBlock* __restrict__ blk,
+    const double* __restrict__ angtab, const double* __restrict__ radtab,
+    const double* __restrict__ u, const double* __restrict__ dR, const double* __restrict__ dA,
+    const double* __restrict__ Hin, const double* __restrict__ dHin, const double* __restrict__ gamma,
+    const double* __restrict__ lam, double* __restrict__ ubar, double* __restrict__ dRb,
+    double* __restrict__ dAb, double* __restrict__ gpart) {
+  __shared__ double red[3][256];
+  const PtBlock b = blk[blockIdx.x];
+  const ShellDev s = sh[b.shell];
+  const int P = s.n_r * s.S;
+  const int q = b.q0 + threadIdx.x;
+  double gb[3] = {0.0, 0.0, 0.0};
+  if (q < P) {
+    const int r = q / s.S, a = q - r * s.S;
+    const long long ub = 50LL * s.pt_off + q;
+    const long long ab = 100LL * s.pt_off + (long long)r * 2 * s.S + a;
+    const long long astride = (long long)s.n_r * 2 * s.S;
+    const Jac J = jacobian(angtab + 5LL * (s.ang_off + a), radtab[2 * (s.rad_off + r)]);
+    double uu[50], du[3][50], H[4], dH[16], lm[50], uo[50], duo[3][50];
+    for (int f = 0; f < 50; ++f) {
+      uu[f] = u[ub + (long long)f * P];
+      lm[f] = lam[ub + (long long)f * P];
+      double d[3];
+      cart(J, dR[ub + (long long)f * P], dA[ab + (long long)f * astride], dA[ab + (long long)f * astride + s.S], d);
+      du[0][f] = d[0]; du[1][f] = d[1]; du[2][f] = d[2];
+    }
+    for (int c = 0; c < 4; ++c) H[c] = Hin[4LL * s.pt_off + (long long)c * P + q];
+    for (int c = 0; c < 16; ++c) dH[c] = dHin[16LL * s.pt_off + (long long)c * P + q];
+    ghp::rhs_vjp(uu, du, H, dH, gamma[3 * s.instance], gamma[3 * s.instance + 1], gamma[3 * s.instance + 2],
+                 lm, uo, duo, gb);
+    for (int f = 0; f < 50; ++f) {
+      ubar[ub + (long long)f * P] = uo[f];
+      const double x = duo[0][f], y = duo[1][f], z = duo[2][f];
+      dRb[ub + (long long)f * P] = J.xr * x + J.yr * y + J.zr * z;
+      dAb[ab + (long long)f * astride] = J.xt * x + J.yt * y + J.zt * z;
+      dAb[ab + (long long)f * astride + s.S] = J.xp * x + J.yp * y;
+    }
+  }
+  for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = gb[c];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) gpart[3LL * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Transpose of the boundary treatment, in place on the cotangent L of d_t u.
+// The interface map writes the same value into both shells, so its transpose
+// takes the summed cotangent back through reconstruction, upwind selection and
+// projection; the outer Dirichlet rows have zero transpose.  The gamma2
+// dependence of the exchange needs the raw d_t u (W); each point's gamma2
+// cotangent goes to bcg[shell * max_S + a] (zero where there is no interface).
+__global__ __launch_bounds__(256) void k_boundary_vjp(const ShellDev* __restrict__ sh, int max_S,
+                                                      const double* __restrict__ bctab,
+                                                      const double* __restrict__ gamma,
+                                                      const double* __restrict__ W, double* __restrict__ Lb,
+                                                      double* __restrict__ bcg) {
+  const int k = blockIdx.y;
+  const ShellDev s = sh[k];
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= max_S) return;
+  double contrib = 0.0;
+  if (a < s.S) {
+    const int P = s.n_r * s.S;
+    const long long ia = 50LL * s.pt_off + (long long)(s.n_r - 1) * s.S + a;
+    if (s.outer) {
+      for (int f = 0; f < 50; ++f) Lb[ia + (long long)f * P] = 0.0;
+    } else if (s.bc_off >= 0) {
+      const ShellDev t = sh[k + 1];
+      const int Pt = t.n_r * t.S;
+      const long long ib = 50LL * t.pt_off + a;
+      const double* T = bctab + s.bc_off + 9LL * a;
+      const double sl[3] = {T[0], T[1], T[2]}, su[3] = {T[3], T[4], T[5]};
+      const double w0 = T[6], wp = T[7], wm = T[8];
+      const double g2 = gamma[3 * s.instance + 2];
+      for (int n = 0; n < 10; ++n) {
+        double l[5];
+        for (int c = 0; c < 5; ++c)
+          l[c] = Lb[ia + (long long)(10 * c + n) * P] + Lb[ib + (long long)(10 * c + n) * Pt];
+        const double slL = sl[0] * l[2] + sl[1] * l[3] + sl[2] * l[4];
+        const double ups_b = l[0] + g2 * l[1];
+        const double up_b = 0.5 * l[1] + 0.5 * slL;
+        const double um_b = 0.5 * l[1] - 0.5 * slL;
+        const double A0 = W[ia + (long long)n * P], B0 = W[ib + (long long)n * Pt];
+        contrib += l[1] * 0.5 * (A0 + B0) - up_b * (wp * A0 + (1.0 - wp) * B0) -
+                   um_b * (wm * A0 + (1.0 - wm) * B0);
+        const double sLu0 = sl[0] * l[2] + sl[1] * l[3] + sl[2] * l[4];   // sum_i s_i u0_b[i]
+        for (int side = 0; side < 2; ++side) {
+          const double xp = side ? 1.0 - wp : wp, xm = side ? 1.0 - wm : wm, x0 = side ? 1.0 - w0 : w0;
+          const double sP_b = xp * up_b - xm * um_b - x0 * sLu0;
+          double o[5];
+          o[0] = 0.5 * ups_b - g2 * (xp * up_b + xm * um_b);
+          o[1] = xp * up_b + xm * um_b;
+          for (int i = 0; i < 3; ++i) o[2 + i] = x0 * l[2 + i] + su[i] * sP_b;
+          for (int c = 0; c < 5; ++c) {
+            if (side) Lb[ib + (long long)(10 * c + n) * Pt] = o[c];
+            else Lb[ia + (long long)(10 * c + n) * P] = o[c];
+          }
+        }
+      }
+    }
+  }
+  bcg[(long long)k * max_S + a] = contrib;
+}
+
+// Reverse of the constraint norm: for loss sum_i lam_norm[i] ||C||_i the
+// cotangent of C_c(p) is lam_norm w_p C_c / (||C|| sum w); it is taken back
+// through C_a (gauge constraint), C_iab = d_i psi_ab - Phi_iab and
+// C_ijab = d_i Phi_jab - d_j Phi_iab to u (overwriting ubar) and to the
+// spherical derivatives (dRb, dAb).
+__global__ __launch_bounds__(256) void k_constraints_vjp(
+    const ShellDev* __restrict__ sh, const PtBlock* __restrict__ blk,
+    const double* __restrict__ angtab, const double* __restrict__ radtab,
+    const double* __restrict__ u, const double* __restrict__ Hin, const double* __restrict__ Cv,
+    const double* __restrict__ norm, const double* __restrict__ wsum, const double* __restrict__ lam_norm,
+    double* __restrict__ ubar, double* __restrict__ dRb, double* __restrict__ dAb) {
+  const PtBlock b = blk[blockIdx.x];
+  const ShellDev s = sh[b.shell];
+  const int P = s.n_r * s.S;
+  const int q = b.q0 + threadIdx.x;
+  if (q >= P) return;
+  const int r = q / s.S, a = q - r * s.S;
+  const long long ub = 50LL * s.pt_off + q;
+  const long long cb = 64LL * s.pt_off + q;
+  const long long ab = 100LL * s.pt_off + (long long)r * 2 * s.S + a;
+  const long long astride = (long long)s.n_r * 2 * s.S;
+  const double* ang = angtab + 5LL * (s.ang_off + a);
+  const Jac J = jacobian(ang, radtab[2 * (s.rad_off + r)]);
+  const double w = ang[4] * radtab[2 * (s.rad_off + r) + 1];
+  const double nrm = norm[s.instance];
+  const double f = (nrm > 0.0) ? lam_norm[s.instance] * w / (nrm * wsum[s.instance]) : 0.0;
+  double uu[50], H[4], uo[50], duo[3][50];
+  for (int c = 0; c < 50; ++c) {
+    uu[c] = u[ub + (long long)c * P];
+    uo[c] = 0.0;
+    duo[0][c] = duo[1][c] = duo[2][c] = 0.0;
+  }
+  for (int c = 0; c < 4; ++c) H[c] = Hin[4LL * s.pt_off + (long long)c * P + q];
+  double Cb[4];
+  for (int c = 0; c < 4; ++c) Cb[c] = f * Cv[cb + (long long)c * P];
+  ghp::gauge_constraint_vjp(uu, H, Cb, uo);
+  for (int i = 0; i < 3; ++i)
+    for (int n = 0; n < 10; ++n) {
+      const double g = f * Cv[cb + (long long)(4 + 10 * i + n) * P];
+      duo[i][n] += g;
+      uo[20 + 10 * i + n] -= g;
+    }
+  const int pi[3] = {0, 0, 1}, pj[3] = {1, 2, 2};
+  for (int m = 0; m < 3; ++m)
+    for (int n = 0; n < 10; ++n) {
+      const double g = f * Cv[cb + (long long)(34 + 10 * m + n) * P];
+      duo[pi[m]][20 + 10 * pj[m] + n] += g;
+      duo[pj[m]][20 + 10 * pi[m] + n] -= g;
+    }
+  for (int c = 0; c < 50; ++c) {
+    ubar[ub + (long long)c * P] = uo[c];
+    const double x = duo[0][c], y = duo[1][c], z = duo[2][c];
+    dRb[ub + (long long)c * P] = J.xr * x + J.yr * y + J.zr * z;
+    dAb[ab + (long long)c * astride] = J.xt * x + J.yt * y + J.zt * z;
+    dAb[ab + (long long)c * astride + s.S] = J.xp * x + J.yp * y;
+  }
+}
+
+// g[i] += coef * (use_dt ? dt[i] : 1) * (gamma cotangents of instance i), summed
+// in a fixed order over its point blocks and its interface points.
+__global__ __launch_bounds__(256) void k_gamma_reduce(const int* __restrict__ blk_range,
+                                                      const int* __restrict__ shell_range, int max_S,
+                                                      const double* __restrict__ gpart,
+                                                      const double* __restrict__ bcg,
+                                                      const double* __restrict__ dt, double coef, int use_dt,
+                                                      double* __restrict__ g) {
+  __shared__ double red[3][256];
+  const int i = blockIdx.x;
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int b = blk_range[2 * i] + threadIdx.x; b < blk_range[2 * i + 1]; b += 256)
+    for (int c = 0; c < 3; ++c) s[c] += gpart[3LL * b + c];
+  const long long e0 = (long long)shell_range[2 * i] * max_S, e1 = (long long)shell_range[2 * i + 1] * max_S;
+  for (long long e = e0 + threadIdx.x; e < e1; e += 256) s[2] += bcg[e];
+  for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = s[c];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) g[3 * i + threadIdx.x] += coef * (use_dt ? dt[i] : 1.0) * red[threadIdx.x][0];
+}
+
+// out = a x + b y + c h z elementwise over the 50 fields (h = dt of the
+// instance if use_dt, else 1); null x, y or z is skipped.  out may alias x, y or z.
+__global__ __launch_bounds__(256) void k_lincomb(const ShellDev* __restrict__ sh, const PtBlock* __restrict__ blk,
+                                                 const double* __restrict__ dt, int use_dt, double ca,
+                                                 const double* x, double cb, const double* y, double cc,
+                                                 const double* z, double* out) {
+  const PtBlock b = blk[blockIdx.x];
+  const ShellDev s = sh[b.shell];
+  const int P = s.n_r * s.S;
+  const int q = b.q0 + threadIdx.x;
+  if (q >= P) return;
+  const long long e = 50LL * s.pt_off + (long long)blockIdx.y * P + q;
+  double v = 0.0;
+  if (x) v += ca * x[e];
+  if (y) v += cb * y[e];
+  if (z) v += cc * (use_dt ? dt[s.instance] : 1.0) * z[e];
+  out[e] = v;
+}
+
+// ---------------------------------------------------------------------------
 // Setup: frozen interface projections from u_bg, and excision outflow speeds.
 // bctab record per interface point: s_i (3), s^i (3), upwind weights of the
 // inner side for u^0, u^+, u^- (1, 0 or 1/2 by the sign of the speed).
@@ -819,7 +1042,8 @@ hipError_t gemm(int shape, const GemmTile* tiles, int n_tiles, const GemmGroup* 
   switch (role) {
     case 0: return gemm_role<0>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
     case 1: return gemm_role<1>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
-    default: return gemm_role<2>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
+    case 2: return gemm_role<2>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
+    default: return gemm_role<3>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
   }
 }
 
@@ -924,6 +1148,46 @@ hipError_t bc_setup(const ShellDev* sh, int n_shells, int max_S, const double* a
                     const double* u_bg, double* bctab, double* exmin, hipStream_t st) {
   dim3 grid((max_S + 255) / 256, n_shells), block(256);
   hipLaunchKernelGGL(k_bc_setup, grid, block, 0, st, sh, max_S, angtab, u_bg, bctab, exmin);
+  return hipGetLastError();
+}
+
+hipError_t pointwise_vjp(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* angtab,
+                         const double* radtab, const double* u, const double* dR, const double* dA,
+                         const double* H, const double* dH, const double* gamma, const double* lam,
+                         double* ubar, double* dRb, double* dAb, double* gpart, hipStream_t st) {
+  hipLaunchKernelGGL(k_pointwise_vjp, dim3(n_blk), dim3(256), 0, st, sh, blk, angtab, radtab, u, dR, dA, H, dH,
+                     gamma, lam, ubar, dRb, dAb, gpart);
+  return hipGetLastError();
+}
+
+hipError_t constraints_vjp(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* angtab,
+                           const double* radtab, const double* u, const double* H, const double* C,
+                           const double* norm, const double* wsum, const double* lam_norm, double* ubar,
+                           double* dRb, double* dAb, hipStream_t st) {
+  hipLaunchKernelGGL(k_constraints_vjp, dim3(n_blk), dim3(256), 0, st, sh, blk, angtab, radtab, u, H, C, norm, wsum,
+                     lam_norm, ubar, dRb, dAb);
+  return hipGetLastError();
+}
+
+hipError_t boundary_vjp(const ShellDev* sh, int n_shells, int max_S, const double* bctab, const double* gamma,
+                        const double* W, double* Lb, double* bcg, hipStream_t st) {
+  dim3 grid((max_S + 255) / 256, n_shells), block(256);
+  hipLaunchKernelGGL(k_boundary_vjp, grid, block, 0, st, sh, max_S, bctab, gamma, W, Lb, bcg);
+  return hipGetLastError();
+}
+
+hipError_t gamma_reduce(const int* blk_range, const int* shell_range, int n_inst, int max_S,
+                        const double* gpart, const double* bcg, const double* dt, double coef, int use_dt,
+                        double* g, hipStream_t st) {
+  hipLaunchKernelGGL(k_gamma_reduce, dim3(n_inst), dim3(256), 0, st, blk_range, shell_range, max_S, gpart, bcg,
+                     dt, coef, use_dt, g);
+  return hipGetLastError();
+}
+
+hipError_t lincomb(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* dt, int use_dt, double ca,
+                   const double* x, double cb, const double* y, double cc, const double* z, double* out,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_lincomb, dim3(n_blk, 50), dim3(256), 0, st, sh, blk, dt, use_dt, ca, x, cb, y, cc, z, out);
   return hipGetLastError();
 }
 

@@ -24,11 +24,11 @@ EXPORTS = [
     "gh_create", "gh_destroy", "gh_set_stream", "gh_set_domain", "gh_num_points",
     "gh_set_background", "gh_set_params", "gh_rhs", "gh_step", "gh_constraints",
     "gh_last_error", "gh_grid_coords", "gh_host_operator", "gh_set_timing", "gh_kernel_stats",
-    "gh_query",
+    "gh_query", "gh_rhs_vjp", "gh_step_vjp", "gh_constraints_vjp",
 ]
 
 KERNEL_KINDS = {"deriv_gemm": 0, "filter_gemm": 1, "radial": 2, "pointwise": 3, "boundary": 4,
-                "rk_stage": 5}
+                "rk_stage": 5, "pointwise_vjp": 6, "deriv_gemm_T": 7}
 
 
 class GHError(RuntimeError):
@@ -75,6 +75,9 @@ def load_library(path=LIB_PATH):
         "gh_set_timing": (i, [vp, i]),
         "gh_kernel_stats": (i, [vp, i, pll, pd]),
         "gh_query": (i, [vp, i, pll]),
+        "gh_rhs_vjp": (i, [vp, vp, vp, vp, vp]),
+        "gh_step_vjp": (i, [vp, vp, vp, vp, vp]),
+        "gh_constraints_vjp": (i, [vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -227,6 +230,32 @@ class GHSolver:
         ms = ctypes.c_double()
         self._check(self.lib.gh_kernel_stats(self.h, KERNEL_KINDS[kind], ctypes.byref(n), ctypes.byref(ms)))
         return int(n.value), float(ms.value)
+
+    def rhs_vjp(self, u, lam, g_gamma=None, out=None):
+        """(d rhs/du)^T lam; g_gamma (float64 CUDA [n_inst*3]) is incremented if given."""
+        out = self.new_field() if out is None else out
+        self._sync_stream()
+        g = ctypes.c_void_p(g_gamma.data_ptr()) if g_gamma is not None else None
+        self._check(self.lib.gh_rhs_vjp(self.h, self._dev(u, 50, "u"), self._dev(lam, 50, "lam"),
+                                        self._dev(out, 50, "lam_u"), g))
+        return out
+
+    def step_vjp(self, u_n, lam_np1, g_gamma=None, out=None):
+        """(d step/du_n)^T lam_np1; g_gamma incremented if given."""
+        out = self.new_field() if out is None else out
+        self._sync_stream()
+        g = ctypes.c_void_p(g_gamma.data_ptr()) if g_gamma is not None else None
+        self._check(self.lib.gh_step_vjp(self.h, self._dev(u_n, 50, "u_n"), self._dev(lam_np1, 50, "lam_np1"),
+                                         self._dev(out, 50, "lam_n"), g))
+        return out
+
+    def constraints_vjp(self, u, lam_norm, out=None):
+        """sum_i lam_norm[i] d||C||_i/du (lam_norm: float64 CUDA [n_inst])."""
+        out = self.new_field() if out is None else out
+        self._sync_stream()
+        self._check(self.lib.gh_constraints_vjp(self.h, self._dev(u, 50, "u"), ctypes.c_void_p(lam_norm.data_ptr()),
+                                                self._dev(out, 50, "lam_u")))
+        return out
 
     def query(self, what):
         """0: derivative GEMM tile (BM*1000+BN), 1: filter GEMM tile, 2: derivative tiles, 3: points."""

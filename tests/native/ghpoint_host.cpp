@@ -10,3 +10,11 @@ extern "C" int ghp_rhs_vjp(int n, const double* u, const double* du, const doubl
                  gbar);
   return 0;
 }
+
+extern "C" int ghp_gauge_constraint_vjp(int n, const double* u, const double* H, const double* Cbar, double* ubar) {
+  for (int p = 0; p < n; ++p) {
+    for (int f = 0; f < 50; ++f) ubar[50 * p + f] = 0.0;
+    ghp::gauge_constraint_vjp(u + 50 * p, H + 4 * p, Cbar + 4 * p, ubar + 50 * p);
+  }
+  return 0;
+}

@@ -77,3 +77,21 @@ def test_pointwise_vjp_matches_complex_step_jvp(harness, seed, gam):
         l2 = np.sum(lam * r2.imag / h)
         r2v = np.sum(ub.T * vu2) + np.sum(np.transpose(dub, (1, 2, 0)) * vdu2) + gb @ vg2
         assert abs(l2 - r2v) < 1e-13 * (np.sum(np.abs(lam * r2.imag / h)) + abs(l2)), (which, l2, r2v)
+
+
+def test_gauge_constraint_vjp_matches_complex_step(harness):
+    u, du, H, dH = _state(7)
+    n = u.shape[1]
+    rng = np.random.default_rng(11)
+    cbar = rng.standard_normal((4, n))
+    vu = rng.standard_normal((50, n))
+    h = 1e-30
+    uc = u + 1j * h * vu
+    psi, Pi, Phi = gh.unpack_fields(uc)
+    C = gh.gauge_constraint(gh.Geometry(psi), Pi, Phi, H)
+    lhs = np.sum(cbar * C.imag / h)
+    ub = np.zeros((n, 50))
+    harness.ghp_gauge_constraint_vjp(n, _ptr(np.ascontiguousarray(u.T)), _ptr(np.ascontiguousarray(H.T)),
+                                     _ptr(np.ascontiguousarray(cbar.T)), _ptr(ub))
+    rhs = np.sum(ub.T * vu)
+    assert abs(lhs - rhs) < 1e-13 * (np.sum(np.abs(cbar * C.imag / h)) + abs(lhs))

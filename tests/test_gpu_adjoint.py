@@ -1,0 +1,133 @@
+"""Adjoint of the GPU path: dot-product tests against the oracle's
+complex-step directional derivatives, and central finite differences of a
+multi-step constraint-norm loss.
+
+<lam, J v> (oracle, complex step, exact to rounding) must equal
+<J^T lam, v> (GPU reverse mode) for random lam, v and damping directions."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+from oracle import domain  # noqa: E402
+from paper_1804_09101_amd import autograd as gha  # noqa: E402
+from paper_1804_09101_amd import configs, ghmi, inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+H_CS = 1e-30
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
+
+
+def _setup(shells, holes, gamma, dt, filt, pert=1e-3, seed=1):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    wl = configs.Workload("adjoint", shells, holes, gamma, dt, filt, 1, None)
+    d = domain.Domain([domain.Shell(*s) for s in shells], filter_params=filt)
+    xyz = d.xyz()
+    u0, ubg, H, dH = wl.initial_data(xyz, d.offsets)
+    u0 = u0 + d.to_layout(inputs.smooth_random_field(xyz, pert, seed, 3, 2.0))
+    s = ghmi.GHSolver(shells, wl.n_inst, filt)
+    s.set_background(dev(H), dev(dH), dev(ubg))
+    s.set_params(wl.gamma, wl.dt)
+    return wl, d, s, u0, ubg, H, dH
+
+
+SHELLS = [(0, 7, 5, 1.8, 2.8), (0, 7, 5, 2.8, 4.5), (1, 6, 3, 1.3, 2.4), (1, 5, 3, 2.4, 3.1)]
+HOLES = [(1.0, 0.0, (0, 0, 1)), (0.8, 0.6, (0.3, -0.5, 0.8))]
+GAM = [(0.7, -0.6, 1.3), (1.0, 0.3, 0.6)]
+
+
+def test_rhs_vjp_dot_product():
+    wl, d, s, u0, ubg, H, dH = _setup(SHELLS, HOLES, GAM, [0.004, 0.003], None)
+    rng = np.random.default_rng(0)
+    lam = rng.standard_normal(u0.shape)
+    v = rng.standard_normal(u0.shape)
+    vg = rng.standard_normal((2, 3))
+    jv = d.rhs(u0 + 1j * H_CS * v, H, dH, ubg, wl.gamma + 1j * H_CS * vg).imag / H_CS
+    lhs = np.sum(lam * jv)
+    g = torch.zeros(6, dtype=torch.float64, device="cuda:0")
+    lu = s.rhs_vjp(dev(u0), dev(lam), g_gamma=g).cpu().numpy()
+    rhs = np.sum(lu * v) + np.sum(g.cpu().numpy().reshape(2, 3) * vg)
+    err = abs(lhs - rhs) / np.sum(np.abs(lam * jv))
+    print(f"  rhs vjp: <lam,Jv> {lhs:.12e} vs {rhs:.12e}, rel {err:.2e}", flush=True)
+    assert err < 1e-12
+    # the gamma part alone
+    jg = d.rhs(u0.astype(complex), H, dH, ubg, wl.gamma + 1j * H_CS * vg).imag / H_CS
+    lg, rg = np.sum(lam * jg), np.sum(g.cpu().numpy().reshape(2, 3) * vg)
+    assert abs(lg - rg) < 1e-11 * np.sum(np.abs(lam * jg))
+
+
+def test_step_vjp_dot_product_with_filter():
+    rs = configs.geometric_radii(1.8, 9.0, 2)
+    shells = [(0, 9, 7, rs[0], rs[1]), (0, 9, 7, rs[1], rs[2])]
+    wl, d, s, u0, ubg, H, dH = _setup(shells, [(1.0, 0.4, (0.1, 0.2, 1.0))], [(0.9, -0.2, 1.1)], [0.005],
+                                      configs.FILTER_DEFAULT)
+    rng = np.random.default_rng(1)
+    lam = rng.standard_normal(u0.shape)
+    v = rng.standard_normal(u0.shape)
+    vg = rng.standard_normal((1, 3))
+    jv = d.rk3_step(u0 + 1j * H_CS * v, H, dH, ubg, wl.gamma + 1j * H_CS * vg, wl.dt).imag / H_CS
+    lhs = np.sum(lam * jv)
+    g = torch.zeros(3, dtype=torch.float64, device="cuda:0")
+    ln = s.step_vjp(dev(u0), dev(lam), g_gamma=g).cpu().numpy()
+    rhs = np.sum(ln * v) + np.sum(g.cpu().numpy() * vg.ravel())
+    err = abs(lhs - rhs) / np.sum(np.abs(lam * jv))
+    print(f"  step vjp: rel {err:.2e}", flush=True)
+    assert err < 1e-12
+
+
+def test_constraints_vjp_dot_product():
+    wl, d, s, u0, ubg, H, dH = _setup(SHELLS, HOLES, GAM, [0.004, 0.003], None, pert=1e-2)
+    rng = np.random.default_rng(2)
+    v = rng.standard_normal(u0.shape)
+    lam_n = np.array([0.7, -1.3])
+    jv = d.constraint_norm(u0 + 1j * H_CS * v, H).imag / H_CS
+    lhs = np.sum(lam_n * jv)
+    lu = s.constraints_vjp(dev(u0), dev(lam_n)).cpu().numpy()
+    rhs = np.sum(lu * v)
+    err = abs(lhs - rhs) / np.sum(np.abs(lam_n * jv))
+    print(f"  constraints vjp: rel {err:.2e}", flush=True)
+    assert err < 1e-12
+
+
+def test_evolve_gradient_matches_central_differences():
+    """Loss = ||C(u_n)|| after 12 RK3 steps (checkpoint every 5); gradient w.r.t.
+    the damping parameters and along the initial Pi perturbation, against central
+    differences with h = 1e-6 run through the same GPU forward path."""
+    wl, d, s, u0, ubg, H, dH = _setup([(0, 9, 5, 1.8, 4.0)], [(1.0, 0.0, (0, 0, 1))], [(1.0, -1.0, 1.0)], [0.01],
+                                      None, pert=0.0)
+    dpi = d.to_layout(inputs.gaussian_pulse_Pi(d.xyz(), 1.0, 2.8, 0.4, 3))
+    amp = 1e-3
+    n = 12
+
+    def loss(gamma_np, a):
+        s.set_params(gamma_np, wl.dt)
+        u = dev(u0 + a * dpi)
+        s.step(u, n)
+        return float(s.constraints(u, want_C=False)[1].cpu().numpy()[0])
+
+    gamma = torch.tensor(wl.gamma, dtype=torch.float64, requires_grad=True)
+    a = torch.tensor(amp, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    u_init = dev(u0) + a * dev(dpi)
+    un = gha.evolve(u_init, gamma, s, wl.dt, n, checkpoint_every=5)
+    L = gha.constraint_norm(un, s).sum()
+    L.backward()
+    g_adj = gamma.grad.numpy().ravel()
+    a_adj = float(a.grad.cpu())
+    h = 1e-6
+    g_fd = []
+    for c in range(3):
+        gp = wl.gamma.copy()
+        gm = wl.gamma.copy()
+        gp[0, c] += h
+        gm[0, c] -= h
+        g_fd.append((loss(gp, amp) - loss(gm, amp)) / (2 * h))
+    a_fd = (loss(wl.gamma, amp + h * amp) - loss(wl.gamma, amp - h * amp)) / (2 * h * amp)
+    print(f"  dL/dgamma adjoint {g_adj}, FD {np.array(g_fd)}; dL/da adjoint {a_adj:.10e} FD {a_fd:.10e}",
+          flush=True)
+    for c in range(3):
+        assert abs(g_adj[c] - g_fd[c]) <= 1e-6 * max(abs(g_fd[c]), 1e-3 * abs(a_fd * amp)), c
+    assert abs(a_adj - a_fd) <= 1e-6 * abs(a_fd)
