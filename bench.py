@@ -7,6 +7,12 @@ is the 8-shell pulse problem: 8 shells r in [1.8, 100], N_r = 21, L = 15
 (16 x 32), Schwarzschild M = 1 with a Gaussian pulse in Pi_ab, FP64.
 
 Metric: grid-point RHS evaluations per second = points * 3 * steps / time.
+The timed region runs with per-kernel HIP-event timing on, which gives the
+angular GEMM's average launch duration for the roofline figure.  Further
+measurements on the same GPU: the same steps replayed from a captured HIP
+graph; the adjoint/forward cost ratio of a 200-step evolution with gradients
+of the final constraint norm (checkpoint every 20 steps); with --batched, 64
+heterogeneous Kerr holes in one context against one context per hole.
 
 Prints one JSON line (rank 0).  With --gpus > 1 it exits: this build runs on
 one GPU.
@@ -62,12 +68,83 @@ def cpu_baseline(wl, n_rhs):
                       f"NumPy oracle, {t:.1f} s"}
 
 
+def adjoint_ratio(solver, u0_dev, wl, n_steps=200, k=20):
+    """Forward time of n_steps vs time of the backward pass of the constraint norm."""
+    import torch
+    from paper_1804_09101_amd import autograd as gha
+    gamma = torch.tensor(wl.gamma, dtype=torch.float64, requires_grad=True)
+    u0 = u0_dev.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    un = gha.evolve(u0, gamma, solver, wl.dt, n_steps, checkpoint_every=k)
+    L = gha.constraint_norm(un, solver).sum()
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    L.backward()
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    return {"workload": f"pulse_8shell, {n_steps} RK3 steps, loss = final constraint norm, "
+                        f"checkpoint every {k} steps",
+            "forward_ms": t_fwd * 1e3, "backward_ms": t_bwd * 1e3, "ratio": t_bwd / t_fwd,
+            "grad_gamma": gamma.grad.numpy().ravel().tolist(),
+            "grad_u0_norm": float(u0.grad.norm())}
+
+
+def batched_comparison(steps):
+    """64 Kerr holes: one context (grouped launches) vs one context per hole."""
+    import torch
+    from paper_1804_09101_amd import configs, ghmi
+    wl = configs.batched_64()
+    xyz = ghmi.grid_coords(wl.shells)
+    offs = np.concatenate([[0], np.cumsum([s[1] * 2 * (s[2] + 1) ** 2 for s in wl.shells])])
+    u0, ubg, H, dH = wl.initial_data(xyz, offs, device="cuda:0")
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    P = int(offs[-1])
+    out = {"workload": "batched_64", "instances": wl.n_inst, "shells": len(wl.shells), "points": P}
+    s = ghmi.GHSolver(wl.shells, wl.n_inst)
+    s.set_background(dev(H), dev(dH), dev(ubg))
+    s.set_params(wl.gamma, wl.dt)
+    s.set_graph(True)
+    u = dev(u0)
+    s.step(u, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(u, steps)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    out["batched_value"] = P * 3 * steps / tb
+    per = []
+    for inst in range(wl.n_inst):
+        ks = [k for k, sh in enumerate(wl.shells) if sh[0] == inst]
+        lo, hi = offs[ks[0]], offs[ks[-1] + 1]
+        si = ghmi.GHSolver([(0,) + tuple(wl.shells[k][1:]) for k in ks], 1)
+        si.set_background(dev(H[4 * lo:4 * hi]), dev(dH[16 * lo:16 * hi]), dev(ubg[50 * lo:50 * hi]))
+        si.set_params(wl.gamma[inst:inst + 1], wl.dt[inst:inst + 1])
+        per.append((si, dev(u0[50 * lo:50 * hi])))
+    for si, ui in per:
+        si.step(ui, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for si, ui in per:
+            si.step(ui, 1)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    out["per_instance_value"] = P * 3 * steps / tp
+    out["speedup"] = tp / tb
+    out["unit"] = "grid-point RHS evals/s"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-rhs", type=int, default=3, help="oracle RHS evaluations for cpu_baseline (0: skip)")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward measurement")
+    ap.add_argument("--batched", action="store_true", help="also run the 64-hole batched comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the path shards by instance or by "
@@ -84,7 +161,7 @@ def main():
     wl = configs.pulse_8shell()
     xyz = ghmi.grid_coords(wl.shells)
     offs = np.concatenate([[0], np.cumsum([s[1] * 2 * (s[2] + 1) ** 2 for s in wl.shells])])
-    u0, ubg, H, dH = wl.initial_data(xyz, offs)
+    u0, ubg, H, dH = wl.initial_data(xyz, offs, device="cuda:0")
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
     solver = ghmi.GHSolver(wl.shells, wl.n_inst, wl.filter_params)
     solver.set_background(dev(H), dev(dH), dev(ubg))
@@ -107,6 +184,16 @@ def main():
 
     P = solver.P
     value = P * 3 * args.steps / t
+    # the same steps from a captured HIP graph (timing off)
+    solver.set_graph(True)
+    ug = dev(u0)
+    solver.step(ug, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.step(ug, args.steps)
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
+    solver.set_graph(False)
     n_g, ms_g = stats["deriv_gemm"]
     avg_s = ms_g / n_g / 1e3
     flops = deriv_gemm_flops(wl.shells)
@@ -135,7 +222,12 @@ def main():
                      "flops_per_launch": flops, "avg_launch_us": avg_s * 1e6},
         "kernels": kernels,
         "gemm_tiles": {"deriv": solver.query(0), "filter": solver.query(1), "deriv_tiles": solver.query(2)},
+        "graph_value": P * 3 * args.steps / t_graph,
     }
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_ratio(solver, dev(u0), wl)
+    if args.batched:
+        out["batched"] = batched_comparison(max(5, args.steps // 10))
     if args.cpu_rhs > 0:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_rhs)
     print(json.dumps(out))

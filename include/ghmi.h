@@ -118,6 +118,16 @@ int gh_rhs(gh_ctx* ctx, const double* u, double* dudt);
  *   u <- 1/3 u + 2/3 (u2 + dt L(u2)), then the filter if enabled. */
 int gh_step(gh_ctx* ctx, double* u, int n_steps);
 
+/* Graph mode for gh_step (default off).  When on, the first gh_step on a
+ * state pointer captures one whole SSP-RK3 step (every kernel of the three
+ * stages and the filter, for all shells of all instances) into a HIP graph on
+ * a stream owned by the context, and every gh_step replays it n_steps times,
+ * ordered after earlier work on the context's stream and before later work
+ * by events.  A new state pointer or domain recaptures; gh_set_params values
+ * are read from device memory at run time, so they need no recapture.
+ * Bypassed while kernel timing is on. */
+int gh_set_graph(gh_ctx* ctx, int enable);
+
 /* Constraints of u.  C (device [64] layout, may be NULL) receives per point
  * C_a (4), C_iab = d_i psi_ab - Phi_iab (30, i = x,y,z) and
  * C_ijab = d_i Phi_jab - d_j Phi_iab (30, ij = xy, xz, yz).

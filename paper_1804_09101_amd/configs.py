@@ -64,7 +64,7 @@ class Workload:
     def shells_of(self, inst):
         return [s for s in self.shells if s[0] == inst]
 
-    def initial_data(self, xyz, offsets):
+    def initial_data(self, xyz, offsets, device="cpu"):
         """Background fields, gauge source and perturbed initial state.
 
         xyz [3, P] collocation coordinates (layout point order) and the shell
@@ -79,7 +79,7 @@ class Workload:
         for inst, (M, chi, axis) in enumerate(self.holes):
             ks = [k for k, s in enumerate(self.shells) if s[0] == inst]
             lo, hi = offsets[ks[0]], offsets[ks[-1] + 1]
-            ex = inputs.kerr_schild(xyz[:, lo:hi], M=M, chi=chi, axis=axis)
+            ex = inputs.kerr_schild(xyz[:, lo:hi], M=M, chi=chi, axis=axis, device=device)
             u_pts[:, lo:hi] = ex["u"]
             H_pts[:, lo:hi] = ex["H"]
             dH_pts[:, lo:hi] = ex["dH"]

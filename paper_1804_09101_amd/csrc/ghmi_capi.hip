@@ -78,6 +78,14 @@ struct gh_ctx {
   double *d_gamma = nullptr, *d_dt = nullptr;
   std::vector<void*> allocs;
 
+  // step graphs (gh_set_graph): one captured SSP-RK3 step per state pointer
+  bool use_graph = false;
+  hipStream_t cap_stream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  const double* graph_u = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+
   // kernel timing (gh_set_timing)
   bool timing = false;
   struct Rec { hipEvent_t a, b; int kind; };
@@ -123,10 +131,20 @@ void clear_timing(gh_ctx* c) {
   c->recs.clear();
 }
 
+void drop_graph(gh_ctx* c) {
+  if (c->cap_stream) (void)hipStreamSynchronize(c->cap_stream);
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+  c->graph_u = nullptr;
+}
+
 void free_domain(gh_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  drop_graph(c);
   clear_timing(c);
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
@@ -306,6 +324,30 @@ int queue_rhs(gh_ctx* c, const double* u, double* out) {
   return GH_OK;
 }
 
+// One SSP-RK3 step (three RHS, three stage updates, filter) in place on u.
+int queue_step(gh_ctx* c, double* u) {
+  int rc;
+  const bool filt = c->filter_kind == 1;
+  auto stage = [&](double c0, const double* u0, double c1, const double* us, double* out) -> int {
+    Timed t(c, 5);
+    HIPCHK(c, ghk::rk_stage(c->d_sh, c->d_blk, c->n_blk, c->d_dt, c0, u0, c1, us, c->d_W, out, c->stream));
+    return GH_OK;
+  };
+  if ((rc = queue_rhs(c, u, c->d_W))) return rc;
+  if ((rc = stage(0.0, nullptr, 1.0, u, c->d_ua))) return rc;
+  if ((rc = queue_rhs(c, c->d_ua, c->d_W))) return rc;
+  if ((rc = stage(0.75, u, 0.25, c->d_ua, c->d_ub))) return rc;
+  if ((rc = queue_rhs(c, c->d_ub, c->d_W))) return rc;
+  double* dst = filt ? c->d_ua : u;
+  if ((rc = stage(1.0 / 3.0, u, 2.0 / 3.0, c->d_ub, dst))) return rc;
+  if (filt) {
+    Timed t(c, 1);
+    HIPCHK(c, ghk::gemm(c->filter.shape, c->filter.d_tiles, c->filter.n_tiles, c->filter.d_groups, c->d_ua, u,
+                        c->stream, 1));
+  }
+  return GH_OK;
+}
+
 // Allocate the adjoint work space and choose tile shapes of the transposed GEMMs.
 int ensure_adjoint(gh_ctx* c) {
   if (c->have_adj) return GH_OK;
@@ -388,6 +430,9 @@ int gh_create(gh_ctx** out, int device, void* hip_stream) {
 int gh_destroy(gh_ctx* c) {
   if (!c) return GH_ERR_ARG;
   free_domain(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+  if (c->ev_out) (void)hipEventDestroy(c->ev_out);
   delete c;
   return GH_OK;
 }
@@ -692,26 +737,51 @@ int gh_step(gh_ctx* c, double* u, int n_steps) {
   if (rc) return rc;
   if (!u || n_steps < 0) return fail(c, GH_ERR_ARG, "need u != NULL and n_steps >= 0");
   HIPCHK(c, hipSetDevice(c->device));
-  const bool filt = c->filter_kind == 1;
-  auto stage = [&](double c0, const double* u0, double c1, const double* us, double* out) -> int {
-    Timed t(c, 5);
-    HIPCHK(c, ghk::rk_stage(c->d_sh, c->d_blk, c->n_blk, c->d_dt, c0, u0, c1, us, c->d_W, out, c->stream));
+  if (n_steps == 0) return GH_OK;
+  if (!c->use_graph || c->timing) {
+    for (int n = 0; n < n_steps; ++n)
+      if ((rc = queue_step(c, u))) return rc;
     return GH_OK;
-  };
-  for (int n = 0; n < n_steps; ++n) {
-    if ((rc = queue_rhs(c, u, c->d_W))) return rc;
-    if ((rc = stage(0.0, nullptr, 1.0, u, c->d_ua))) return rc;
-    if ((rc = queue_rhs(c, c->d_ua, c->d_W))) return rc;
-    if ((rc = stage(0.75, u, 0.25, c->d_ua, c->d_ub))) return rc;
-    if ((rc = queue_rhs(c, c->d_ub, c->d_W))) return rc;
-    double* dst = filt ? c->d_ua : u;
-    if ((rc = stage(1.0 / 3.0, u, 2.0 / 3.0, c->d_ub, dst))) return rc;
-    if (filt) {
-      Timed t(c, 1);
-      HIPCHK(c, ghk::gemm(c->filter.shape, c->filter.d_tiles, c->filter.n_tiles, c->filter.d_groups, c->d_ua, u,
-                          c->stream, 1));
-    }
   }
+  // graph path: capture one step on the library's own stream (the caller's
+  // stream may be the legacy default stream, which cannot be captured), then
+  // replay it n_steps times, ordered after / before the caller's work by events
+  if (c->graph_u != u) {
+    drop_graph(c);
+    hipStream_t user = c->stream;
+    c->stream = c->cap_stream;
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    rc = queue_step(c, u);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    c->stream = user;
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(c, GH_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    c->graph = g;
+    HIPCHK(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+    c->graph_u = u;
+  }
+  HIPCHK(c, hipEventRecord(c->ev_in, c->stream));
+  HIPCHK(c, hipStreamWaitEvent(c->cap_stream, c->ev_in, 0));
+  for (int n = 0; n < n_steps; ++n) HIPCHK(c, hipGraphLaunch(c->graph_exec, c->cap_stream));
+  HIPCHK(c, hipEventRecord(c->ev_out, c->cap_stream));
+  HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_out, 0));
+  return GH_OK;
+}
+
+int gh_set_graph(gh_ctx* c, int enable) {
+  if (!c) return GH_ERR_ARG;
+  HIPCHK(c, hipSetDevice(c->device));
+  drop_graph(c);
+  if (enable && !c->cap_stream) {
+    HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIPCHK(c, hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+    HIPCHK(c, hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+  }
+  c->use_graph = enable != 0;
   return GH_OK;
 }
 

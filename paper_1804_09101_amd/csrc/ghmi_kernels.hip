@@ -970,7 +970,11 @@ __global__ __launch_bounds__(256) void k_bc_setup(const ShellDev* __restrict__ s
   const int k = blockIdx.y;
   const ShellDev s = sh[k];
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= s.S) return;
+  if (a >= max_S) return;
+  if (a >= s.S) {                     // every entry of the shell's row is written
+    exmin[(long long)k * max_S + a] = INFINITY;
+    return;
+  }
   const int P = s.n_r * s.S;
   const double* ang = angtab + 5LL * (s.ang_off + a);
   double sl[3], su[3], v0, vp, vm;

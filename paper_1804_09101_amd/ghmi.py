@@ -25,6 +25,7 @@ EXPORTS = [
     "gh_set_background", "gh_set_params", "gh_rhs", "gh_step", "gh_constraints",
     "gh_last_error", "gh_grid_coords", "gh_host_operator", "gh_set_timing", "gh_kernel_stats",
     "gh_query", "gh_rhs_vjp", "gh_step_vjp", "gh_constraints_vjp",
+    "gh_set_graph",
 ]
 
 KERNEL_KINDS = {"deriv_gemm": 0, "filter_gemm": 1, "radial": 2, "pointwise": 3, "boundary": 4,
@@ -78,6 +79,7 @@ def load_library(path=LIB_PATH):
         "gh_rhs_vjp": (i, [vp, vp, vp, vp, vp]),
         "gh_step_vjp": (i, [vp, vp, vp, vp, vp]),
         "gh_constraints_vjp": (i, [vp, vp, vp, vp]),
+        "gh_set_graph": (i, [vp, i]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -220,6 +222,9 @@ class GHSolver:
                                             self._dev(C, 64, "C") if want_C else None,
                                             ctypes.c_void_p(norm.data_ptr())))
         return C, norm
+
+    def set_graph(self, enable=True):
+        self._check(self.lib.gh_set_graph(self.h, 1 if enable else 0))
 
     def set_timing(self, enable=True):
         self._check(self.lib.gh_set_timing(self.h, 1 if enable else 0))

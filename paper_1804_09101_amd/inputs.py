@@ -59,12 +59,14 @@ def lorentz_boost(vel):
     return B
 
 
-def kerr_schild_metric(M, chi, axis=(0.0, 0.0, 1.0), boost=None):
+def kerr_schild_metric(M, chi, axis=(0.0, 0.0, 1.0), boost=None, device="cpu"):
     """Return g(X) -> [4,4] for a Kerr-Schild hole (optionally Lorentz-boosted)."""
     a = float(chi) * float(M)
     Lam = torch.eye(4, dtype=torch.float64)
     Lam[1:, 1:] = torch.tensor(rotation_to(axis), dtype=torch.float64)
-    B = None if boost is None else torch.tensor(lorentz_boost(boost), dtype=torch.float64)
+    Lam = Lam.to(device)
+    eta = _ETA.to(device)
+    B = None if boost is None else torch.tensor(lorentz_boost(boost), dtype=torch.float64).to(device)
 
     def g_spin_z(X):
         x, y, z = X[1], X[2], X[3]
@@ -74,7 +76,7 @@ def kerr_schild_metric(M, chi, axis=(0.0, 0.0, 1.0), boost=None):
         Hs = M * r * r2 / (r2 * r2 + a * a * z * z)
         l = torch.stack([torch.ones_like(x), (r * x + a * y) / (r2 + a * a),
                          (r * y - a * x) / (r2 + a * a), z / r])
-        return _ETA + 2.0 * Hs * torch.outer(l, l)
+        return eta + 2.0 * Hs * torch.outer(l, l)
 
     def g_rot(X):
         # psi'_ab(x) = Lam_a^c Lam_b^d psi_cd(Lam^T x)
@@ -120,9 +122,11 @@ def _first_order_fields(gfun):
     return u_of_X, H_of_X
 
 
-def exact_spacetime(xyz, gfun, t=0.0, with_derivs=False, chunk=65536):
+def exact_spacetime(xyz, gfun, t=0.0, with_derivs=False, chunk=65536, device="cpu"):
     """Fields, gauge source and (optionally) exact derivatives at points xyz [3, P].
 
+    device: where torch evaluates the exact solution ("cpu" or a CUDA device);
+    the results are returned on the host either way.
     Returns dict with numpy float64 arrays:
       u [50, P], H [4, P], dH [16, P] (row a*4+b = d_a H_b);
       with_derivs: du [3, 50, P] (spatial), dtu [50, P] (time derivative).
@@ -142,21 +146,23 @@ def exact_spacetime(xyz, gfun, t=0.0, with_derivs=False, chunk=65536):
         X = torch.empty((e - s, 4), dtype=torch.float64)
         X[:, 0] = t
         X[:, 1:] = torch.from_numpy(xyz[:, s:e].T.copy())
-        outs["u"].append(f_u(X).T.numpy())
-        outs["H"].append(f_H(X).T.numpy())
+        X = X.to(device)
+        outs["u"].append(f_u(X).T.cpu().numpy())
+        outs["H"].append(f_H(X).T.cpu().numpy())
         dH = f_dH(X)                                  # [P, b, a] = d_a H_b
-        outs["dH"].append(dH.permute(2, 1, 0).reshape(16, e - s).numpy())
+        outs["dH"].append(dH.permute(2, 1, 0).reshape(16, e - s).cpu().numpy())
         if with_derivs:
             du = f_du(X)                              # [P, 50, 4]
-            outs["du"].append(du[:, :, 1:].permute(2, 1, 0).numpy())
-            outs["dtu"].append(du[:, :, 0].T.numpy())
+            outs["du"].append(du[:, :, 1:].permute(2, 1, 0).cpu().numpy())
+            outs["dtu"].append(du[:, :, 0].T.cpu().numpy())
     res = {k: np.ascontiguousarray(np.concatenate(v, axis=-1)) for k, v in outs.items()}
     return res
 
 
-def kerr_schild(xyz, M=1.0, chi=0.0, axis=(0.0, 0.0, 1.0), with_derivs=False):
+def kerr_schild(xyz, M=1.0, chi=0.0, axis=(0.0, 0.0, 1.0), with_derivs=False, device="cpu"):
     """Stationary Kerr-Schild hole at the origin (see module docstring)."""
-    return exact_spacetime(xyz, kerr_schild_metric(M, chi, axis), with_derivs=with_derivs)
+    return exact_spacetime(xyz, kerr_schild_metric(M, chi, axis, device=device), with_derivs=with_derivs,
+                           device=device)
 
 
 def random_polarisation(seed):

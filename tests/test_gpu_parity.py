@@ -202,3 +202,18 @@ def test_error_paths():
     with pytest.raises(ghmi.GHError) as ei:
         s.set_background(dev(bad), dev(dH), dev(ubg))
     assert ei.value.code == -6                      # GH_ERR_NONFINITE
+
+
+def test_set_background_again_after_steps_mixed_L():
+    """Regression: the excision check must not read stale work space for angular
+    indices beyond a smaller-L shell (instances with different L)."""
+    shells = [(0, 7, 5, 1.8, 2.6), (0, 9, 5, 2.6, 4.0), (1, 5, 3, 1.3, 2.5), (1, 6, 3, 2.5, 3.3)]
+    holes = [(1.0, 0.0, (0, 0, 1)), (0.8, 0.6, (0.3, -0.5, 0.8))]
+    wl = _wl("mixed_L", shells, holes)
+    c = Case(wl, pert_amp=1e-2, seed=9)
+    u = dev(c.u0)
+    c.s.rhs(u)
+    c.s.step(u, 3)
+    torch.cuda.synchronize()
+    for _ in range(2):
+        c.s.set_background(dev(c.H), dev(c.dH), dev(c.ubg))
