@@ -93,10 +93,12 @@ def test_constraints_vjp_dot_product():
     assert err < 1e-12
 
 
-def test_evolve_gradient_matches_central_differences():
-    """Loss = ||C(u_n)|| after 12 RK3 steps (checkpoint every 5); gradient w.r.t.
-    the damping parameters and along the initial Pi perturbation, against central
-    differences with h = 1e-6 run through the same GPU forward path."""
+def test_evolve_gradient_matches_central_differences_and_oracle():
+    """Loss = ||C(u_n)|| after 12 RK3 steps (checkpoint every 5).  The gradient
+    with respect to (gamma0, gamma1, gamma2) and the log-amplitude of the initial
+    Pi perturbation is compared with (a) central differences, h = 1e-6, run
+    through the same GPU forward path, to 1e-6 of the gradient norm, and (b) the
+    oracle's complex-step derivatives through 12 oracle steps, to 1e-9."""
     wl, d, s, u0, ubg, H, dH = _setup([(0, 9, 5, 1.8, 4.0)], [(1.0, 0.0, (0, 0, 1))], [(1.0, -1.0, 1.0)], [0.01],
                                       None, pert=0.0)
     dpi = d.to_layout(inputs.gaussian_pulse_Pi(d.xyz(), 1.0, 2.8, 0.4, 3))
@@ -115,8 +117,7 @@ def test_evolve_gradient_matches_central_differences():
     un = gha.evolve(u_init, gamma, s, wl.dt, n, checkpoint_every=5)
     L = gha.constraint_norm(un, s).sum()
     L.backward()
-    g_adj = gamma.grad.numpy().ravel()
-    a_adj = float(a.grad.cpu())
+    g_adj = np.concatenate([gamma.grad.numpy().ravel(), [float(a.grad.cpu()) * amp]])
     h = 1e-6
     g_fd = []
     for c in range(3):
@@ -125,9 +126,25 @@ def test_evolve_gradient_matches_central_differences():
         gp[0, c] += h
         gm[0, c] -= h
         g_fd.append((loss(gp, amp) - loss(gm, amp)) / (2 * h))
-    a_fd = (loss(wl.gamma, amp + h * amp) - loss(wl.gamma, amp - h * amp)) / (2 * h * amp)
-    print(f"  dL/dgamma adjoint {g_adj}, FD {np.array(g_fd)}; dL/da adjoint {a_adj:.10e} FD {a_fd:.10e}",
-          flush=True)
-    for c in range(3):
-        assert abs(g_adj[c] - g_fd[c]) <= 1e-6 * max(abs(g_fd[c]), 1e-3 * abs(a_fd * amp)), c
-    assert abs(a_adj - a_fd) <= 1e-6 * abs(a_fd)
+    g_fd.append((loss(wl.gamma, amp * (1 + h)) - loss(wl.gamma, amp * (1 - h))) / (2 * h))
+    g_fd = np.array(g_fd)
+    # oracle reference: complex step through the oracle's own RK3 evolution
+    g_or = []
+    hc = 1e-30
+    for c in range(4):
+        gam = wl.gamma.astype(complex)
+        uc = (u0 + amp * dpi).astype(complex)
+        if c < 3:
+            gam[0, c] += 1j * hc
+        else:
+            uc = uc + 1j * hc * amp * dpi
+        for _ in range(n):
+            uc = d.rk3_step(uc, H, dH, ubg, gam, wl.dt)
+        g_or.append(d.constraint_norm(uc, H)[0].imag / hc)
+    g_or = np.array(g_or)
+    gn = np.linalg.norm(g_or)
+    print(f"  adjoint {g_adj}\n  FD      {g_fd}\n  oracle  {g_or}", flush=True)
+    print(f"  max |adj-FD|/|g| {np.max(np.abs(g_adj - g_fd)) / gn:.2e}, "
+          f"max |adj-oracle|/|g| {np.max(np.abs(g_adj - g_or)) / gn:.2e}", flush=True)
+    assert np.max(np.abs(g_adj - g_fd)) <= 1e-6 * gn
+    assert np.max(np.abs(g_adj - g_or)) <= 1e-9 * gn
