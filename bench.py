@@ -72,6 +72,7 @@ def adjoint_ratio(solver, u0_dev, wl, n_steps=200, k=20):
     """Forward time of n_steps vs time of the backward pass of the constraint norm."""
     import torch
     from paper_1804_09101_amd import autograd as gha
+    from paper_1804_09101_amd import ghmi
     gamma = torch.tensor(wl.gamma, dtype=torch.float64, requires_grad=True)
     u0 = u0_dev.clone().requires_grad_(True)
     torch.cuda.synchronize()
@@ -84,7 +85,18 @@ def adjoint_ratio(solver, u0_dev, wl, n_steps=200, k=20):
     L.backward()
     torch.cuda.synchronize()
     t_bwd = time.perf_counter() - t0
-    return {"workload": f"pulse_8shell, {n_steps} RK3 steps, loss = final constraint norm, "
+    # per-kernel split of one more backward pass (event timing adds a little overhead)
+    gamma.grad = None
+    u0.grad = None
+    un = gha.evolve(u0, gamma, solver, wl.dt, n_steps, checkpoint_every=k)
+    L = gha.constraint_norm(un, solver).sum()
+    torch.cuda.synchronize()
+    solver.set_timing(True)
+    L.backward()
+    torch.cuda.synchronize()
+    split = {kk: round(solver.kernel_stats(kk)[1], 3) for kk in ghmi.KERNEL_KINDS}
+    solver.set_timing(False)
+    return {"backward_kernel_ms": split,"workload": f"pulse_8shell, {n_steps} RK3 steps, loss = final constraint norm, "
                         f"checkpoint every {k} steps",
             "forward_ms": t_fwd * 1e3, "backward_ms": t_bwd * 1e3, "ratio": t_bwd / t_fwd,
             "grad_gamma": gamma.grad.numpy().ravel().tolist(),
@@ -145,6 +157,8 @@ def main():
     ap.add_argument("--cpu-rhs", type=int, default=3, help="oracle RHS evaluations for cpu_baseline (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward measurement")
     ap.add_argument("--batched", action="store_true", help="also run the 64-hole batched comparison")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB device copy 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the path shards by instance or by "
@@ -155,6 +169,15 @@ def main():
     import torch
     from paper_1804_09101_amd import configs, ghmi
 
+    if args.calibrate_copy:
+        n = 256 * 1024 * 1024 // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n * 8, "copies": 5}))
+        return
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)

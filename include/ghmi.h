@@ -155,6 +155,17 @@ int gh_rhs_vjp(gh_ctx* ctx, const double* u, const double* lam, double* lam_u, d
  * from u_n.  lam_n may alias lam_np1 but not u_n. */
 int gh_step_vjp(gh_ctx* ctx, const double* u_n, const double* lam_np1, double* lam_n, double* g_gamma);
 
+/* One gh_step (same arithmetic) that also stores the two SSP-RK3 stage states
+ * u1 = u + dt L(u) and u2 = 3/4 u + 1/4 (u1 + dt L(u1)) into u1, u2 (device
+ * [50], distinct from u), for a later gh_step_vjp_stages. */
+int gh_step_stages(gh_ctx* ctx, double* u, double* u1, double* u2);
+
+/* gh_step_vjp with the stage states supplied (from gh_step_stages on u_n), so
+ * they are not recomputed.  Same outputs and aliasing rules as gh_step_vjp
+ * (lam_n must also not alias u1 or u2). */
+int gh_step_vjp_stages(gh_ctx* ctx, const double* u_n, const double* u1, const double* u2,
+                       const double* lam_np1, double* lam_n, double* g_gamma);
+
 /* Transpose of the constraint norm: lam_u = sum_i lam_norm[i] d||C||_i / d u
  * at state u (lam_norm: device [n_inst]; lam_u: device [50], overwritten,
  * not aliasing u).  A zero norm contributes nothing. */

@@ -1,11 +1,12 @@
 """torch.autograd wrappers of the evolution and of the constraint norm.
 
 GHEvolve runs n SSP-RK3 steps with the HIP library and, in backward, walks the
-steps in reverse with gh_step_vjp.  It keeps a copy of the state every
-`checkpoint_every` steps during the forward pass; backward re-runs each segment
-forward from its checkpoint (storing that segment's states) and then applies
-the step transposes in reverse order.  Memory: n/k checkpoints plus k segment
-states of 50 P doubles each.
+steps in reverse.  It keeps a copy of the state every `checkpoint_every` steps
+during the forward pass; backward re-runs each segment forward from its
+checkpoint with gh_step_stages (storing every step's start state and its two
+RK stage states) and then applies gh_step_vjp_stages in reverse order, so each
+step costs one forward step plus three RHS transposes.  Memory: n/k
+checkpoints plus 3k segment states of 50 P doubles each.
 
 GHConstraintNorm returns the per-instance constraint norm of a state; its
 backward is gh_constraints_vjp.
@@ -49,14 +50,19 @@ class GHEvolve(torch.autograd.Function):
         for seg in reversed(range(len(ctx.ckpts))):
             s0 = seg * k
             s1 = min(n, s0 + k)
-            states = [ctx.ckpts[seg].clone()]
-            for _ in range(s0, s1 - 1):
+            # re-run the segment, keeping every step's start state and its two stage states
+            states, stages = [ctx.ckpts[seg].clone()], []
+            for j in range(s1 - s0):
                 nxt = states[-1].clone()
-                solver.step(nxt, 1)
-                states.append(nxt)
+                u1, u2 = torch.empty_like(nxt), torch.empty_like(nxt)
+                solver.step_stages(nxt, u1, u2)
+                stages.append((u1, u2))
+                if j < s1 - s0 - 1:
+                    states.append(nxt)
             for j in reversed(range(s1 - s0)):
-                solver.step_vjp(states[j], lam, g_gamma=g, out=lam)
-            del states
+                u1, u2 = stages[j]
+                solver.step_vjp_stages(states[j], u1, u2, lam, g_gamma=g, out=lam)
+            del states, stages
         return lam, g.view(solver.n_inst, 3).cpu(), None, None, None, None
 
 

@@ -505,4 +505,536 @@ GHP_HD void gauge_constraint_vjp(const double* u, const double* H, const double*
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Register-lean reverse pass in pair storage.  Same mathematics as rhs_vjp;
+// symmetric cotangents are kept as one value per pair ("full entry" values,
+// i.e. the cotangent of one of the two equal tensor entries), the spatial
+// inverse-metric cotangent as its symmetric part giS = gi_b + gi_b^T and the
+// psi^ab cotangent as PS = P_b + P_b^T.  The derivative cotangents are
+// produced pair by pair through `load(n, dpsi, dPi, dPhi)` (Cartesian
+// derivatives of the five fields of pair n; dPhi[k][i] = d_k Phi_i) and
+// `store(n, dpsi_b, dPi_b, dPhi_b)`, so that a kernel can stream them.
+// ---------------------------------------------------------------------------
+GHP_HD int s3(int i, int j) {
+  return i <= j ? (i * 3 - i * (i - 1) / 2 + j - i) : (j * 3 - j * (j - 1) / 2 + i - j);
+}
+GHP_HD double pmul(int a, int b) { return a == b ? 1.0 : 2.0; }
+
+template <class Load, class Store>
+GHP_HD void rhs_vjp_pairs(const double* u, const double* H, const double* dH, double g0, double g1,
+                          double g2, const double* lam, Load load, Store store, double* ubar, double* gbar) {
+  const double* psi = u;
+  const double* Pi = u + 10;
+  const double* Phi = u + 20;            // Phi_i pair n at Phi[10 i + n]
+  const double* lpsi = lam;
+  const double* lPi = lam + 10;
+  const double* lPhi = lam + 20;
+  // geometry
+  double gi[6], Nu[3], beta[3], N, tu[4], P[10];
+  {
+    const double g11 = psi[4], g12 = psi[5], g13 = psi[6], g22 = psi[7], g23 = psi[8], g33 = psi[9];
+    const double A = g22 * g33 - g23 * g23, B = g13 * g23 - g12 * g33, Cc = g12 * g23 - g13 * g22;
+    const double D = g11 * g33 - g13 * g13, E = g12 * g13 - g11 * g23, F = g11 * g22 - g12 * g12;
+    const double idet = 1.0 / (g11 * A + g12 * B + g13 * Cc);
+    gi[0] = A * idet; gi[1] = B * idet; gi[2] = Cc * idet; gi[3] = D * idet; gi[4] = E * idet; gi[5] = F * idet;
+    beta[0] = psi[1]; beta[1] = psi[2]; beta[2] = psi[3];
+    double nsq = -psi[0];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      Nu[i] = gi[s3(i, 0)] * beta[0] + gi[s3(i, 1)] * beta[1] + gi[s3(i, 2)] * beta[2];
+      nsq += Nu[i] * beta[i];
+    }
+    N = sqrt(nsq);
+    tu[0] = 1.0 / N;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) tu[i + 1] = -Nu[i] / N;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = a; b < 4; ++b)
+        P[pair(a, b)] = ((a > 0 && b > 0) ? gi[s3(a - 1, b - 1)] : 0.0) - tu[a] * tu[b];
+  }
+#pragma unroll
+  for (int f = 0; f < 50; ++f) ubar[f] = 0.0;
+  double Nu_b[3] = {0.0, 0.0, 0.0}, N_b = 0.0, giS[6] = {0, 0, 0, 0, 0, 0}, tu_b[4] = {0, 0, 0, 0};
+  double PS[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double gb0 = 0.0, gb1 = 0.0, gb2 = 0.0;
+
+  // (1) principal parts, streamed per pair
+#pragma unroll
+  for (int n = 0; n < 10; ++n) {
+    double dpsi[3], dPi[3], dPhi[3][3];
+    load(n, dpsi, dPi, dPhi);
+    const double lp = lpsi[n], lP = lPi[n];
+    const double lF[3] = {lPhi[n], lPhi[10 + n], lPhi[20 + n]};
+    double dpsi_b[3], dPi_b[3], dPhi_b[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      dpsi_b[k] = (1.0 + g1) * Nu[k] * lp + g1 * g2 * Nu[k] * lP + g2 * N * lF[k];
+      dPi_b[k] = Nu[k] * lP - N * lF[k];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) dPhi_b[k][i] = Nu[k] * lF[i] - N * gi[s3(k, i)] * lP;
+    }
+    store(n, dpsi_b, dPi_b, dPhi_b);
+    double adv = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      adv += Nu[k] * dpsi[k];
+      Nu_b[k] += lp * (1.0 + g1) * dpsi[k] + lP * (dPi[k] + g1 * g2 * dpsi[k]);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) Nu_b[k] += lF[i] * dPhi[k][i];
+    }
+    double div = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) div += gi[s3(k, i)] * dPhi[k][i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) N_b += lF[i] * (-dPi[i] + g2 * dpsi[i]);
+    N_b += -lP * div;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int i = k; i < 3; ++i)
+        giS[s3(k, i)] += -N * lP * (k == i ? 2.0 * dPhi[k][k] : dPhi[k][i] + dPhi[i][k]);
+    gb1 += lp * adv + g2 * lP * adv;
+    double dps = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dps += lF[i] * dpsi[i];
+    gb2 += N * dps + g1 * lP * adv;
+  }
+
+  // (2) algebraic part of d_t psi, and the -g1 g2 N^i Phi_i term of d_t Pi
+#pragma unroll
+  for (int n = 0; n < 10; ++n) {
+    const double NuPhi = Nu[0] * Phi[n] + Nu[1] * Phi[10 + n] + Nu[2] * Phi[20 + n];
+    N_b += -lpsi[n] * Pi[n];
+    ubar[10 + n] += -N * lpsi[n];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      ubar[20 + 10 * i + n] += -(g1 * lpsi[n] + g1 * g2 * lPi[n]) * Nu[i];
+      Nu_b[i] += -(g1 * lpsi[n] + g1 * g2 * lPi[n]) * Phi[10 * i + n];
+    }
+    gb1 += -(lpsi[n] + g2 * lPi[n]) * NuPhi;
+    gb2 += -g1 * lPi[n] * NuPhi;
+  }
+
+  // (3) algebraic part of d_t Phi: 1/2 N ttPhi_i Pi + N Gt_ik Phi_k - g2 N Phi_i
+  {
+    double ttPhi[3], tPhi[3][3], Gt[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int d = c; d < 4; ++d) s += pmul(c, d) * tu[c] * tu[d] * Phi[10 * i + pair(c, d)];
+      ttPhi[i] = s;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        double t = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) t += tu[c] * Phi[10 * i + pair(j + 1, c)];
+        tPhi[i][j] = t;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        Gt[i][k] = gi[s3(0, k)] * tPhi[i][0] + gi[s3(1, k)] * tPhi[i][1] + gi[s3(2, k)] * tPhi[i][2];
+    double ttPhi_b[3] = {0, 0, 0}, Gt_b[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int n = 0; n < 10; ++n) {
+        const double l = lPhi[10 * i + n];
+        double gtp = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          gtp += Gt[i][k] * Phi[10 * k + n];
+          Gt_b[i][k] += N * l * Phi[10 * k + n];
+          ubar[20 + 10 * k + n] += N * Gt[i][k] * l;
+        }
+        N_b += l * (0.5 * ttPhi[i] * Pi[n] + gtp - g2 * Phi[10 * i + n]);
+        gb2 += -N * l * Phi[10 * i + n];
+        ttPhi_b[i] += 0.5 * N * l * Pi[n];
+        ubar[10 + n] += 0.5 * N * l * ttPhi[i];
+        ubar[20 + 10 * i + n] += -g2 * N * l;
+      }
+    double tPhi_b[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        tPhi_b[i][j] = Gt_b[i][0] * gi[s3(j, 0)] + Gt_b[i][1] * gi[s3(j, 1)] + Gt_b[i][2] * gi[s3(j, 2)];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = j; k < 3; ++k) {
+        double c = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) c += Gt_b[i][k] * tPhi[i][j] + (k == j ? Gt_b[i][k] * tPhi[i][j] : Gt_b[i][j] * tPhi[i][k]);
+        giS[s3(j, k)] += c;
+      }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          tu_b[c] += tPhi_b[i][j] * Phi[10 * i + pair(j + 1, c)];
+          ubar[20 + 10 * i + pair(j + 1, c)] += tPhi_b[i][j] * tu[c];
+        }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) s += tu[d] * Phi[10 * i + pair(c, d)];
+        tu_b[c] += 2.0 * ttPhi_b[i] * s;
+#pragma unroll
+        for (int d = c; d < 4; ++d) ubar[20 + 10 * i + pair(c, d)] += pmul(c, d) * ttPhi_b[i] * tu[c] * tu[d];
+      }
+  }
+
+  // (4) the rest of d_t Pi: Christoffels, constraint, Q, damping
+  double G[4][10];
+  {
+    double d0[10];
+#pragma unroll
+    for (int n = 0; n < 10; ++n) d0[n] = -N * Pi[n] + Nu[0] * Phi[n] + Nu[1] * Phi[10 + n] + Nu[2] * Phi[20 + n];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = a; b < 4; ++b) {
+          const double x = (a == 0) ? d0[pair(c, b)] : Phi[10 * (a - 1) + pair(c, b)];
+          const double y = (b == 0) ? d0[pair(c, a)] : Phi[10 * (b - 1) + pair(c, a)];
+          const double z = (c == 0) ? d0[pair(a, b)] : Phi[10 * (c - 1) + pair(a, b)];
+          G[c][pair(a, b)] = 0.5 * (x + y - z);
+        }
+  }
+  double C[4], Hup[4], tC = 0.0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    double s = H[a];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int c = b; c < 4; ++c) s += pmul(b, c) * P[pair(b, c)] * G[a][pair(b, c)];
+    C[a] = s;
+    Hup[a] = P[pair(a, 0)] * H[0] + P[pair(a, 1)] * H[1] + P[pair(a, 2)] * H[2] + P[pair(a, 3)] * H[3];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) tC += tu[a] * C[a];
+  double ttPi = 0.0, w[3], v[3];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int d = c; d < 4; ++d) ttPi += pmul(c, d) * tu[c] * tu[d] * Pi[pair(c, d)];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) w[i] = tu[0] * Pi[pair(0, i + 1)] + tu[1] * Pi[pair(1, i + 1)] +
+                                    tu[2] * Pi[pair(2, i + 1)] + tu[3] * Pi[pair(3, i + 1)];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) v[j] = w[0] * gi[s3(0, j)] + w[1] * gi[s3(1, j)] + w[2] * gi[s3(2, j)];
+
+  // Q (full symmetric 4x4) for the N cotangent
+  double Qm[4][4];
+  {
+    double Pf[4][4], Pif[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) { Pf[a][b] = P[pair(a, b)]; Pif[a][b] = Pi[pair(a, b)]; }
+    double T[4][4], Mx[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) Qm[a][b] = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double Rf[4][4], Ff[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int n = pair(a, b);
+          Rf[a][b] = gi[s3(j, 0)] * Phi[n] + gi[s3(j, 1)] * Phi[10 + n] + gi[s3(j, 2)] * Phi[20 + n];
+          Ff[a][b] = Phi[10 * j + n];
+        }
+      mmm(Rf, Pf, Ff, T);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) Qm[a][b] += T[a][b];
+    }
+    mmm(Pif, Pf, Pif, T);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) Qm[a][b] -= T[a][b];
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) {
+      double Gf[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) Gf[a][b] = G[bb][pair(a, b)];
+      mmm(Pf, Gf, Pf, Mx);                 // P G_bb P
+#pragma unroll
+      for (int aa = 0; aa < 4; ++aa) {
+        double t3 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) t3 += G[aa][pair(c, e)] * Mx[c][e];
+        Qm[aa][bb] -= t3;
+      }
+    }
+  }
+  // scalar-type contributions of d_t Pi
+  double Hup_b[4] = {0, 0, 0, 0}, tC_b = 0.0, ttPi_b = 0.0, v_b[3] = {0, 0, 0}, tl_b0 = 0.0;
+  double C_b[4] = {0, 0, 0, 0};
+  double G_b[4][10];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int n = 0; n < 10; ++n) G_b[c][n] = 0.0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = a; b < 4; ++b) {
+      const int n = pair(a, b);
+      const double l = lPi[n];
+      const double hg = Hup[0] * G[0][n] + Hup[1] * G[1][n] + Hup[2] * G[2][n] + Hup[3] * G[3][n];
+      const double vphi = v[0] * Phi[n] + v[1] * Phi[10 + n] + v[2] * Phi[20 + n];
+      const double Dn = -N * ((a == 0 ? C[b] : 0.0) + (b == 0 ? C[a] : 0.0)) - psi[n] * tC;
+      N_b += l * (2.0 * Qm[a][b] - (dH[a * 4 + b] + dH[b * 4 + a]) + 2.0 * hg - 0.5 * ttPi * Pi[n] - vphi + g0 * Dn);
+      gb0 += N * l * Dn;
+      const double half = (a == b) ? 1.0 : 0.5;
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        Hup_b[d] += 2.0 * N * l * G[d][n];
+        G_b[d][n] += 2.0 * N * Hup[d] * l * half;
+      }
+      ttPi_b += -0.5 * N * l * Pi[n];
+      ubar[10 + n] += -0.5 * N * ttPi * l;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        v_b[j] += -N * l * Phi[10 * j + n];
+        ubar[20 + 10 * j + n] += -N * v[j] * l;
+      }
+      // damping D = t_a C_b + t_b C_a - psi tC with t_a = (-N, 0, 0, 0)
+      const double Db = g0 * N * l * half;     // full-entry cotangent
+      if (a == 0) { tl_b0 += 2.0 * Db * C[b] * (b == 0 ? 1.0 : 1.0); C_b[b] += 2.0 * Db * (-N); }
+      if (b == 0 && a != 0) { tl_b0 += 2.0 * Db * C[a]; C_b[a] += 2.0 * Db * (-N); }
+      ubar[n] += -tC * g0 * N * l;
+      tC_b += -g0 * N * l * psi[n];
+    }
+  N_b += -tl_b0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    tu_b[c] += tC_b * C[c];
+    C_b[c] += tC_b * tu[c];
+  }
+#pragma unroll
+  for (int d = 0; d < 4; ++d)
+#pragma unroll
+    for (int c = d; c < 4; ++c)
+      PS[pair(d, c)] += (d == c) ? 2.0 * Hup_b[d] * H[c] : Hup_b[d] * H[c] + Hup_b[c] * H[d];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double s = 0.0;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) s += tu[d] * Pi[pair(c, d)];
+    tu_b[c] += 2.0 * ttPi_b * s;
+#pragma unroll
+    for (int d = c; d < 4; ++d) ubar[10 + pair(c, d)] += pmul(c, d) * ttPi_b * tu[c] * tu[d];
+  }
+  {
+    double w_b[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) w_b[i] = v_b[0] * gi[s3(i, 0)] + v_b[1] * gi[s3(i, 1)] + v_b[2] * gi[s3(i, 2)];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = i; j < 3; ++j) giS[s3(i, j)] += v_b[j] * w[i] + v_b[i] * w[j];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        tu_b[c] += w_b[i] * Pi[pair(c, i + 1)];
+        ubar[10 + pair(c, i + 1)] += w_b[i] * tu[c];
+      }
+  }
+  // Q reverse (full matrices), Q_b full-entry = 2 N lPi (1/2 off-diagonal)
+  {
+    double Qb[4][4], Pf[4][4], Pif[4][4], T1[4][4], T2[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        Qb[a][b] = 2.0 * N * lPi[pair(a, b)] * (a == b ? 1.0 : 0.5);
+        Pf[a][b] = P[pair(a, b)];
+        Pif[a][b] = Pi[pair(a, b)];
+      }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double Rf[4][4], Ff[4][4], Rb[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int n = pair(a, b);
+          Rf[a][b] = gi[s3(j, 0)] * Phi[n] + gi[s3(j, 1)] * Phi[10 + n] + gi[s3(j, 2)] * Phi[20 + n];
+          Ff[a][b] = Phi[10 * j + n];
+        }
+      mmm(Qb, Ff, Pf, Rb);       // dQ/dR_j
+      mmm(Rf, Qb, Ff, T1);       // dQ/dP
+      mmm(Pf, Rf, Qb, T2);       // dQ/dPhi_j
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = a; b < 4; ++b) {
+          const int n = pair(a, b);
+          PS[n] += T1[a][b] + T1[b][a];
+          ubar[20 + 10 * j + n] += (a == b) ? T2[a][a] : T2[a][b] + T2[b][a];
+          const double rb = (a == b) ? Rb[a][a] : Rb[a][b] + Rb[b][a];
+#pragma unroll
+          for (int i = 0; i < 3; ++i) ubar[20 + 10 * i + n] += gi[s3(j, i)] * rb;
+        }
+      // gi_b[j][i] += <Rb, Phi_i>
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        double dot = 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) dot += Rb[a][b] * Phi[10 * i + pair(a, b)];
+        giS[s3(j, i)] += (i == j) ? 2.0 * dot : dot;
+      }
+    }
+    mmm(Qb, Pif, Pf, T1);        // X = Qb Pi P
+    mmm(Pif, Qb, Pif, T2);       // Pi Qb Pi
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = a; b < 4; ++b) {
+        const int n = pair(a, b);
+        ubar[10 + n] += -((a == b) ? 2.0 * T1[a][a] : 2.0 * (T1[a][b] + T1[b][a]));
+        PS[n] += -2.0 * T2[a][b];
+      }
+    // T3 part, cotangent -Qb
+#pragma unroll
+    for (int aa = 0; aa < 4; ++aa) {
+      double Y[4][4], Ga[4][4], Z[4][4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          double y = 0.0;
+#pragma unroll
+          for (int bb = 0; bb < 4; ++bb) y += -Qb[aa][bb] * G[bb][pair(c, e)];
+          Y[c][e] = y;
+          Ga[c][e] = G[aa][pair(c, e)];
+        }
+      double PYP[4][4];
+      mmm(Pf, Y, Pf, PYP);       // sum_b T3b[a][b] P G_b P
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int e = c; e < 4; ++e) G_b[aa][pair(c, e)] += 2.0 * PYP[c][e];
+      mmm(Ga, Pf, Y, Z);         // G_a P Y_a
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int e = c; e < 4; ++e) PS[pair(c, e)] += 2.0 * (Z[c][e] + Z[e][c]);
+    }
+  }
+  // C_a = H_a + P^bc G_abc
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int n = 0; n < 10; ++n) {
+      PS[n] += 2.0 * C_b[a] * G[a][n];
+      G_b[a][n] += C_b[a] * P[n];
+    }
+  // Gamma_cab = (d4_acb + d4_bca - d4_cab)/2: pair cotangents of d_x psi_yz
+  {
+    double d4b[4][10];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y)
+#pragma unroll
+        for (int z = y; z < 4; ++z)
+          d4b[x][pair(y, z)] = (y == z) ? G_b[y][pair(x, y)] - 0.5 * G_b[x][pair(y, y)]
+                                        : G_b[y][pair(x, z)] + G_b[z][pair(x, y)] - G_b[x][pair(y, z)];
+#pragma unroll
+    for (int n = 0; n < 10; ++n) {
+      N_b += -d4b[0][n] * Pi[n];
+      ubar[10 + n] += -N * d4b[0][n];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        Nu_b[i] += d4b[0][n] * Phi[10 * i + n];
+        ubar[20 + 10 * i + n] += Nu[i] * d4b[0][n] + d4b[i + 1][n];
+      }
+    }
+  }
+  // P^ab = g^ab - t^a t^b
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) giS[s3(i, j)] += PS[pair(i + 1, j + 1)];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    double s = 0.0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) s += PS[pair(a, b)] * tu[b];
+    tu_b[a] += -s;
+  }
+  // t^a = (1/N, -N^i/N)
+  N_b += -tu_b[0] / (N * N);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    N_b += tu_b[i + 1] * Nu[i] / (N * N);
+    Nu_b[i] += -tu_b[i + 1] / N;
+  }
+  const double nsq_b = N_b / (2.0 * N);
+  double beta_b[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    Nu_b[i] += nsq_b * beta[i];
+    beta_b[i] = nsq_b * Nu[i];
+  }
+  ubar[0] += -nsq_b;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) giS[s3(i, j)] += Nu_b[i] * beta[j] + Nu_b[j] * beta[i];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) beta_b[j] += gi[s3(0, j)] * Nu_b[0] + gi[s3(1, j)] * Nu_b[1] + gi[s3(2, j)] * Nu_b[2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) ubar[pair(0, i + 1)] += beta_b[i];
+  // g^ij = inv(g_ij): psi pair (i+1, j+1) gets -(g^-1 giS g^-1)_ij (1/2 on the diagonal)
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int l = 0; l < 3; ++l) s += gi[s3(i, k)] * giS[s3(k, l)] * gi[s3(l, j)];
+      ubar[pair(i + 1, j + 1)] += -(i == j ? 0.5 : 1.0) * s;
+    }
+  gbar[0] += gb0;
+  gbar[1] += gb1;
+  gbar[2] += gb2;
+}
+
 }  // namespace ghp

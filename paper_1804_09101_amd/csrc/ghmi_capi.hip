@@ -51,6 +51,8 @@ struct gh_ctx {
   PtBlock* d_blk = nullptr;
   int n_blk = 0;
   PtBlock* d_cblk = nullptr;   // column blocks (shell, first angular point) for the radial kernel
+  PtBlock* d_fblk = nullptr;   // point blocks covering both faces of every interface
+  int n_fblk = 0;
   int n_cblk = 0;
   int maxr = 0;                // register-array size of the column radial kernel (0: point form)
   double *d_dtab = nullptr, *d_angtab = nullptr, *d_radtab = nullptr, *d_bctab = nullptr;
@@ -162,7 +164,7 @@ void free_domain(gh_ctx* c) {
   c->d_u1 = c->d_u2 = c->d_lam3 = c->d_mu1 = c->d_mu2 = nullptr;
   c->d_gpart = c->d_bcg = nullptr;
   c->d_C = c->d_norm = nullptr;
-  c->d_sh = nullptr; c->d_blk = nullptr; c->d_cblk = nullptr;
+  c->d_sh = nullptr; c->d_blk = nullptr; c->d_cblk = nullptr; c->d_fblk = nullptr;
   c->d_dtab = c->d_angtab = c->d_radtab = c->d_bctab = nullptr;
   c->d_inst_range = nullptr; c->d_wsum = c->d_partial = nullptr;
   c->d_dR = c->d_dA = c->d_W = c->d_ua = c->d_ub = nullptr;
@@ -382,8 +384,10 @@ int queue_rhs_vjp(gh_ctx* c, const double* x, const double* mu, double* out, dou
                   double* g) {
   int rc = queue_derivs(c, x);
   if (rc) return rc;
-  HIPCHK(c, ghk::pointwise_rhs(c->d_sh, c->d_blk, c->n_blk, c->d_angtab, c->d_radtab, x, c->d_dR, c->d_dA,
-                               c->d_H, c->d_dH, c->d_gamma, c->d_W, c->stream));
+  // the transposed exchange needs the raw d_t u only on interface faces
+  if (c->n_fblk)
+    HIPCHK(c, ghk::pointwise_rhs(c->d_sh, c->d_fblk, c->n_fblk, c->d_angtab, c->d_radtab, x, c->d_dR, c->d_dA,
+                                 c->d_H, c->d_dH, c->d_gamma, c->d_W, c->stream));
   HIPCHK(c, ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 0, 1.0, mu, 0.0, nullptr, 0.0, nullptr, c->d_Lb,
                          c->stream));
   HIPCHK(c, ghk::boundary_vjp(c->d_sh, c->n_shells, c->max_S, c->d_bctab, c->d_gamma, c->d_W, c->d_Lb, c->d_bcg,
@@ -549,10 +553,21 @@ int gh_set_domain(gh_ctx* c, int n_inst, int n_shells, const gh_shell* shells, i
   }
   c->n_cblk = int(cblk.size());
   c->maxr = ghk::radial_col_maxr(max_nr);
+  std::vector<PtBlock> fblk;
+  for (int k = 0; k + 1 < n_shells; ++k) {
+    if (shells[k + 1].instance != shells[k].instance) continue;
+    int S = c->h_sh[k].S;
+    for (int a0 = 0; a0 < S; a0 += 256) {
+      fblk.push_back(PtBlock{k, (shells[k].n_r - 1) * S + a0});
+      fblk.push_back(PtBlock{k + 1, a0});
+    }
+  }
+  c->n_fblk = int(fblk.size());
 
   if ((rc = upload(c, &c->d_sh, c->h_sh))) return rc;
   if ((rc = upload(c, &c->d_blk, c->h_blk))) return rc;
   if ((rc = upload(c, &c->d_cblk, cblk))) return rc;
+  if ((rc = upload(c, &c->d_fblk, fblk))) return rc;
   if ((rc = upload(c, &c->d_dtab, dtab))) return rc;
   if ((rc = upload(c, &c->d_angtab, angtab))) return rc;
   if ((rc = upload(c, &c->d_radtab, radtab))) return rc;
@@ -809,6 +824,34 @@ int gh_rhs_vjp(gh_ctx* c, const double* u, const double* lam, double* lam_u, dou
   return queue_rhs_vjp(c, u, lam, lam_u, 1.0, 0, g_gamma);
 }
 
+// Reverse sweep of one RK3 step given its stage states u1, u2.
+int queue_step_vjp(gh_ctx* c, const double* u_n, const double* u1, const double* u2, const double* lam_np1,
+                   double* lam_n, double* g_gamma) {
+  int rc;
+  // filter: u_{n+1} = F u3, so lam3 = F^T lam_{n+1}
+  const double* lam3 = lam_np1;
+  if (c->filter_kind == 1) {
+    HIPCHK(c, ghk::gemm(c->filterT.shape, c->filterT.d_tiles, c->filterT.n_tiles, c->filterT.d_groups, lam_np1,
+                        c->d_lam3, c->stream, 3));
+    lam3 = c->d_lam3;
+  }
+  // u3 = 1/3 u + 2/3 (u2 + h L(u2))
+  if ((rc = queue_rhs_vjp(c, u2, lam3, c->d_T, 2.0 / 3.0, 1, g_gamma))) return rc;
+  HIPCHK(c, ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 1, 0.0, nullptr, 2.0 / 3.0, lam3, 2.0 / 3.0, c->d_T,
+                         c->d_mu2, c->stream));
+  // u2 = 3/4 u + 1/4 (u1 + h L(u1))
+  if ((rc = queue_rhs_vjp(c, u1, c->d_mu2, c->d_T, 0.25, 1, g_gamma))) return rc;
+  HIPCHK(c, ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 1, 0.0, nullptr, 0.25, c->d_mu2, 0.25, c->d_T,
+                         c->d_mu1, c->stream));
+  // u1 = u + h L(u)
+  if ((rc = queue_rhs_vjp(c, u_n, c->d_mu1, c->d_T, 1.0, 1, g_gamma))) return rc;
+  HIPCHK(c, ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 0, 1.0 / 3.0, lam3, 0.75, c->d_mu2, 0.0, nullptr,
+                         lam_n, c->stream));
+  HIPCHK(c, ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 1, 1.0, lam_n, 1.0, c->d_mu1, 1.0, c->d_T, lam_n,
+                         c->stream));
+  return GH_OK;
+}
+
 int gh_step_vjp(gh_ctx* c, const double* u_n, const double* lam_np1, double* lam_n, double* g_gamma) {
   int rc = check_ready(c, true);
   if (rc) return rc;
@@ -822,28 +865,45 @@ int gh_step_vjp(gh_ctx* c, const double* u_n, const double* lam_np1, double* lam
   if ((rc = queue_rhs(c, c->d_u1, c->d_W))) return rc;
   HIPCHK(c, ghk::rk_stage(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 0.75, u_n, 0.25, c->d_u1, c->d_W, c->d_u2,
                           c->stream));
-  // filter: u_{n+1} = F u3, so lam3 = F^T lam_{n+1}
-  const double* lam3 = lam_np1;
-  if (c->filter_kind == 1) {
-    HIPCHK(c, ghk::gemm(c->filterT.shape, c->filterT.d_tiles, c->filterT.n_tiles, c->filterT.d_groups, lam_np1,
-                        c->d_lam3, c->stream, 3));
-    lam3 = c->d_lam3;
+  return queue_step_vjp(c, u_n, c->d_u1, c->d_u2, lam_np1, lam_n, g_gamma);
+}
+
+int gh_step_stages(gh_ctx* c, double* u, double* u1, double* u2) {
+  int rc = check_ready(c, true);
+  if (rc) return rc;
+  if (!u || !u1 || !u2 || u1 == u || u2 == u || u1 == u2)
+    return fail(c, GH_ERR_ARG, "u, u1, u2 must be distinct device pointers");
+  HIPCHK(c, hipSetDevice(c->device));
+  const bool filt = c->filter_kind == 1;
+  auto stage = [&](double c0, const double* u0, double c1, const double* us, double* out) -> int {
+    Timed t(c, 5);
+    HIPCHK(c, ghk::rk_stage(c->d_sh, c->d_blk, c->n_blk, c->d_dt, c0, u0, c1, us, c->d_W, out, c->stream));
+    return GH_OK;
+  };
+  if ((rc = queue_rhs(c, u, c->d_W))) return rc;
+  if ((rc = stage(0.0, nullptr, 1.0, u, u1))) return rc;
+  if ((rc = queue_rhs(c, u1, c->d_W))) return rc;
+  if ((rc = stage(0.75, u, 0.25, u1, u2))) return rc;
+  if ((rc = queue_rhs(c, u2, c->d_W))) return rc;
+  double* dst = filt ? c->d_ua : u;
+  if ((rc = stage(1.0 / 3.0, u, 2.0 / 3.0, u2, dst))) return rc;
+  if (filt) {
+    Timed t(c, 1);
+    HIPCHK(c, ghk::gemm(c->filter.shape, c->filter.d_tiles, c->filter.n_tiles, c->filter.d_groups, c->d_ua, u,
+                        c->stream, 1));
   }
-  // u3 = 1/3 u + 2/3 (u2 + h L(u2))
-  if ((rc = queue_rhs_vjp(c, c->d_u2, lam3, c->d_T, 2.0 / 3.0, 1, g_gamma))) return rc;
-  HIPCHK(c, ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 1, 0.0, nullptr, 2.0 / 3.0, lam3, 2.0 / 3.0, c->d_T,
-                         c->d_mu2, c->stream));
-  // u2 = 3/4 u + 1/4 (u1 + h L(u1))
-  if ((rc = queue_rhs_vjp(c, c->d_u1, c->d_mu2, c->d_T, 0.25, 1, g_gamma))) return rc;
-  HIPCHK(c, ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 1, 0.0, nullptr, 0.25, c->d_mu2, 0.25, c->d_T,
-                         c->d_mu1, c->stream));
-  // u1 = u + h L(u)
-  if ((rc = queue_rhs_vjp(c, u_n, c->d_mu1, c->d_T, 1.0, 1, g_gamma))) return rc;
-  HIPCHK(c, ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 0, 1.0 / 3.0, lam3, 0.75, c->d_mu2, 0.0, nullptr,
-                         lam_n, c->stream));
-  HIPCHK(c, ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 1, 1.0, lam_n, 1.0, c->d_mu1, 1.0, c->d_T, lam_n,
-                         c->stream));
   return GH_OK;
+}
+
+int gh_step_vjp_stages(gh_ctx* c, const double* u_n, const double* u1, const double* u2, const double* lam_np1,
+                       double* lam_n, double* g_gamma) {
+  int rc = check_ready(c, true);
+  if (rc) return rc;
+  if (!u_n || !u1 || !u2 || !lam_np1 || !lam_n || lam_n == u_n || lam_n == u1 || lam_n == u2)
+    return fail(c, GH_ERR_ARG, "device pointers required; lam_n must not alias u_n, u1 or u2");
+  HIPCHK(c, hipSetDevice(c->device));
+  if ((rc = ensure_adjoint(c))) return rc;
+  return queue_step_vjp(c, u_n, u1, u2, lam_np1, lam_n, g_gamma);
 }
 
 int gh_constraints_vjp(gh_ctx* c, const double* u, const double* lam_norm, double* lam_u) {

@@ -738,25 +738,39 @@ __global__ __launch_bounds__(256) void k_pointwise_vjp(
     const long long ab = 100LL * s.pt_off + (long long)r * 2 * s.S + a;
     const long long astride = (long long)s.n_r * 2 * s.S;
     const Jac J = jacobian(angtab + 5LL * (s.ang_off + a), radtab[2 * (s.rad_off + r)]);
-    double uu[50], du[3][50], H[4], dH[16], lm[50], uo[50], duo[3][50];
+    double uu[50], H[4], dH[16], lm[50], uo[50];
     for (int f = 0; f < 50; ++f) {
       uu[f] = u[ub + (long long)f * P];
       lm[f] = lam[ub + (long long)f * P];
-      double d[3];
-      cart(J, dR[ub + (long long)f * P], dA[ab + (long long)f * astride], dA[ab + (long long)f * astride + s.S], d);
-      du[0][f] = d[0]; du[1][f] = d[1]; du[2][f] = d[2];
     }
     for (int c = 0; c < 4; ++c) H[c] = Hin[4LL * s.pt_off + (long long)c * P + q];
     for (int c = 0; c < 16; ++c) dH[c] = dHin[16LL * s.pt_off + (long long)c * P + q];
-    ghp::rhs_vjp(uu, du, H, dH, gamma[3 * s.instance], gamma[3 * s.instance + 1], gamma[3 * s.instance + 2],
-                 lm, uo, duo, gb);
-    for (int f = 0; f < 50; ++f) {
-      ubar[ub + (long long)f * P] = uo[f];
-      const double x = duo[0][f], y = duo[1][f], z = duo[2][f];
+    // derivatives of the five fields of pair n, streamed from dR / dA
+    auto load = [&](int n, double* dpsi, double* dPi, double (*dPhi)[3]) {
+      cart(J, dR[ub + (long long)n * P], dA[ab + (long long)n * astride], dA[ab + (long long)n * astride + s.S], dpsi);
+      const int fp = 10 + n;
+      cart(J, dR[ub + (long long)fp * P], dA[ab + (long long)fp * astride], dA[ab + (long long)fp * astride + s.S], dPi);
+      for (int i = 0; i < 3; ++i) {
+        const int ff = 20 + 10 * i + n;
+        double d[3];
+        cart(J, dR[ub + (long long)ff * P], dA[ab + (long long)ff * astride], dA[ab + (long long)ff * astride + s.S], d);
+        dPhi[0][i] = d[0]; dPhi[1][i] = d[1]; dPhi[2][i] = d[2];
+      }
+    };
+    // Cartesian cotangents -> spherical cotangents (transpose of the Jacobian)
+    auto put = [&](int f, double x, double y, double z) {
       dRb[ub + (long long)f * P] = J.xr * x + J.yr * y + J.zr * z;
       dAb[ab + (long long)f * astride] = J.xt * x + J.yt * y + J.zt * z;
       dAb[ab + (long long)f * astride + s.S] = J.xp * x + J.yp * y;
-    }
+    };
+    auto store = [&](int n, const double* dpsi_b, const double* dPi_b, const double (*dPhi_b)[3]) {
+      put(n, dpsi_b[0], dpsi_b[1], dpsi_b[2]);
+      put(10 + n, dPi_b[0], dPi_b[1], dPi_b[2]);
+      for (int i = 0; i < 3; ++i) put(20 + 10 * i + n, dPhi_b[0][i], dPhi_b[1][i], dPhi_b[2][i]);
+    };
+    ghp::rhs_vjp_pairs(uu, H, dH, gamma[3 * s.instance], gamma[3 * s.instance + 1], gamma[3 * s.instance + 2], lm,
+                       load, store, uo, gb);
+    for (int f = 0; f < 50; ++f) ubar[ub + (long long)f * P] = uo[f];
   }
   for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = gb[c];
   __syncthreads();

@@ -25,7 +25,7 @@ EXPORTS = [
     "gh_set_background", "gh_set_params", "gh_rhs", "gh_step", "gh_constraints",
     "gh_last_error", "gh_grid_coords", "gh_host_operator", "gh_set_timing", "gh_kernel_stats",
     "gh_query", "gh_rhs_vjp", "gh_step_vjp", "gh_constraints_vjp",
-    "gh_set_graph",
+    "gh_set_graph", "gh_step_stages", "gh_step_vjp_stages",
 ]
 
 KERNEL_KINDS = {"deriv_gemm": 0, "filter_gemm": 1, "radial": 2, "pointwise": 3, "boundary": 4,
@@ -80,6 +80,8 @@ def load_library(path=LIB_PATH):
         "gh_step_vjp": (i, [vp, vp, vp, vp, vp]),
         "gh_constraints_vjp": (i, [vp, vp, vp, vp]),
         "gh_set_graph": (i, [vp, i]),
+        "gh_step_stages": (i, [vp, vp, vp, vp]),
+        "gh_step_vjp_stages": (i, [vp, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -252,6 +254,23 @@ class GHSolver:
         g = ctypes.c_void_p(g_gamma.data_ptr()) if g_gamma is not None else None
         self._check(self.lib.gh_step_vjp(self.h, self._dev(u_n, 50, "u_n"), self._dev(lam_np1, 50, "lam_np1"),
                                          self._dev(out, 50, "lam_n"), g))
+        return out
+
+    def step_stages(self, u, u1, u2):
+        """One step in place on u, storing the stage states into u1, u2."""
+        self._sync_stream()
+        self._check(self.lib.gh_step_stages(self.h, self._dev(u, 50, "u"), self._dev(u1, 50, "u1"),
+                                            self._dev(u2, 50, "u2")))
+        return u
+
+    def step_vjp_stages(self, u_n, u1, u2, lam_np1, g_gamma=None, out=None):
+        """step_vjp with the stage states given (from step_stages)."""
+        out = self.new_field() if out is None else out
+        self._sync_stream()
+        g = ctypes.c_void_p(g_gamma.data_ptr()) if g_gamma is not None else None
+        self._check(self.lib.gh_step_vjp_stages(self.h, self._dev(u_n, 50, "u_n"), self._dev(u1, 50, "u1"),
+                                                self._dev(u2, 50, "u2"), self._dev(lam_np1, 50, "lam_np1"),
+                                                self._dev(out, 50, "lam_n"), g))
         return out
 
     def constraints_vjp(self, u, lam_norm, out=None):

@@ -95,3 +95,23 @@ def test_gauge_constraint_vjp_matches_complex_step(harness):
                                      _ptr(np.ascontiguousarray(cbar.T)), _ptr(ub))
     rhs = np.sum(ub.T * vu)
     assert abs(lhs - rhs) < 1e-13 * (np.sum(np.abs(cbar * C.imag / h)) + abs(lhs))
+
+
+@pytest.mark.parametrize("seed,gam", [(3, (1.0, -1.0, 1.0)), (4, (0.3, 0.7, 1.6)), (5, (2.0, 0.0, -0.5))])
+def test_pair_form_vjp_equals_full_tensor_vjp(harness, seed, gam):
+    """The register-lean pair-storage reverse pass gives the full-tensor one to rounding."""
+    u, du, H, dH = _state(seed)
+    n = u.shape[1]
+    lam = np.random.default_rng(200 + seed).standard_normal((50, n))
+    args = [np.ascontiguousarray(a) for a in (u.T, np.transpose(du, (2, 0, 1)), H.T, dH.T)]
+    g = np.array(gam, dtype=float)
+    LAM = np.ascontiguousarray(lam.T)
+    out = []
+    for fn in (harness.ghp_rhs_vjp, harness.ghp_rhs_vjp_pairs):
+        ub = np.zeros((n, 50))
+        dub = np.zeros((n, 3, 50))
+        gb = np.zeros(3)
+        fn(n, *[_ptr(a) for a in args], _ptr(g), _ptr(LAM), _ptr(ub), _ptr(dub), _ptr(gb))
+        out.append((ub, dub, gb))
+    for a, b in zip(out[0], out[1]):
+        assert np.max(np.abs(a - b)) <= 1e-13 * max(1.0, np.max(np.abs(a))), np.max(np.abs(a - b))

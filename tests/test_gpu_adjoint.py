@@ -148,3 +148,22 @@ def test_evolve_gradient_matches_central_differences_and_oracle():
           f"max |adj-oracle|/|g| {np.max(np.abs(g_adj - g_or)) / gn:.2e}", flush=True)
     assert np.max(np.abs(g_adj - g_fd)) <= 1e-6 * gn
     assert np.max(np.abs(g_adj - g_or)) <= 1e-9 * gn
+
+
+def test_stage_saving_step_and_vjp_match_plain_ones():
+    """gh_step_stages == gh_step and gh_step_vjp_stages == gh_step_vjp, bitwise."""
+    rs = configs.geometric_radii(1.8, 9.0, 2)
+    shells = [(0, 9, 7, rs[0], rs[1]), (0, 9, 7, rs[1], rs[2])]
+    wl, d, s, u0, ubg, H, dH = _setup(shells, [(1.0, 0.4, (0.1, 0.2, 1.0))], [(0.9, -0.2, 1.1)], [0.005],
+                                      configs.FILTER_DEFAULT)
+    lam = dev(np.random.default_rng(4).standard_normal(u0.shape))
+    a, b = dev(u0), dev(u0)
+    u1, u2 = torch.empty_like(a), torch.empty_like(a)
+    s.step(a, 1)
+    s.step_stages(b, u1, u2)
+    assert torch.equal(a, b)
+    g1 = torch.zeros(3, dtype=torch.float64, device="cuda:0")
+    g2 = torch.zeros(3, dtype=torch.float64, device="cuda:0")
+    l1 = s.step_vjp(dev(u0), lam, g_gamma=g1)
+    l2 = s.step_vjp_stages(dev(u0), u1, u2, lam, g_gamma=g2)
+    assert torch.equal(l1, l2) and torch.equal(g1, g2)
