@@ -166,67 +166,55 @@ std::vector<double> exp_filter_sigma(int L, double eta_c, double alpha, double o
   return sig;
 }
 
-// Tables of the real Y_lm and their derivatives at all S nodes.
-// mode index = l*l + l + m; returns Y, dY/dtheta, dY/dphi as [(L+1)^2][S].
-static void ylm_node_tables(int L, std::vector<double>& Y, std::vector<double>& Yt,
-                            std::vector<double>& Yp, std::vector<double>& W) {
+std::vector<double> sphere_operator(int L, int which, const std::vector<double>& sigma) {
+  // M = Syn * Ana with Ana[lm][a] = W_a Y_lm(a).  For a fixed order m the two real
+  // harmonics of that order combine into a function of the azimuth difference:
+  //   sum_{+-m} Y_lm(j) Y_lm(a) = c_m P_l^m(x_j) P_l^m(x_a) cos(m (phi_j - phi_a)),
+  // c_0 = 1, c_m = 2 (normalised P_l^m as in legendre_normalised), so
+  //   d/dtheta:  M[j][a] = W_a sum_m c_m Kd_m(i_j, i_a) cos(m dphi)
+  //   d/dphi:    M[j][a] = -W_a sum_m c_m m K_m(i_j, i_a) sin(m dphi)
+  //   filter:    M[j][a] = W_a sum_m c_m Ks_m(i_j, i_a) cos(m dphi)
+  // with theta kernels K_m = sum_l P_l^m P_l^m, Kd_m = sum_l dP_l^m/dtheta P_l^m and
+  // Ks_m = sum_l sigma_l P_l^m P_l^m.  Cost S^2 (L+1) instead of S^2 (L+1)^2.
   std::vector<double> x, w;
   gauss_legendre(L, x, w);
-  int nth = L + 1, nph = 2 * (L + 1), S = nth * nph, nm = (L + 1) * (L + 1), n = L + 1;
-  Y.assign(size_t(nm) * S, 0.0);
-  Yt.assign(size_t(nm) * S, 0.0);
-  Yp.assign(size_t(nm) * S, 0.0);
-  W.assign(S, 0.0);
-  const double r2 = std::sqrt(2.0);
-  std::vector<double> P, dP;
-  for (int i = 0; i < nth; ++i) {
-    legendre_normalised(L, x[i], P, dP);
-    for (int k = 0; k < nph; ++k) {
-      int a = i * nph + k;
-      double ph = 2.0 * kPi * k / nph;
-      W[a] = w[i] * 2.0 * kPi / nph;
-      for (int l = 0; l <= L; ++l) {
-        Y[size_t(l * l + l) * S + a] = P[size_t(l) * n + 0];
-        Yt[size_t(l * l + l) * S + a] = dP[size_t(l) * n + 0];
-        for (int m = 1; m <= l; ++m) {
-          double c = std::cos(m * ph), sn = std::sin(m * ph);
-          double p = r2 * P[size_t(l) * n + m], dp = r2 * dP[size_t(l) * n + m];
-          size_t ip = size_t(l * l + l + m) * S + a, im = size_t(l * l + l - m) * S + a;
-          Y[ip] = p * c;
-          Y[im] = p * sn;
-          Yt[ip] = dp * c;
-          Yt[im] = dp * sn;
-          Yp[ip] = -m * p * sn;
-          Yp[im] = m * p * c;
+  const int nth = L + 1, nph = 2 * (L + 1), S = nth * nph, n = L + 1;
+  std::vector<std::vector<double>> P(nth), dP(nth);
+  for (int i = 0; i < nth; ++i) legendre_normalised(L, x[i], P[i], dP[i]);
+  // kernels [m][i][i']
+  std::vector<double> K(size_t(n) * nth * nth, 0.0);
+  for (int m = 0; m <= L; ++m)
+    for (int i = 0; i < nth; ++i)
+      for (int ip = 0; ip < nth; ++ip) {
+        double acc = 0.0;
+        for (int l = m; l <= L; ++l) {
+          const double left = (which == 0) ? dP[i][size_t(l) * n + m] : P[i][size_t(l) * n + m];
+          const double f = (which == 2) ? sigma[l] : 1.0;
+          acc += f * left * P[ip][size_t(l) * n + m];
+        }
+        K[(size_t(m) * nth + i) * nth + ip] = acc * (m == 0 ? 1.0 : 2.0) * (which == 1 ? -double(m) : 1.0);
+      }
+  // azimuthal factors for every difference d = k - k' (mod nph)
+  std::vector<double> trig(size_t(n) * nph);
+  for (int m = 0; m <= L; ++m)
+    for (int d = 0; d < nph; ++d) {
+      const double ang = 2.0 * kPi * double((m * d) % nph) / nph;
+      trig[size_t(m) * nph + d] = (which == 1) ? std::sin(ang) : std::cos(ang);
+    }
+  std::vector<double> M(size_t(S) * S, 0.0);
+  for (int ij = 0; ij < nth; ++ij)
+    for (int kj = 0; kj < nph; ++kj) {
+      double* row = &M[size_t(ij * nph + kj) * S];
+      for (int ia = 0; ia < nth; ++ia) {
+        const double wa = w[ia] * 2.0 * kPi / nph;
+        for (int ka = 0; ka < nph; ++ka) {
+          const int d = ((kj - ka) % nph + nph) % nph;
+          double acc = 0.0;
+          for (int m = 0; m <= L; ++m) acc += K[(size_t(m) * nth + ij) * nth + ia] * trig[size_t(m) * nph + d];
+          row[ia * nph + ka] = wa * acc;
         }
       }
     }
-  }
-}
-
-std::vector<double> sphere_operator(int L, int which, const std::vector<double>& sigma) {
-  std::vector<double> Y, Yt, Yp, W;
-  ylm_node_tables(L, Y, Yt, Yp, W);
-  int S = 2 * (L + 1) * (L + 1), nm = (L + 1) * (L + 1);
-  const std::vector<double>& Syn = (which == 0) ? Yt : (which == 1) ? Yp : Y;
-  // Ana[lm][a] = W_a Y_lm(a), scaled by sigma_l for the filter
-  std::vector<double> Ana(size_t(nm) * S);
-  for (int l = 0; l <= L; ++l)
-    for (int m = -l; m <= l; ++m) {
-      int lm = l * l + l + m;
-      double f = (which == 2) ? sigma[l] : 1.0;
-      for (int a = 0; a < S; ++a) Ana[size_t(lm) * S + a] = f * W[a] * Y[size_t(lm) * S + a];
-    }
-  std::vector<double> M(size_t(S) * S, 0.0);
-  for (int j = 0; j < S; ++j) {
-    double* row = &M[size_t(j) * S];
-    for (int lm = 0; lm < nm; ++lm) {
-      double c = Syn[size_t(lm) * S + j];
-      if (c == 0.0) continue;
-      const double* ar = &Ana[size_t(lm) * S];
-      for (int a = 0; a < S; ++a) row[a] += c * ar[a];
-    }
-  }
   return M;
 }
 

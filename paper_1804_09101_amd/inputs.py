@@ -185,24 +185,37 @@ def gaussian_pulse_Pi(xyz, amp, r0, width, seed):
     return du
 
 
-def smooth_random_field(xyz, amp, seed, degree, kappa_max, ncomp=50):
+def smooth_random_field(xyz, amp, seed, degree, kappa_max, ncomp=50, chunk=65536):
     """Seeded smooth random perturbation of every component, [ncomp, P].
 
-    Each component is amp * p(n) * cos(kappa ln r + phase) / norm, with p a
-    random polynomial of total degree <= `degree` in the unit radial vector n
-    (so it is band-limited on every sphere) and kappa uniform in [0, kappa_max].
+    Each component is amp * p(n) * cos(kappa ln r + phase), with p a random
+    polynomial of total degree <= `degree` in the unit radial vector n (so it
+    is band-limited on every sphere) with N(0,1)/sqrt(#monomials) coefficients
+    and kappa uniform in [0, kappa_max].  Draw order per component: the
+    coefficients, then kappa, then the phase.
     """
     xyz = np.asarray(xyz, dtype=float)
     rng = np.random.default_rng(seed)
-    r = np.sqrt(np.sum(xyz * xyz, axis=0))
-    n = xyz / r
     monos = [(i, j, k) for i in range(degree + 1) for j in range(degree + 1 - i)
              for k in range(degree + 1 - i - j)]
-    out = np.zeros((ncomp, xyz.shape[1]))
+    coef = np.zeros((ncomp, len(monos)))
+    kap = np.zeros(ncomp)
+    ph = np.zeros(ncomp)
     for c in range(ncomp):
-        coef = rng.standard_normal(len(monos)) / math.sqrt(len(monos))
-        p = sum(cf * n[0] ** i * n[1] ** j * n[2] ** k for cf, (i, j, k) in zip(coef, monos))
-        kap = rng.uniform(0.0, kappa_max)
-        ph = rng.uniform(0.0, 2 * math.pi)
-        out[c] = amp * p * np.cos(kap * np.log(r) + ph)
+        coef[c] = rng.standard_normal(len(monos)) / math.sqrt(len(monos))
+        kap[c] = rng.uniform(0.0, kappa_max)
+        ph[c] = rng.uniform(0.0, 2 * math.pi)
+    P = xyz.shape[1]
+    out = np.zeros((ncomp, P))
+    for s0 in range(0, P, chunk):
+        e = min(P, s0 + chunk)
+        x = xyz[:, s0:e]
+        r = np.sqrt(np.sum(x * x, axis=0))
+        n = x / r
+        pw = [[np.ones_like(r)] for _ in range(3)]
+        for a in range(3):
+            for _ in range(degree):
+                pw[a].append(pw[a][-1] * n[a])
+        table = np.stack([pw[0][i] * pw[1][j] * pw[2][k] for (i, j, k) in monos])   # [monos, pts]
+        out[:, s0:e] = amp * (coef @ table) * np.cos(np.outer(kap, np.log(r)) + ph[:, None])
     return out
