@@ -33,20 +33,6 @@ MI355X_FP64_PEAK_TFLOPS = 78.6
 MI355X_HBM_PEAK_GBS = 8000.0
 
 
-def deriv_gemm_flops(shells):
-    """Algorithmic flops of one angular derivative GEMM launch over the domain.
-
-    Per shell: C[50 n_r x 2S] = U[50 n_r x S] B[S x 2S], 2 * 50 n_r * 2S * S flops
-    (the paper's angular transform count N_e N_r S (2S - 1) per direction,
-    section "Spectral Operations", counted as 2 flops per multiply-add).
-    """
-    f = 0
-    for (_, n_r, L, _, _) in shells:
-        S = 2 * (L + 1) ** 2
-        f += 2 * 50 * n_r * 2 * S * S
-    return f
-
-
 def cpu_baseline(wl, n_rhs):
     """Time the CPU oracle on n_rhs RHS evaluations of the same workload."""
     from oracle import domain
@@ -167,7 +153,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1804_09101_amd import configs, ghmi
+    from paper_1804_09101_amd import configs, costs, ghmi
 
     if args.calibrate_copy:
         n = 256 * 1024 * 1024 // 8
@@ -219,7 +205,7 @@ def main():
     solver.set_graph(False)
     n_g, ms_g = stats["deriv_gemm"]
     avg_s = ms_g / n_g / 1e3
-    flops = deriv_gemm_flops(wl.shells)
+    flops = costs.angular_gemm_flops(wl.shells)
     achieved = flops / avg_s / 1e12
     kernels = {k: {"launches": n, "avg_us": (ms / n * 1e3 if n else None),
                    "share": ms / (t * 1e3)} for k, (n, ms) in stats.items()}
@@ -243,6 +229,8 @@ def main():
                      "achieved": achieved, "peak": MI355X_FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / MI355X_FP64_PEAK_TFLOPS, "traffic": None,
                      "flops_per_launch": flops, "avg_launch_us": avg_s * 1e6},
+        "paper_model": dict(costs.domain_model(wl.shells), note="the paper's dense shell differentiator "
+                            "count for one derivative pass of 50 fields (unfused, minimum M and F)"),
         "kernels": kernels,
         "gemm_tiles": {"deriv": solver.query(0), "filter": solver.query(1), "deriv_tiles": solver.query(2)},
         "graph_value": P * 3 * args.steps / t_graph,
