@@ -131,7 +131,7 @@ def ylm_tables(L):
                 dT[lm_index(l, 0)] = (nrm * dPlm)[:, None] * np.ones_like(phi)[None, :]
                 dP[lm_index(l, 0)] = 0.0
             else:
-                c, sn = np.cos(m * phi), np.sin(m * phi)
+                c, sn = _grid.azimuthal_factors(L, m)
                 f = math.sqrt(2.0) * nrm
                 Y[lm_index(l, m)] = f * np.outer(Plm, c)
                 Y[lm_index(l, -m)] = f * np.outer(Plm, sn)

@@ -160,3 +160,27 @@ def test_volume_weights_give_shell_volume():
         g = grid.ShellGrid(n_r, L, a, b)
         vol = np.sum(g.volume_weights())
         assert abs(vol - 4.0 * math.pi / 3.0 * (b ** 3 - a ** 3)) < 1e-12 * vol
+
+
+@pytest.mark.parametrize("L", [0, 1, 4, 15, 31, 63])
+def test_gauss_legendre_rule_is_exact_to_degree_2L_plus_1(L):
+    """Closed forms: int_{-1}^{1} x^k dx = 2/(k+1) (k even), 0 (k odd), and the
+    nodes are the roots of P_{L+1}, which numpy's leggauss also returns."""
+    x, w = grid.gauss_legendre(L)
+    assert np.all(np.diff(x) > 0)
+    for k in range(2 * L + 2):
+        want = 2.0 / (k + 1) if k % 2 == 0 else 0.0
+        assert abs(np.sum(w * x ** k) - want) < 4e-16 * (L + 1)
+    xn, wn = np.polynomial.legendre.leggauss(L + 1)
+    assert np.max(np.abs(x - xn)) < 1e-14 and np.max(np.abs(w - wn)) < 1e-13
+
+
+@pytest.mark.parametrize("L", [15, 31])
+def test_angular_derivatives_of_a_constant_vanish_to_rounding(L):
+    """d/dtheta and d/dphi of a constant are zero; the transforms must give
+    zero to a few ulps of the derivative tables (not the 1e-12 that a
+    1e-15 quadrature-weight error or cos(m phi) of a rounded product give)."""
+    sph = spectral.Sphere(L)
+    one = np.ones((sph.nth, sph.nph))
+    assert np.max(np.abs(sph.d_dtheta(one))) < 2e-13
+    assert np.max(np.abs(sph.d_dphi(one))) < 2e-13
