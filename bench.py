@@ -232,7 +232,8 @@ def main():
         "paper_model": dict(costs.domain_model(wl.shells), note="the paper's dense shell differentiator "
                             "count for one derivative pass of 50 fields (unfused, minimum M and F)"),
         "kernels": kernels,
-        "gemm_tiles": {"deriv": solver.query(0), "filter": solver.query(1), "deriv_tiles": solver.query(2)},
+        "gemm_tiles": {"deriv": solver.query(0), "filter": solver.query(1), "deriv_tiles": solver.query(2),
+                       "deriv_order": solver.query(4), "filter_order": solver.query(5)},
         "graph_value": P * 3 * args.steps / t_graph,
     }
     if not args.no_adjoint:

@@ -177,7 +177,8 @@ int gh_constraints_vjp(gh_ctx* ctx, const double* u, const double* lam_norm, dou
  * and their summed duration in milliseconds since timing was enabled or last
  * queried, and clears that kind's record.
  * kind 0: angular derivative GEMM; 1: filter GEMM; 2: radial derivative;
- *      3: pointwise GH RHS; 4: boundary; 5: RK3 stage update;
+ *      3: pointwise GH RHS; 4: boundary treatment (in gh_step together with
+ *      the RK3 stage update); 5: RK3 stage combinations of the reverse pass;
  *      6: pointwise reverse pass; 7: transposed angular derivative GEMM. */
 #define GH_NUM_KERNEL_KINDS 8
 int gh_set_timing(gh_ctx* ctx, int enable);
@@ -186,7 +187,9 @@ int gh_kernel_stats(gh_ctx* ctx, int kind, long long* launches, double* total_ms
 /* Facts about the configured context: what 0: tile shape of the angular
  * derivative GEMM chosen by the autotuner, as BM*1000 + BN; 1: the same for the
  * filter GEMM (0 without filter); 2: number of tiles of one derivative GEMM
- * launch; 3: total collocation points. */
+ * launch; 3: total collocation points; 4: tile order of the derivative GEMM
+ * (0: each XCD takes whole column blocks, 1: whole row blocks); 5: the same
+ * for the filter GEMM. */
 int gh_query(const gh_ctx* ctx, int what, long long* value);
 
 /* Message of the last error on this context (never NULL). */

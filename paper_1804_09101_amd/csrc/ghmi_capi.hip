@@ -21,6 +21,7 @@ namespace {
 // shells sharing an angular operator, cut into tiles of one tile shape.
 struct GemmPlan {
   int shape = 0;
+  int order = 0;                          // tile order, see build_tiles
   std::vector<GemmGroup> groups;          // host copy (operator pointers resolved)
   GemmGroup* d_groups = nullptr;
   GemmTile* d_tiles = nullptr;
@@ -125,6 +126,14 @@ struct Timed {
   }
 };
 
+// The reverse pass's stage combinations, timed as kind 5 (the forward stage
+// update is timed with the boundary treatment it includes, kind 4).
+#define LINCOMB(expr)          \
+  do {                         \
+    Timed t_(c, 5);            \
+    HIPCHK(c, expr);           \
+  } while (0)
+
 void clear_timing(gh_ctx* c) {
   for (auto& r : c->recs) {
     (void)hipEventDestroy(r.a);
@@ -198,16 +207,27 @@ int upload(gh_ctx* c, T** p, const std::vector<T>& h) {
 // Order tiles so that, with workgroups dispatched round-robin over the 8 XCDs,
 // all tiles of one n-column block land on one XCD (its L2 then holds that
 // slice of the operator while the field rows stream past).
-std::vector<GemmTile> build_tiles(const std::vector<GemmGroup>& groups, int shape) {
+// Tile list of one grouped GEMM launch.  Workgroups are dispatched
+// round-robin over the 8 XCDs, so list position p runs on XCD p % 8; the list
+// interleaves 8 per-XCD sequences.  order 0: each XCD takes whole n-column
+// blocks (its slice of the operator stays in its L2 while the field rows
+// stream past); order 1: each XCD takes whole row blocks (the field rows are
+// fetched once, every XCD reads the operator).
+std::vector<GemmTile> build_tiles(const std::vector<GemmGroup>& groups, int shape, int order) {
   int bm, bn;
   ghk::tile_dims(shape, &bm, &bn);
   const int NX = 8;
   std::vector<std::vector<GemmTile>> per(NX);
-  int col_block = 0;
+  int block = 0;
   for (size_t g = 0; g < groups.size(); ++g) {
     int mt = (groups[g].M + bm - 1) / bm, nt = (groups[g].N + bn - 1) / bn;
-    for (int j = 0; j < nt; ++j, ++col_block)
-      for (int i = 0; i < mt; ++i) per[col_block % NX].push_back(GemmTile{int(g), i * bm, j * bn, 0});
+    if (order == 0) {
+      for (int j = 0; j < nt; ++j, ++block)
+        for (int i = 0; i < mt; ++i) per[block % NX].push_back(GemmTile{int(g), i * bm, j * bn, 0});
+    } else {
+      for (int i = 0; i < mt; ++i, ++block)
+        for (int j = 0; j < nt; ++j) per[block % NX].push_back(GemmTile{int(g), i * bm, j * bn, 0});
+    }
   }
   std::vector<GemmTile> out;
   size_t longest = 0;
@@ -218,9 +238,10 @@ std::vector<GemmTile> build_tiles(const std::vector<GemmGroup>& groups, int shap
   return out;
 }
 
-int plan_upload(gh_ctx* c, GemmPlan& pl, int shape) {
-  std::vector<GemmTile> tiles = build_tiles(pl.groups, shape);
+int plan_upload(gh_ctx* c, GemmPlan& pl, int shape, int order) {
+  std::vector<GemmTile> tiles = build_tiles(pl.groups, shape, order);
   pl.shape = shape;
+  pl.order = order;
   pl.n_tiles = int(tiles.size());
   int rc;
   if (!pl.d_groups) {
@@ -230,29 +251,36 @@ int plan_upload(gh_ctx* c, GemmPlan& pl, int shape) {
   return GH_OK;
 }
 
-// Time every tile shape on the plan (A = src, C = dst work space) and keep the fastest.
+// Time every (tile shape, tile order) on the plan (A = src, C = dst work
+// space) and keep the fastest.
 int autotune(gh_ctx* c, GemmPlan& pl, const double* src, double* dst, int role) {
   float best = 1e30f;
-  int best_shape = 0;
+  int best_shape = 0, best_order = 0;
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
   for (int sh = 0; sh < ghk::NUM_TILE_SHAPES; ++sh) {
-    int rc = plan_upload(c, pl, sh);
-    if (rc) return rc;
-    HIPCHK(c, ghk::gemm(sh, pl.d_tiles, pl.n_tiles, pl.d_groups, src, dst, c->stream, role));
-    HIPCHK(c, hipEventRecord(e0, c->stream));
-    for (int it = 0; it < 5; ++it)
+    for (int order = 0; order < 2; ++order) {
+      int rc = plan_upload(c, pl, sh, order);
+      if (rc) return rc;
       HIPCHK(c, ghk::gemm(sh, pl.d_tiles, pl.n_tiles, pl.d_groups, src, dst, c->stream, role));
-    HIPCHK(c, hipEventRecord(e1, c->stream));
-    HIPCHK(c, hipEventSynchronize(e1));
-    float ms = 0;
-    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best) { best = ms; best_shape = sh; }
+      HIPCHK(c, hipEventRecord(e0, c->stream));
+      for (int it = 0; it < 5; ++it)
+        HIPCHK(c, ghk::gemm(sh, pl.d_tiles, pl.n_tiles, pl.d_groups, src, dst, c->stream, role));
+      HIPCHK(c, hipEventRecord(e1, c->stream));
+      HIPCHK(c, hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        best_shape = sh;
+        best_order = order;
+      }
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  return plan_upload(c, pl, best_shape);
+  return plan_upload(c, pl, best_shape, best_order);
 }
 
 int check_ready(gh_ctx* c, bool need_dt) {
@@ -326,22 +354,32 @@ int queue_rhs(gh_ctx* c, const double* u, double* out) {
   return GH_OK;
 }
 
-// One SSP-RK3 step (three RHS, three stage updates, filter) in place on u.
+// One SSP-RK3 stage: out = c0 u0 + c1 (us + dt L(us)).  The raw d_t u goes to
+// the work space; the stage kernel applies the boundary treatment on the fly.
+int queue_stage(gh_ctx* c, double c0, const double* u0, double c1, const double* us, double* out) {
+  int rc = queue_derivs(c, us);
+  if (rc) return rc;
+  {
+    Timed t(c, 3);
+    HIPCHK(c, ghk::pointwise_rhs(c->d_sh, c->d_blk, c->n_blk, c->d_angtab, c->d_radtab, us, c->d_dR, c->d_dA,
+                                 c->d_H, c->d_dH, c->d_gamma, c->d_W, c->stream));
+  }
+  {
+    Timed t(c, 4);
+    HIPCHK(c, ghk::stage_bc(c->d_sh, c->d_blk, c->n_blk, c->d_bctab, c->d_gamma, c->d_dt, c0, u0, c1, us, c->d_W,
+                            out, c->stream));
+  }
+  return GH_OK;
+}
+
+// One SSP-RK3 step (three stages, then the filter) in place on u.
 int queue_step(gh_ctx* c, double* u) {
   int rc;
   const bool filt = c->filter_kind == 1;
-  auto stage = [&](double c0, const double* u0, double c1, const double* us, double* out) -> int {
-    Timed t(c, 5);
-    HIPCHK(c, ghk::rk_stage(c->d_sh, c->d_blk, c->n_blk, c->d_dt, c0, u0, c1, us, c->d_W, out, c->stream));
-    return GH_OK;
-  };
-  if ((rc = queue_rhs(c, u, c->d_W))) return rc;
-  if ((rc = stage(0.0, nullptr, 1.0, u, c->d_ua))) return rc;
-  if ((rc = queue_rhs(c, c->d_ua, c->d_W))) return rc;
-  if ((rc = stage(0.75, u, 0.25, c->d_ua, c->d_ub))) return rc;
-  if ((rc = queue_rhs(c, c->d_ub, c->d_W))) return rc;
+  if ((rc = queue_stage(c, 0.0, nullptr, 1.0, u, c->d_ua))) return rc;
+  if ((rc = queue_stage(c, 0.75, u, 0.25, c->d_ua, c->d_ub))) return rc;
   double* dst = filt ? c->d_ua : u;
-  if ((rc = stage(1.0 / 3.0, u, 2.0 / 3.0, c->d_ub, dst))) return rc;
+  if ((rc = queue_stage(c, 1.0 / 3.0, u, 2.0 / 3.0, c->d_ub, dst))) return rc;
   if (filt) {
     Timed t(c, 1);
     HIPCHK(c, ghk::gemm(c->filter.shape, c->filter.d_tiles, c->filter.n_tiles, c->filter.d_groups, c->d_ua, u,
@@ -388,7 +426,7 @@ int queue_rhs_vjp(gh_ctx* c, const double* x, const double* mu, double* out, dou
   if (c->n_fblk)
     HIPCHK(c, ghk::pointwise_rhs(c->d_sh, c->d_fblk, c->n_fblk, c->d_angtab, c->d_radtab, x, c->d_dR, c->d_dA,
                                  c->d_H, c->d_dH, c->d_gamma, c->d_W, c->stream));
-  HIPCHK(c, ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 0, 1.0, mu, 0.0, nullptr, 0.0, nullptr, c->d_Lb,
+  LINCOMB(ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 0, 1.0, mu, 0.0, nullptr, 0.0, nullptr, c->d_Lb,
                          c->stream));
   HIPCHK(c, ghk::boundary_vjp(c->d_sh, c->n_shells, c->max_S, c->d_bctab, c->d_gamma, c->d_W, c->d_Lb, c->d_bcg,
                               c->stream));
@@ -837,17 +875,17 @@ int queue_step_vjp(gh_ctx* c, const double* u_n, const double* u1, const double*
   }
   // u3 = 1/3 u + 2/3 (u2 + h L(u2))
   if ((rc = queue_rhs_vjp(c, u2, lam3, c->d_T, 2.0 / 3.0, 1, g_gamma))) return rc;
-  HIPCHK(c, ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 1, 0.0, nullptr, 2.0 / 3.0, lam3, 2.0 / 3.0, c->d_T,
+  LINCOMB(ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 1, 0.0, nullptr, 2.0 / 3.0, lam3, 2.0 / 3.0, c->d_T,
                          c->d_mu2, c->stream));
   // u2 = 3/4 u + 1/4 (u1 + h L(u1))
   if ((rc = queue_rhs_vjp(c, u1, c->d_mu2, c->d_T, 0.25, 1, g_gamma))) return rc;
-  HIPCHK(c, ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 1, 0.0, nullptr, 0.25, c->d_mu2, 0.25, c->d_T,
+  LINCOMB(ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 1, 0.0, nullptr, 0.25, c->d_mu2, 0.25, c->d_T,
                          c->d_mu1, c->stream));
   // u1 = u + h L(u)
   if ((rc = queue_rhs_vjp(c, u_n, c->d_mu1, c->d_T, 1.0, 1, g_gamma))) return rc;
-  HIPCHK(c, ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 0, 1.0 / 3.0, lam3, 0.75, c->d_mu2, 0.0, nullptr,
+  LINCOMB(ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 0, 1.0 / 3.0, lam3, 0.75, c->d_mu2, 0.0, nullptr,
                          lam_n, c->stream));
-  HIPCHK(c, ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 1, 1.0, lam_n, 1.0, c->d_mu1, 1.0, c->d_T, lam_n,
+  LINCOMB(ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 1, 1.0, lam_n, 1.0, c->d_mu1, 1.0, c->d_T, lam_n,
                          c->stream));
   return GH_OK;
 }
@@ -860,11 +898,8 @@ int gh_step_vjp(gh_ctx* c, const double* u_n, const double* lam_np1, double* lam
   HIPCHK(c, hipSetDevice(c->device));
   if ((rc = ensure_adjoint(c))) return rc;
   // recompute the stages: u1 = u + h L(u), u2 = 3/4 u + 1/4 (u1 + h L(u1))
-  if ((rc = queue_rhs(c, u_n, c->d_W))) return rc;
-  HIPCHK(c, ghk::rk_stage(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 0.0, nullptr, 1.0, u_n, c->d_W, c->d_u1, c->stream));
-  if ((rc = queue_rhs(c, c->d_u1, c->d_W))) return rc;
-  HIPCHK(c, ghk::rk_stage(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 0.75, u_n, 0.25, c->d_u1, c->d_W, c->d_u2,
-                          c->stream));
+  if ((rc = queue_stage(c, 0.0, nullptr, 1.0, u_n, c->d_u1))) return rc;
+  if ((rc = queue_stage(c, 0.75, u_n, 0.25, c->d_u1, c->d_u2))) return rc;
   return queue_step_vjp(c, u_n, c->d_u1, c->d_u2, lam_np1, lam_n, g_gamma);
 }
 
@@ -875,18 +910,10 @@ int gh_step_stages(gh_ctx* c, double* u, double* u1, double* u2) {
     return fail(c, GH_ERR_ARG, "u, u1, u2 must be distinct device pointers");
   HIPCHK(c, hipSetDevice(c->device));
   const bool filt = c->filter_kind == 1;
-  auto stage = [&](double c0, const double* u0, double c1, const double* us, double* out) -> int {
-    Timed t(c, 5);
-    HIPCHK(c, ghk::rk_stage(c->d_sh, c->d_blk, c->n_blk, c->d_dt, c0, u0, c1, us, c->d_W, out, c->stream));
-    return GH_OK;
-  };
-  if ((rc = queue_rhs(c, u, c->d_W))) return rc;
-  if ((rc = stage(0.0, nullptr, 1.0, u, u1))) return rc;
-  if ((rc = queue_rhs(c, u1, c->d_W))) return rc;
-  if ((rc = stage(0.75, u, 0.25, u1, u2))) return rc;
-  if ((rc = queue_rhs(c, u2, c->d_W))) return rc;
+  if ((rc = queue_stage(c, 0.0, nullptr, 1.0, u, u1))) return rc;
+  if ((rc = queue_stage(c, 0.75, u, 0.25, u1, u2))) return rc;
   double* dst = filt ? c->d_ua : u;
-  if ((rc = stage(1.0 / 3.0, u, 2.0 / 3.0, u2, dst))) return rc;
+  if ((rc = queue_stage(c, 1.0 / 3.0, u, 2.0 / 3.0, u2, dst))) return rc;
   if (filt) {
     Timed t(c, 1);
     HIPCHK(c, ghk::gemm(c->filter.shape, c->filter.d_tiles, c->filter.n_tiles, c->filter.d_groups, c->d_ua, u,
@@ -941,6 +968,8 @@ int gh_query(const gh_ctx* c, int what, long long* value) {
       break;
     case 2: *value = c->deriv.n_tiles; break;
     case 3: *value = c->P; break;
+    case 4: *value = c->deriv.order; break;
+    case 5: *value = c->filter_kind == 1 ? c->filter.order : 0; break;
     default: return GH_ERR_ARG;
   }
   return GH_OK;

@@ -69,9 +69,11 @@ hipError_t pointwise_rhs(const ShellDev* sh, const PtBlock* blk, int n_blk, cons
 hipError_t boundary(const ShellDev* sh, int n_shells, int max_S, const double* bctab,
                     const double* gamma, double* rhs, hipStream_t st);
 
-hipError_t rk_stage(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* dt,
-                    double c0, const double* u0, double c1, const double* u, const double* L,
-                    double* out, hipStream_t st);
+// One SSP-RK3 stage, out = c0 u0 + c1 (us + dt L'), with the boundary
+// treatment of L (raw d_t u, read only) applied on the fly; out may alias u0.
+hipError_t stage_bc(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* bctab,
+                    const double* gamma, const double* dt, double c0, const double* u0, double c1,
+                    const double* us, const double* L, double* out, hipStream_t st);
 
 hipError_t constraints(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* angtab,
                        const double* radtab, const double* u, const double* dR, const double* dA,

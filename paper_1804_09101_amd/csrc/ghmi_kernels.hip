@@ -529,8 +529,34 @@ __global__ __launch_bounds__(256) void k_pointwise_rhs(
 }
 
 // ---------------------------------------------------------------------------
-// Boundary treatment: characteristic upwinding at interfaces, Dirichlet at the
-// outer boundary.  blockIdx.y = shell; threads over angular points.
+// Characteristic upwinding of one symmetric pair at an interface point.
+// A, B: the five components (psi, Pi, Phi_x, Phi_y, Phi_z) of d_t u of that
+// pair on the inner and the outer shell; T: the point's frozen record (s_i,
+// s^i, upwind weights of u^0, u^+, u^-).  out: the value both shells take.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void interface_pair(const double A[5], const double B[5],
+                                               const double* __restrict__ T, double g2,
+                                               double out[5]) {
+  const double sl[3] = {T[0], T[1], T[2]}, su[3] = {T[3], T[4], T[5]};
+  const double w0 = T[6], wp = T[7], wm = T[8];
+  const double sPa = su[0] * A[2] + su[1] * A[3] + su[2] * A[4];
+  const double sPb = su[0] * B[2] + su[1] * B[3] + su[2] * B[4];
+  const double upsi = 0.5 * (A[0] + B[0]);
+  const double up = wp * (A[1] + sPa - g2 * A[0]) + (1.0 - wp) * (B[1] + sPb - g2 * B[0]);
+  const double um = wm * (A[1] - sPa - g2 * A[0]) + (1.0 - wm) * (B[1] - sPb - g2 * B[0]);
+  out[0] = upsi;
+  out[1] = 0.5 * (up + um) + g2 * upsi;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double u0 = w0 * (A[2 + i] - sl[i] * sPa) + (1.0 - w0) * (B[2 + i] - sl[i] * sPb);
+    out[2 + i] = u0 + 0.5 * sl[i] * (up - um);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Boundary treatment in place on d_t u: characteristic upwinding at
+// interfaces, Dirichlet at the outer boundary.  blockIdx.y = shell; threads
+// over angular points.  (Used by gh_rhs; a time step uses k_stage_bc.)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_boundary(const ShellDev* __restrict__ sh,
                                                   const double* __restrict__ bctab,
@@ -552,30 +578,16 @@ __global__ __launch_bounds__(256) void k_boundary(const ShellDev* __restrict__ s
   const int Pt = t.n_r * t.S;
   const long long ib = 50LL * t.pt_off + a;
   const double* T = bctab + s.bc_off + 9LL * a;
-  const double sl[3] = {T[0], T[1], T[2]}, su[3] = {T[3], T[4], T[5]};
-  const double w0 = T[6], wp = T[7], wm = T[8];
   const double g2 = gamma[3 * s.instance + 2];
 #pragma unroll 2
   for (int n = 0; n < 10; ++n) {
-    double A[5], B[5];
+    double A[5], B[5], out[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       A[c] = rhs[ia + (long long)(10 * c + n) * P];
       B[c] = rhs[ib + (long long)(10 * c + n) * Pt];
     }
-    const double sPa = su[0] * A[2] + su[1] * A[3] + su[2] * A[4];
-    const double sPb = su[0] * B[2] + su[1] * B[3] + su[2] * B[4];
-    const double upsi = 0.5 * (A[0] + B[0]);
-    const double up = wp * (A[1] + sPa - g2 * A[0]) + (1.0 - wp) * (B[1] + sPb - g2 * B[0]);
-    const double um = wm * (A[1] - sPa - g2 * A[0]) + (1.0 - wm) * (B[1] - sPb - g2 * B[0]);
-    double out[5];
-    out[0] = upsi;
-    out[1] = 0.5 * (up + um) + g2 * upsi;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const double u0 = w0 * (A[2 + i] - sl[i] * sPa) + (1.0 - w0) * (B[2 + i] - sl[i] * sPb);
-      out[2 + i] = u0 + 0.5 * sl[i] * (up - um);
-    }
+    interface_pair(A, B, T, g2, out);
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       rhs[ia + (long long)(10 * c + n) * P] = out[c];
@@ -585,23 +597,57 @@ __global__ __launch_bounds__(256) void k_boundary(const ShellDev* __restrict__ s
 }
 
 // ---------------------------------------------------------------------------
-// SSP-RK3 stage: out = c0 u0 + c1 (u + dt L), dt per instance; blockIdx.y = field.
+// SSP-RK3 stage with the boundary treatment folded in:
+//   out = c0 u0 + c1 (us + dt L'),
+// where L' is the raw d_t u in L except on treated faces: zero on the outer
+// boundary, the upwinded interface value on both faces of an interface (each
+// element recomputes its pair's projection from L, which this kernel only
+// reads, so both shells get bitwise the same value).  dt per instance;
+// blockIdx.y = field.  out may alias u0.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_rk_stage(const ShellDev* __restrict__ sh,
+__global__ __launch_bounds__(256) void k_stage_bc(const ShellDev* __restrict__ sh,
                                                   const PtBlock* __restrict__ blk,
+                                                  const double* __restrict__ bctab,
+                                                  const double* __restrict__ gamma,
                                                   const double* __restrict__ dt, double c0,
                                                   const double* u0, double c1,
-                                                  const double* __restrict__ u,
-                                                  const double* __restrict__ L,
-                                                  double* out) {
+                                                  const double* __restrict__ us,
+                                                  const double* __restrict__ L, double* out) {
   const PtBlock b = blk[blockIdx.x];
   const ShellDev s = sh[b.shell];
   const int P = s.n_r * s.S;
   const int q = b.q0 + threadIdx.x;
   if (q >= P) return;
-  const long long e = 50LL * s.pt_off + (long long)blockIdx.y * P + q;
-  const double h = dt[s.instance];
-  double v = c1 * (u[e] + h * L[e]);
+  const int f = blockIdx.y;
+  const long long e = 50LL * s.pt_off + (long long)f * P + q;
+  const int r = q / s.S;
+  double val;
+  if (r == s.n_r - 1 && s.outer) {
+    val = 0.0;
+  } else if ((r == s.n_r - 1 && s.bc_off >= 0) || (r == 0 && !s.inner)) {
+    // interface between shell ki (inner side) and ki + 1
+    const int ki = (r == 0) ? b.shell - 1 : b.shell;
+    const ShellDev si = sh[ki], so = sh[ki + 1];
+    const int a = q - r * s.S;
+    const int Pi = si.n_r * si.S, Po = so.n_r * so.S;
+    const long long ia = 50LL * si.pt_off + (long long)(si.n_r - 1) * si.S + a;
+    const long long ib = 50LL * so.pt_off + a;
+    const int n = f % 10, c = f / 10;
+    double A[5], B[5], o[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      A[k] = L[ia + (long long)(10 * k + n) * Pi];
+      B[k] = L[ib + (long long)(10 * k + n) * Po];
+    }
+    interface_pair(A, B, bctab + si.bc_off + 9LL * a, gamma[3 * si.instance + 2], o);
+    val = o[0];
+#pragma unroll
+    for (int k = 1; k < 5; ++k)
+      if (c == k) val = o[k];
+  } else {
+    val = L[e];
+  }
+  double v = c1 * (us[e] + dt[s.instance] * val);
   if (c0 != 0.0) v += c0 * u0[e];
   out[e] = v;
 }
@@ -1140,11 +1186,11 @@ hipError_t boundary(const ShellDev* sh, int n_shells, int max_S, const double* b
   return hipGetLastError();
 }
 
-hipError_t rk_stage(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* dt,
-                    double c0, const double* u0, double c1, const double* u, const double* L,
-                    double* out, hipStream_t st) {
+hipError_t stage_bc(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* bctab,
+                    const double* gamma, const double* dt, double c0, const double* u0, double c1,
+                    const double* us, const double* L, double* out, hipStream_t st) {
   dim3 grid(n_blk, 50), block(256);
-  hipLaunchKernelGGL(k_rk_stage, grid, block, 0, st, sh, blk, dt, c0, u0, c1, u, L, out);
+  hipLaunchKernelGGL(k_stage_bc, grid, block, 0, st, sh, blk, bctab, gamma, dt, c0, u0, c1, us, L, out);
   return hipGetLastError();
 }
 

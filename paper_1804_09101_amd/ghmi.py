@@ -29,7 +29,7 @@ EXPORTS = [
 ]
 
 KERNEL_KINDS = {"deriv_gemm": 0, "filter_gemm": 1, "radial": 2, "pointwise": 3, "boundary": 4,
-                "rk_stage": 5, "pointwise_vjp": 6, "deriv_gemm_T": 7}
+                "rk_combine_vjp": 5, "pointwise_vjp": 6, "deriv_gemm_T": 7}
 
 
 class GHError(RuntimeError):

@@ -6,13 +6,26 @@ The oracle cannot evaluate the whole domain in test time, so outputs are
 sampled: the RHS at interior points of a shell depends only on that shell, so
 three shells are compared with one-shell oracle domains (no boundary
 treatment); one interface is compared with a two-shell oracle domain.  A short
-evolution must stay finite with a bounded constraint norm."""
+evolution must stay finite with a bounded constraint norm.
+
+Error scale.  Far out (r ~ 300) the fields are O(1) (psi ~ eta) while their
+derivatives are ~1e-5.  Every FP64 evaluation of a derivative D u then carries
+a rounding error of order eps |D| |u| (the standard bound for a sum of
+products), and the two sides use different, equally valid evaluations of the
+same operator: the oracle's Chebyshev transform differentiates a constant
+with an error growing like N_r^3 eps at the shell faces (8.6e-13 at N_r = 33),
+the dense matrix with negative-sum diagonal with 6e-14.  Those errors are far
+above 1e-12 |D u| at large radius, so the sampled shells are compared with
+the term scale kappa = max(|D_r| |u| + |Theta| |u| / r + |Phi| |u| / (r sin theta))
+(operators traced from the oracle's transforms) at 1e-14, about 45 ulps of
+it.  The innermost shell, where FP64 allows it, must also meet 1e-12 of
+max(|RHS|, |d u|)."""
 
 import numpy as np
 import pytest
 
 torch = pytest.importorskip("torch")
-from oracle import domain  # noqa: E402
+from oracle import domain, spectral  # noqa: E402
 from paper_1804_09101_amd import configs, ghmi  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -42,6 +55,26 @@ def _slice(a, ncomp, offs, k0, k1):
     return a[ncomp * offs[k0]: ncomp * offs[k1]]
 
 
+def _traced(fn, n):
+    return np.stack([fn(np.eye(n)[k]) for k in range(n)], axis=1)
+
+
+def _rounding_scale(d, j, ublk):
+    """kappa of one shell block [50, n_r, N_theta, N_phi] of domain d."""
+    g = d.grids[j]
+    sph = d.spheres[g.L]
+    S = sph.S
+    eye = np.eye(S).reshape(S, sph.nth, sph.nph)
+    Th = np.abs(sph.d_dtheta(eye).reshape(S, S))          # [input, output]
+    Ph = np.abs(sph.d_dphi(eye).reshape(S, S))
+    Dr = np.abs(_traced(spectral.d_dxi, g.n_r)) * (2.0 / (g.r_out - g.r_in))
+    U = np.abs(ublk).reshape(50, g.n_r, S)
+    k_r = np.einsum("ij,fjs->fis", Dr, U)
+    k_t = (U @ Th) / g.R.reshape(1, g.n_r, S)
+    k_p = (U @ Ph) / (g.R * np.sin(g.TH)).reshape(1, g.n_r, S)
+    return float(np.max(k_r + k_t + k_p))
+
+
 @pytest.mark.parametrize("k", [0, 10, 19])
 def test_interior_rhs_of_sampled_shells(large, k):
     wl, offs, u0, ubg, H, dH, s, rhs = large
@@ -50,10 +83,16 @@ def test_interior_rhs_of_sampled_shells(large, k):
     ref = d.rhs(sl(u0, 50), sl(H, 4), sl(dH, 16), sl(ubg, 50), wl.gamma, apply_bc=False)
     g = d.split(sl(rhs, 50), 50)[0][:, 1:-1]
     r = d.split(ref, 50)[0][:, 1:-1]
-    tau = np.max(np.abs(d.cartesian_derivs(0, d.split(sl(u0, 50), 50)[0])))
-    err = np.max(np.abs(g - r)) / max(np.max(np.abs(r)), tau)
-    print(f"  shell {k}: interior rhs rel err {err:.3e} (term scale {tau:.3e})", flush=True)
-    assert err < 1e-12
+    ublk = d.split(sl(u0, 50), 50)[0]
+    tau = np.max(np.abs(d.cartesian_derivs(0, ublk)))
+    kappa = _rounding_scale(d, 0, ublk)
+    diff = np.max(np.abs(g - r))
+    err_du = diff / max(np.max(np.abs(r)), tau)
+    print(f"  shell {k}: interior rhs max diff {diff:.3e}; / term scale {kappa:.3e} = {diff / kappa:.3e}; "
+          f"/ max(|rhs|, |du| = {tau:.3e}) = {err_du:.3e}", flush=True)
+    assert diff < 1e-14 * kappa
+    if k == 0:
+        assert err_du < 1e-12
 
 
 def test_interface_rhs_of_sampled_pair(large):
@@ -63,11 +102,10 @@ def test_interface_rhs_of_sampled_pair(large):
     sl = lambda a, c: _slice(a, c, offs, k, k + 2)
     ref = d.split(d.rhs(sl(u0, 50), sl(H, 4), sl(dH, 16), sl(ubg, 50), wl.gamma), 50)
     got = d.split(sl(rhs, 50), 50)
-    tau = max(np.max(np.abs(d.cartesian_derivs(j, b))) for j, b in enumerate(d.split(sl(u0, 50), 50)))
+    kappa = max(_rounding_scale(d, j, b) for j, b in enumerate(d.split(sl(u0, 50), 50)))
     err = max(np.max(np.abs(got[0][:, -1] - ref[0][:, -1])), np.max(np.abs(got[1][:, 0] - ref[1][:, 0])))
-    err /= max(np.max(np.abs(ref[0][:, -1])), tau)
-    print(f"  interface {k}|{k + 1}: rel err {err:.3e}", flush=True)
-    assert err < 1e-12
+    print(f"  interface {k}|{k + 1}: max diff {err:.3e}; / term scale {kappa:.3e} = {err / kappa:.3e}", flush=True)
+    assert err < 1e-14 * kappa
 
 
 def test_short_evolution_is_stable(large):
