@@ -157,13 +157,20 @@ int gh_step_vjp(gh_ctx* ctx, const double* u_n, const double* lam_np1, double* l
 
 /* One gh_step (same arithmetic) that also stores the two SSP-RK3 stage states
  * u1 = u + dt L(u) and u2 = 3/4 u + 1/4 (u1 + dt L(u1)) into u1, u2 (device
- * [50], distinct from u), for a later gh_step_vjp_stages. */
-int gh_step_stages(gh_ctx* ctx, double* u, double* u1, double* u2);
+ * [50], distinct from u), for a later gh_step_vjp_stages.  derivs (device,
+ * may be NULL) receives the spatial derivatives the three RHS evaluations
+ * computed, of u, u1 and u2 in that order, each as the radial derivative
+ * d/dxi ([50] layout) followed by the angular ones (per shell a row-major
+ * [50 n_r][2S] block starting at 100 * offset_k: d_theta of the row's S
+ * points, then d_phi): 3 x 150 P doubles, owned by the caller. */
+int gh_step_stages(gh_ctx* ctx, double* u, double* u1, double* u2, double* derivs);
 
 /* gh_step_vjp with the stage states supplied (from gh_step_stages on u_n), so
- * they are not recomputed.  Same outputs and aliasing rules as gh_step_vjp
- * (lam_n must also not alias u1 or u2). */
-int gh_step_vjp_stages(gh_ctx* ctx, const double* u_n, const double* u1, const double* u2,
+ * they are not recomputed; with derivs (from the same gh_step_stages call,
+ * may be NULL) the derivatives of the three states are not recomputed either.
+ * Same outputs and aliasing rules as gh_step_vjp (lam_n must also not alias
+ * u1, u2 or derivs).  The results do not depend on whether derivs is given. */
+int gh_step_vjp_stages(gh_ctx* ctx, const double* u_n, const double* u1, const double* u2, const double* derivs,
                        const double* lam_np1, double* lam_n, double* g_gamma);
 
 /* Transpose of the constraint norm: lam_u = sum_i lam_norm[i] d||C||_i / d u

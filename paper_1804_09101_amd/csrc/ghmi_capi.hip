@@ -322,19 +322,23 @@ int validate_shells(int n_inst, int n_shells, const gh_shell* s, std::string& wh
 }
 
 // All derivative work of one RHS: the angular GEMM and the radial derivative.
-int queue_derivs(gh_ctx* c, const double* u) {
+// Radial (dR, [50] layout) and angular (dA, [100] layout) derivatives of u;
+// into the context's work space unless targets are given.
+int queue_derivs(gh_ctx* c, const double* u, double* dR = nullptr, double* dA = nullptr) {
+  if (!dR) dR = c->d_dR;
+  if (!dA) dA = c->d_dA;
   {
     Timed t(c, 0);
-    HIPCHK(c, ghk::gemm(c->deriv.shape, c->deriv.d_tiles, c->deriv.n_tiles, c->deriv.d_groups, u, c->d_dA,
-                        c->stream, 0));
+    HIPCHK(c, ghk::gemm(c->deriv.shape, c->deriv.d_tiles, c->deriv.n_tiles, c->deriv.d_groups, u, dA, c->stream,
+                        0));
   }
   {
     Timed t(c, 2);
     if (c->maxr)
-      HIPCHK(c, ghk::radial_col(c->maxr, c->d_sh, c->d_cblk, c->n_cblk, c->d_dtab, u, c->d_dR, 0, 50, false,
-                                false, c->stream));
+      HIPCHK(c, ghk::radial_col(c->maxr, c->d_sh, c->d_cblk, c->n_cblk, c->d_dtab, u, dR, 0, 50, false, false,
+                                c->stream));
     else
-      HIPCHK(c, ghk::radial(c->d_sh, c->d_blk, c->n_blk, c->d_dtab, u, c->d_dR, 0, 50, c->stream));
+      HIPCHK(c, ghk::radial(c->d_sh, c->d_blk, c->n_blk, c->d_dtab, u, dR, 0, 50, c->stream));
   }
   return GH_OK;
 }
@@ -356,13 +360,17 @@ int queue_rhs(gh_ctx* c, const double* u, double* out) {
 
 // One SSP-RK3 stage: out = c0 u0 + c1 (us + dt L(us)).  The raw d_t u goes to
 // the work space; the stage kernel applies the boundary treatment on the fly.
-int queue_stage(gh_ctx* c, double c0, const double* u0, double c1, const double* us, double* out) {
-  int rc = queue_derivs(c, us);
+// With `keep` (150 P doubles) the derivatives of us are written there and kept.
+int queue_stage(gh_ctx* c, double c0, const double* u0, double c1, const double* us, double* out,
+                double* keep = nullptr) {
+  double* dR = keep ? keep : c->d_dR;
+  double* dA = keep ? keep + size_t(50) * c->P : c->d_dA;
+  int rc = queue_derivs(c, us, dR, dA);
   if (rc) return rc;
   {
     Timed t(c, 3);
-    HIPCHK(c, ghk::pointwise_rhs(c->d_sh, c->d_blk, c->n_blk, c->d_angtab, c->d_radtab, us, c->d_dR, c->d_dA,
-                                 c->d_H, c->d_dH, c->d_gamma, c->d_W, c->stream));
+    HIPCHK(c, ghk::pointwise_rhs(c->d_sh, c->d_blk, c->n_blk, c->d_angtab, c->d_radtab, us, dR, dA, c->d_H,
+                                 c->d_dH, c->d_gamma, c->d_W, c->stream));
   }
   {
     Timed t(c, 4);
@@ -418,23 +426,28 @@ int ensure_adjoint(gh_ctx* c) {
 
 // out = (d RHS / d u)^T mu at state x; adds coef * (use_dt ? dt : 1) * (dRHS/dgamma)^T mu
 // to g (device [n_inst][3]) if g is not null.  Uses d_W, d_dA, d_dR, d_Lb, d_dRb, d_dAb.
+// `kept`: derivatives of x saved by gh_step_stages (150 P doubles), else they
+// are recomputed here.
 int queue_rhs_vjp(gh_ctx* c, const double* x, const double* mu, double* out, double coef, int use_dt,
-                  double* g) {
-  int rc = queue_derivs(c, x);
-  if (rc) return rc;
+                  double* g, const double* kept = nullptr) {
+  const double* dR = kept ? kept : c->d_dR;
+  const double* dA = kept ? kept + size_t(50) * c->P : c->d_dA;
+  if (!kept) {
+    int rc = queue_derivs(c, x);
+    if (rc) return rc;
+  }
   // the transposed exchange needs the raw d_t u only on interface faces
   if (c->n_fblk)
-    HIPCHK(c, ghk::pointwise_rhs(c->d_sh, c->d_fblk, c->n_fblk, c->d_angtab, c->d_radtab, x, c->d_dR, c->d_dA,
-                                 c->d_H, c->d_dH, c->d_gamma, c->d_W, c->stream));
+    HIPCHK(c, ghk::pointwise_rhs(c->d_sh, c->d_fblk, c->n_fblk, c->d_angtab, c->d_radtab, x, dR, dA, c->d_H,
+                                 c->d_dH, c->d_gamma, c->d_W, c->stream));
   LINCOMB(ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 0, 1.0, mu, 0.0, nullptr, 0.0, nullptr, c->d_Lb,
                          c->stream));
   HIPCHK(c, ghk::boundary_vjp(c->d_sh, c->n_shells, c->max_S, c->d_bctab, c->d_gamma, c->d_W, c->d_Lb, c->d_bcg,
                               c->stream));
   {
     Timed t(c, 6);
-    HIPCHK(c, ghk::pointwise_vjp(c->d_sh, c->d_blk, c->n_blk, c->d_angtab, c->d_radtab, x, c->d_dR, c->d_dA,
-                                 c->d_H, c->d_dH, c->d_gamma, c->d_Lb, out, c->d_dRb, c->d_dAb, c->d_gpart,
-                                 c->stream));
+    HIPCHK(c, ghk::pointwise_vjp(c->d_sh, c->d_blk, c->n_blk, c->d_angtab, c->d_radtab, x, dR, dA, c->d_H,
+                                 c->d_dH, c->d_gamma, c->d_Lb, out, c->d_dRb, c->d_dAb, c->d_gpart, c->stream));
   }
   {
     Timed t(c, 7);
@@ -864,8 +877,12 @@ int gh_rhs_vjp(gh_ctx* c, const double* u, const double* lam, double* lam_u, dou
 
 // Reverse sweep of one RK3 step given its stage states u1, u2.
 int queue_step_vjp(gh_ctx* c, const double* u_n, const double* u1, const double* u2, const double* lam_np1,
-                   double* lam_n, double* g_gamma) {
+                   double* lam_n, double* g_gamma, const double* kept = nullptr) {
   int rc;
+  const size_t F150 = size_t(150) * c->P;
+  const double* k0 = kept ? kept : nullptr;
+  const double* k1 = kept ? kept + F150 : nullptr;
+  const double* k2 = kept ? kept + 2 * F150 : nullptr;
   // filter: u_{n+1} = F u3, so lam3 = F^T lam_{n+1}
   const double* lam3 = lam_np1;
   if (c->filter_kind == 1) {
@@ -874,15 +891,15 @@ int queue_step_vjp(gh_ctx* c, const double* u_n, const double* u1, const double*
     lam3 = c->d_lam3;
   }
   // u3 = 1/3 u + 2/3 (u2 + h L(u2))
-  if ((rc = queue_rhs_vjp(c, u2, lam3, c->d_T, 2.0 / 3.0, 1, g_gamma))) return rc;
+  if ((rc = queue_rhs_vjp(c, u2, lam3, c->d_T, 2.0 / 3.0, 1, g_gamma, k2))) return rc;
   LINCOMB(ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 1, 0.0, nullptr, 2.0 / 3.0, lam3, 2.0 / 3.0, c->d_T,
                          c->d_mu2, c->stream));
   // u2 = 3/4 u + 1/4 (u1 + h L(u1))
-  if ((rc = queue_rhs_vjp(c, u1, c->d_mu2, c->d_T, 0.25, 1, g_gamma))) return rc;
+  if ((rc = queue_rhs_vjp(c, u1, c->d_mu2, c->d_T, 0.25, 1, g_gamma, k1))) return rc;
   LINCOMB(ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 1, 0.0, nullptr, 0.25, c->d_mu2, 0.25, c->d_T,
                          c->d_mu1, c->stream));
   // u1 = u + h L(u)
-  if ((rc = queue_rhs_vjp(c, u_n, c->d_mu1, c->d_T, 1.0, 1, g_gamma))) return rc;
+  if ((rc = queue_rhs_vjp(c, u_n, c->d_mu1, c->d_T, 1.0, 1, g_gamma, k0))) return rc;
   LINCOMB(ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 0, 1.0 / 3.0, lam3, 0.75, c->d_mu2, 0.0, nullptr,
                          lam_n, c->stream));
   LINCOMB(ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 1, 1.0, lam_n, 1.0, c->d_mu1, 1.0, c->d_T, lam_n,
@@ -903,17 +920,20 @@ int gh_step_vjp(gh_ctx* c, const double* u_n, const double* lam_np1, double* lam
   return queue_step_vjp(c, u_n, c->d_u1, c->d_u2, lam_np1, lam_n, g_gamma);
 }
 
-int gh_step_stages(gh_ctx* c, double* u, double* u1, double* u2) {
+int gh_step_stages(gh_ctx* c, double* u, double* u1, double* u2, double* derivs) {
   int rc = check_ready(c, true);
   if (rc) return rc;
   if (!u || !u1 || !u2 || u1 == u || u2 == u || u1 == u2)
     return fail(c, GH_ERR_ARG, "u, u1, u2 must be distinct device pointers");
+  if (derivs && (derivs == u || derivs == u1 || derivs == u2))
+    return fail(c, GH_ERR_ARG, "derivs must not alias u, u1 or u2");
   HIPCHK(c, hipSetDevice(c->device));
   const bool filt = c->filter_kind == 1;
-  if ((rc = queue_stage(c, 0.0, nullptr, 1.0, u, u1))) return rc;
-  if ((rc = queue_stage(c, 0.75, u, 0.25, u1, u2))) return rc;
+  const size_t F150 = size_t(150) * c->P;
+  if ((rc = queue_stage(c, 0.0, nullptr, 1.0, u, u1, derivs))) return rc;
+  if ((rc = queue_stage(c, 0.75, u, 0.25, u1, u2, derivs ? derivs + F150 : nullptr))) return rc;
   double* dst = filt ? c->d_ua : u;
-  if ((rc = queue_stage(c, 1.0 / 3.0, u, 2.0 / 3.0, u2, dst))) return rc;
+  if ((rc = queue_stage(c, 1.0 / 3.0, u, 2.0 / 3.0, u2, dst, derivs ? derivs + 2 * F150 : nullptr))) return rc;
   if (filt) {
     Timed t(c, 1);
     HIPCHK(c, ghk::gemm(c->filter.shape, c->filter.d_tiles, c->filter.n_tiles, c->filter.d_groups, c->d_ua, u,
@@ -922,15 +942,16 @@ int gh_step_stages(gh_ctx* c, double* u, double* u1, double* u2) {
   return GH_OK;
 }
 
-int gh_step_vjp_stages(gh_ctx* c, const double* u_n, const double* u1, const double* u2, const double* lam_np1,
-                       double* lam_n, double* g_gamma) {
+int gh_step_vjp_stages(gh_ctx* c, const double* u_n, const double* u1, const double* u2, const double* derivs,
+                       const double* lam_np1, double* lam_n, double* g_gamma) {
   int rc = check_ready(c, true);
   if (rc) return rc;
-  if (!u_n || !u1 || !u2 || !lam_np1 || !lam_n || lam_n == u_n || lam_n == u1 || lam_n == u2)
-    return fail(c, GH_ERR_ARG, "device pointers required; lam_n must not alias u_n, u1 or u2");
+  if (!u_n || !u1 || !u2 || !lam_np1 || !lam_n || lam_n == u_n || lam_n == u1 || lam_n == u2 ||
+      (derivs && lam_n == derivs))
+    return fail(c, GH_ERR_ARG, "device pointers required; lam_n must not alias u_n, u1, u2 or derivs");
   HIPCHK(c, hipSetDevice(c->device));
   if ((rc = ensure_adjoint(c))) return rc;
-  return queue_step_vjp(c, u_n, u1, u2, lam_np1, lam_n, g_gamma);
+  return queue_step_vjp(c, u_n, u1, u2, lam_np1, lam_n, g_gamma, derivs);
 }
 
 int gh_constraints_vjp(gh_ctx* c, const double* u, const double* lam_norm, double* lam_u) {

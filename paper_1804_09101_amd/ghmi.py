@@ -80,8 +80,8 @@ def load_library(path=LIB_PATH):
         "gh_step_vjp": (i, [vp, vp, vp, vp, vp]),
         "gh_constraints_vjp": (i, [vp, vp, vp, vp]),
         "gh_set_graph": (i, [vp, i]),
-        "gh_step_stages": (i, [vp, vp, vp, vp]),
-        "gh_step_vjp_stages": (i, [vp, vp, vp, vp, vp, vp, vp]),
+        "gh_step_stages": (i, [vp, vp, vp, vp, vp]),
+        "gh_step_vjp_stages": (i, [vp, vp, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -256,20 +256,23 @@ class GHSolver:
                                          self._dev(out, 50, "lam_n"), g))
         return out
 
-    def step_stages(self, u, u1, u2):
-        """One step in place on u, storing the stage states into u1, u2."""
+    def step_stages(self, u, u1, u2, derivs=None):
+        """One step in place on u, storing the stage states into u1, u2 and,
+        if derivs (float64 CUDA [450 P]) is given, the derivatives of u, u1, u2."""
         self._sync_stream()
+        d = self._dev(derivs, 450, "derivs") if derivs is not None else None
         self._check(self.lib.gh_step_stages(self.h, self._dev(u, 50, "u"), self._dev(u1, 50, "u1"),
-                                            self._dev(u2, 50, "u2")))
+                                            self._dev(u2, 50, "u2"), d))
         return u
 
-    def step_vjp_stages(self, u_n, u1, u2, lam_np1, g_gamma=None, out=None):
-        """step_vjp with the stage states given (from step_stages)."""
+    def step_vjp_stages(self, u_n, u1, u2, lam_np1, g_gamma=None, out=None, derivs=None):
+        """step_vjp with the stage states (and optionally their derivatives) from step_stages."""
         out = self.new_field() if out is None else out
         self._sync_stream()
         g = ctypes.c_void_p(g_gamma.data_ptr()) if g_gamma is not None else None
+        d = self._dev(derivs, 450, "derivs") if derivs is not None else None
         self._check(self.lib.gh_step_vjp_stages(self.h, self._dev(u_n, 50, "u_n"), self._dev(u1, 50, "u1"),
-                                                self._dev(u2, 50, "u2"), self._dev(lam_np1, 50, "lam_np1"),
+                                                self._dev(u2, 50, "u2"), d, self._dev(lam_np1, 50, "lam_np1"),
                                                 self._dev(out, 50, "lam_n"), g))
         return out
 
@@ -282,7 +285,8 @@ class GHSolver:
         return out
 
     def query(self, what):
-        """0: derivative GEMM tile (BM*1000+BN), 1: filter GEMM tile, 2: derivative tiles, 3: points."""
+        """0: derivative GEMM tile (BM*1000+BN), 1: filter GEMM tile, 2: derivative tiles, 3: points,
+        4: derivative GEMM tile order, 5: filter GEMM tile order."""
         v = ctypes.c_longlong()
         self._check(self.lib.gh_query(self.h, int(what), ctypes.byref(v)))
         return int(v.value)

@@ -114,7 +114,7 @@ def test_evolve_gradient_matches_central_differences_and_oracle():
     gamma = torch.tensor(wl.gamma, dtype=torch.float64, requires_grad=True)
     a = torch.tensor(amp, dtype=torch.float64, device="cuda:0", requires_grad=True)
     u_init = dev(u0) + a * dev(dpi)
-    un = gha.evolve(u_init, gamma, s, wl.dt, n, checkpoint_every=5)
+    un = gha.evolve(u_init, gamma, s, wl.dt, n, checkpoint_every=5, save_derivatives=True)
     L = gha.constraint_norm(un, s).sum()
     L.backward()
     g_adj = np.concatenate([gamma.grad.numpy().ravel(), [float(a.grad.cpu()) * amp]])
@@ -151,7 +151,8 @@ def test_evolve_gradient_matches_central_differences_and_oracle():
 
 
 def test_stage_saving_step_and_vjp_match_plain_ones():
-    """gh_step_stages == gh_step and gh_step_vjp_stages == gh_step_vjp, bitwise."""
+    """gh_step_stages == gh_step and gh_step_vjp_stages == gh_step_vjp, bitwise,
+    with and without the saved stage derivatives."""
     rs = configs.geometric_radii(1.8, 9.0, 2)
     shells = [(0, 9, 7, rs[0], rs[1]), (0, 9, 7, rs[1], rs[2])]
     wl, d, s, u0, ubg, H, dH = _setup(shells, [(1.0, 0.4, (0.1, 0.2, 1.0))], [(0.9, -0.2, 1.1)], [0.005],
@@ -167,3 +168,12 @@ def test_stage_saving_step_and_vjp_match_plain_ones():
     l1 = s.step_vjp(dev(u0), lam, g_gamma=g1)
     l2 = s.step_vjp_stages(dev(u0), u1, u2, lam, g_gamma=g2)
     assert torch.equal(l1, l2) and torch.equal(g1, g2)
+    c = dev(u0)
+    d = torch.full((450 * s.P,), float("nan"), dtype=torch.float64, device="cuda:0")
+    v1, v2 = torch.empty_like(c), torch.empty_like(c)
+    s.step_stages(c, v1, v2, derivs=d)
+    assert torch.equal(a, c) and torch.equal(u1, v1) and torch.equal(u2, v2)
+    assert bool(torch.isfinite(d).all())
+    g3 = torch.zeros(3, dtype=torch.float64, device="cuda:0")
+    l3 = s.step_vjp_stages(dev(u0), v1, v2, lam, g_gamma=g3, derivs=d)
+    assert torch.equal(l1, l3) and torch.equal(g1, g3)
