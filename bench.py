@@ -33,6 +33,34 @@ MI355X_FP64_PEAK_TFLOPS = 78.6
 MI355X_HBM_PEAK_GBS = 8000.0
 
 
+PROFILE = os.path.join(ROOT, "profiles", "pulse_8shell_step_kernels.md")
+KERNEL_SOURCES = ["ghmi_kernels.hip", "ghmi_capi.hip", "ghmi_internal.h"]
+
+
+def gemm_traffic(tile, order):
+    """HBM bytes per launch of the derivative GEMM from the committed PMC record.
+
+    The record (a `traffic-record:` line of the profile summary) holds
+    FETCH_SIZE and WRITE_SIZE per dispatch scaled by a plain copy's counts,
+    the tile shape and order it was taken with, and a hash of the kernel
+    sources.  Returns None unless all three match the running library.
+    """
+    import hashlib
+    try:
+        line = next(l for l in open(PROFILE) if l.startswith("traffic-record:"))
+    except (OSError, StopIteration):
+        return None
+    rec = dict(kv.split("=", 1) for kv in line.split()[1:])
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1804_09101_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if rec.get("sources_sha256") != h.hexdigest() or int(rec.get("tile", -1)) != tile \
+            or int(rec.get("order", -1)) != order:
+        return None
+    return int(rec["bytes_per_launch"])
+
+
 def cpu_baseline(wl, n_rhs):
     """Time the CPU oracle on n_rhs RHS evaluations of the same workload."""
     from oracle import domain
@@ -227,7 +255,10 @@ def main():
                    "dt": float(wl.dt[0]), "parallelism": "single GPU"},
         "roofline": {"kernel": "angular derivative GEMM (FP64 MFMA)", "bound": "mfma",
                      "achieved": achieved, "peak": MI355X_FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / MI355X_FP64_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / MI355X_FP64_PEAK_TFLOPS,
+                     "traffic": gemm_traffic(solver.query(0), solver.query(4)),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_bytes": costs.angular_gemm_bytes(wl.shells),
                      "flops_per_launch": flops, "avg_launch_us": avg_s * 1e6},
         "paper_model": dict(costs.domain_model(wl.shells), note="the paper's dense shell differentiator "
                             "count for one derivative pass of 50 fields (unfused, minimum M and F)"),

@@ -74,3 +74,18 @@ def angular_gemm_flops(shells, n_e=N_FIELDS):
         S = 2 * (L + 1) ** 2
         f += 2 * n_e * n_r * 2 * S * S
     return f
+
+
+def angular_gemm_bytes(shells, n_e=N_FIELDS, w=8):
+    """Minimum HBM bytes of one angular derivative GEMM launch: every field
+    row read once, each distinct operator [S x 2S] read once, the result
+    [n_e n_r x 2S] written once."""
+    b = 0
+    seen = set()
+    for (_, n_r, L, _, _) in shells:
+        S = 2 * (L + 1) ** 2
+        b += w * n_e * n_r * (S + 2 * S)
+        if L not in seen:
+            seen.add(L)
+            b += w * S * 2 * S
+    return b

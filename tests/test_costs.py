@@ -62,3 +62,9 @@ def test_angular_gemm_is_angular_part_of_model():
     assert g == ref
     dm = costs.domain_model(shells)
     assert dm["points"] == 21 * 512 + 11 * 128
+
+
+def test_angular_gemm_bytes_of_the_8_shell_domain():
+    # field matrix 8400 x 512, operator 512 x 1024 (one L), result 8400 x 1024, doubles
+    shells = [(0, 21, 15, 1.0 + i, 2.0 + i) for i in range(8)]
+    assert costs.angular_gemm_bytes(shells) == 8 * (8400 * 512 + 512 * 1024 + 8400 * 1024)
