@@ -37,13 +37,13 @@ PROFILE = os.path.join(ROOT, "profiles", "pulse_8shell_step_kernels.md")
 KERNEL_SOURCES = ["ghmi_kernels.hip", "ghmi_capi.hip", "ghmi_internal.h"]
 
 
-def gemm_traffic(tile, order):
+def gemm_traffic(variant, order):
     """HBM bytes per launch of the derivative GEMM from the committed PMC record.
 
     The record (a `traffic-record:` line of the profile summary) holds
     FETCH_SIZE and WRITE_SIZE per dispatch scaled by a plain copy's counts,
-    the tile shape and order it was taken with, and a hash of the kernel
-    sources.  Returns None unless all three match the running library.
+    the kernel variant and tile order it was taken with, and a hash of the
+    kernel sources.  Returns None unless all three match the running library.
     """
     import hashlib
     try:
@@ -55,7 +55,7 @@ def gemm_traffic(tile, order):
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1804_09101_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if rec.get("sources_sha256") != h.hexdigest() or int(rec.get("tile", -1)) != tile \
+    if rec.get("sources_sha256") != h.hexdigest() or int(rec.get("variant", -1)) != variant \
             or int(rec.get("order", -1)) != order:
         return None
     return int(rec["bytes_per_launch"])
@@ -256,7 +256,7 @@ def main():
         "roofline": {"kernel": "angular derivative GEMM (FP64 MFMA)", "bound": "mfma",
                      "achieved": achieved, "peak": MI355X_FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / MI355X_FP64_PEAK_TFLOPS,
-                     "traffic": gemm_traffic(solver.query(0), solver.query(4)),
+                     "traffic": gemm_traffic(solver.query(6), solver.query(4)),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "algorithmic_bytes": costs.angular_gemm_bytes(wl.shells),
                      "flops_per_launch": flops, "avg_launch_us": avg_s * 1e6},
@@ -264,7 +264,8 @@ def main():
                             "count for one derivative pass of 50 fields (unfused, minimum M and F)"),
         "kernels": kernels,
         "gemm_tiles": {"deriv": solver.query(0), "filter": solver.query(1), "deriv_tiles": solver.query(2),
-                       "deriv_order": solver.query(4), "filter_order": solver.query(5)},
+                       "deriv_order": solver.query(4), "filter_order": solver.query(5),
+                       "deriv_variant": solver.query(6), "filter_variant": solver.query(7)},
         "graph_value": P * 3 * args.steps / t_graph,
     }
     if not args.no_adjoint:

@@ -196,7 +196,9 @@ int gh_kernel_stats(gh_ctx* ctx, int kind, long long* launches, double* total_ms
  * filter GEMM (0 without filter); 2: number of tiles of one derivative GEMM
  * launch; 3: total collocation points; 4: tile order of the derivative GEMM
  * (0: each XCD takes whole column blocks, 1: whole row blocks); 5: the same
- * for the filter GEMM. */
+ * for the filter GEMM; 6: kernel variant of the derivative GEMM (index into
+ * the library's list of tile shape, wave layout and LDS layout); 7: the same
+ * for the filter GEMM (-1 without filter). */
 int gh_query(const gh_ctx* ctx, int what, long long* value);
 
 /* Message of the last error on this context (never NULL). */

@@ -991,6 +991,8 @@ int gh_query(const gh_ctx* c, int what, long long* value) {
     case 3: *value = c->P; break;
     case 4: *value = c->deriv.order; break;
     case 5: *value = c->filter_kind == 1 ? c->filter.order : 0; break;
+    case 6: *value = c->deriv.shape; break;
+    case 7: *value = c->filter_kind == 1 ? c->filter.shape : -1; break;
     default: return GH_ERR_ARG;
   }
   return GH_OK;

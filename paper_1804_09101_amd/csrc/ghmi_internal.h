@@ -43,7 +43,7 @@ struct GemmTile {
 // Kernel launchers (ghmi_kernels.hip).  All are asynchronous on `st`.
 namespace ghk {
 
-enum { NUM_TILE_SHAPES = 8 };
+enum { NUM_TILE_SHAPES = 10 };
 void tile_dims(int shape, int* bm, int* bn);
 
 // role: 0 angular derivative, 1 filter, 2 transposed derivative (separate kernel symbols).

@@ -286,7 +286,8 @@ class GHSolver:
 
     def query(self, what):
         """0: derivative GEMM tile (BM*1000+BN), 1: filter GEMM tile, 2: derivative tiles, 3: points,
-        4: derivative GEMM tile order, 5: filter GEMM tile order."""
+        4: derivative GEMM tile order, 5: filter GEMM tile order, 6: derivative GEMM kernel variant,
+        7: filter GEMM kernel variant."""
         v = ctypes.c_longlong()
         self._check(self.lib.gh_query(self.h, int(what), ctypes.byref(v)))
         return int(v.value)
