@@ -33,6 +33,11 @@ MI355X_FP64_PEAK_TFLOPS = 78.6
 MI355X_HBM_PEAK_GBS = 8000.0
 
 
+def log(msg):
+    """Progress line on stderr (stdout carries only the JSON result)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 PROFILE = os.path.join(ROOT, "profiles", "pulse_8shell_step_kernels.md")
 KERNEL_SOURCES = ["ghmi_kernels.hip", "ghmi_capi.hip", "ghmi_internal.h"]
 
@@ -87,6 +92,7 @@ def adjoint_ratio(solver, u0_dev, wl, n_steps=200, k=20):
     import torch
     from paper_1804_09101_amd import autograd as gha
     from paper_1804_09101_amd import ghmi
+    warm_adjoint(solver, u0_dev)
     gamma = torch.tensor(wl.gamma, dtype=torch.float64, requires_grad=True)
     u0 = u0_dev.clone().requires_grad_(True)
     torch.cuda.synchronize()
@@ -118,28 +124,22 @@ def adjoint_ratio(solver, u0_dev, wl, n_steps=200, k=20):
 
 
 def batched_comparison(steps):
-    """64 Kerr holes: one context (grouped launches) vs one context per hole."""
+    """64 Kerr holes: one context (one launch per kernel for every hole) against
+    one context per hole, both stepped eagerly and both from captured graphs."""
     import torch
     from paper_1804_09101_amd import configs, ghmi
     wl = configs.batched_64()
+    log("batched: building inputs")
     xyz = ghmi.grid_coords(wl.shells)
     offs = np.concatenate([[0], np.cumsum([s[1] * 2 * (s[2] + 1) ** 2 for s in wl.shells])])
     u0, ubg, H, dH = wl.initial_data(xyz, offs, device="cuda:0")
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
     P = int(offs[-1])
-    out = {"workload": "batched_64", "instances": wl.n_inst, "shells": len(wl.shells), "points": P}
+    out = {"workload": "batched_64", "instances": wl.n_inst, "shells": len(wl.shells), "points": P,
+           "unit": "grid-point RHS evals/s", "steps": steps}
     s = ghmi.GHSolver(wl.shells, wl.n_inst)
     s.set_background(dev(H), dev(dH), dev(ubg))
     s.set_params(wl.gamma, wl.dt)
-    s.set_graph(True)
-    u = dev(u0)
-    s.step(u, 2)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.step(u, steps)
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
-    out["batched_value"] = P * 3 * steps / tb
     per = []
     for inst in range(wl.n_inst):
         ks = [k for k, sh in enumerate(wl.shells) if sh[0] == inst]
@@ -148,18 +148,99 @@ def batched_comparison(steps):
         si.set_background(dev(H[4 * lo:4 * hi]), dev(dH[16 * lo:16 * hi]), dev(ubg[50 * lo:50 * hi]))
         si.set_params(wl.gamma[inst:inst + 1], wl.dt[inst:inst + 1])
         per.append((si, dev(u0[50 * lo:50 * hi])))
-    for si, ui in per:
-        si.step(ui, 2)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
+    u = dev(u0)
+    for mode in ("eager", "graph"):
+        g = mode == "graph"
+        s.set_graph(g)
+        for si, _ in per:
+            si.set_graph(g)
+        s.step(u, 2)
         for si, ui in per:
-            si.step(ui, 1)
+            si.step(ui, 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(u, steps)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for si, ui in per:
+                si.step(ui, 1)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        out[mode] = {"batched_value": P * 3 * steps / tb, "per_instance_value": P * 3 * steps / tp,
+                     "batched_ms_per_step": tb / steps * 1e3, "per_instance_ms_per_step": tp / steps * 1e3,
+                     "speedup": tp / tb}
+        log(f"batched ({mode}): one context {tb * 1e3 / steps:.2f} ms/step, "
+            f"one per hole {tp * 1e3 / steps:.2f} ms/step")
+    return out
+
+
+def warm_adjoint(solver, u):
+    """One RHS transpose before timing: its first call allocates the reverse
+    work space and tunes the transposed GEMMs (setup, like the forward's
+    tuning in gh_set_domain)."""
+    import torch
+    solver.rhs_vjp(u, torch.zeros_like(u))
     torch.cuda.synchronize()
-    tp = time.perf_counter() - t0
-    out["per_instance_value"] = P * 3 * steps / tp
-    out["speedup"] = tp / tb
-    out["unit"] = "grid-point RHS evals/s"
+
+
+def large_measurement(steps, adj_steps, k):
+    """The 20-shell L = 31 domain: forward rate of one instance, and the
+    adjoint/forward ratio of a checkpointed gradient on a 4-instance batch."""
+    import torch
+    from paper_1804_09101_amd import autograd as gha
+    from paper_1804_09101_amd import configs, costs, ghmi
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    out = {}
+    for name, wl in (("single", configs.large_20shell()), ("batch4", configs.large_20shell_batch(4))):
+        log(f"large {name}: building inputs")
+        xyz = ghmi.grid_coords(wl.shells)
+        offs = np.concatenate([[0], np.cumsum([s[1] * 2 * (s[2] + 1) ** 2 for s in wl.shells])])
+        u0, ubg, H, dH = wl.initial_data(xyz, offs, device="cuda:0")
+        del xyz
+        s = ghmi.GHSolver(wl.shells, wl.n_inst, wl.filter_params)
+        s.set_background(dev(H), dev(dH), dev(ubg))
+        s.set_params(wl.gamma, wl.dt)
+        del H, dH, ubg
+        u = dev(u0)
+        s.step(u, 2)
+        torch.cuda.synchronize()
+        s.set_timing(True)
+        t0 = time.perf_counter()
+        s.step(u, steps)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        n_g, ms_g = s.kernel_stats("deriv_gemm")
+        s.set_timing(False)
+        flops = costs.angular_gemm_flops(wl.shells)
+        rec = {"points": s.P, "instances": wl.n_inst, "steps": steps, "ms_per_step": t / steps * 1e3,
+               "value": s.P * 3 * steps / t, "unit": "grid-point RHS evals/s",
+               "deriv_gemm_avg_us": ms_g / n_g * 1e3, "deriv_gemm_tflops": flops / (ms_g / n_g / 1e3) / 1e12,
+               "deriv_variant": s.query(6), "deriv_order": s.query(4)}
+        log(f"large {name}: {steps} steps in {t:.2f} s")
+        if name == "batch4":
+            warm_adjoint(s, u)
+            gamma = torch.tensor(wl.gamma, dtype=torch.float64, requires_grad=True)
+            ua = dev(u0).requires_grad_(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            un = gha.evolve(ua, gamma, s, wl.dt, adj_steps, checkpoint_every=k)
+            L = gha.constraint_norm(un, s).sum()
+            torch.cuda.synchronize()
+            t_f = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            L.backward()
+            torch.cuda.synchronize()
+            t_b = time.perf_counter() - t0
+            log(f"large {name}: adjoint forward {t_f:.2f} s, backward {t_b:.2f} s")
+            rec["adjoint"] = {"steps": adj_steps, "checkpoint_every": k, "forward_ms": t_f * 1e3,
+                              "backward_ms": t_b * 1e3, "ratio": t_b / t_f,
+                              "grad_gamma_norm": float(gamma.grad.norm()), "grad_u0_norm": float(ua.grad.norm())}
+            del ua, un, L, gamma
+        out[name] = rec
+        del s, u, u0
+        torch.cuda.empty_cache()
     return out
 
 
@@ -171,6 +252,8 @@ def main():
     ap.add_argument("--cpu-rhs", type=int, default=3, help="oracle RHS evaluations for cpu_baseline (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward measurement")
     ap.add_argument("--batched", action="store_true", help="also run the 64-hole batched comparison")
+    ap.add_argument("--large", action="store_true",
+                    help="also measure the 20-shell L = 31 domain (forward, and the adjoint of a 4-instance batch)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -268,11 +351,18 @@ def main():
                        "deriv_variant": solver.query(6), "filter_variant": solver.query(7)},
         "graph_value": P * 3 * args.steps / t_graph,
     }
+    log(f"timed {args.steps} steps: {t * 1e3 / args.steps:.3f} ms/step; graph {t_graph * 1e3 / args.steps:.3f} ms/step")
     if not args.no_adjoint:
         out["adjoint"] = adjoint_ratio(solver, dev(u0), wl)
+        log(f"adjoint ratio {out['adjoint']['ratio']:.2f}")
     if args.batched:
         out["batched"] = batched_comparison(max(5, args.steps // 10))
+        log(f"batched speedup eager {out['batched']['eager']['speedup']:.2f}, "
+            f"graph {out['batched']['graph']['speedup']:.2f}")
+    if args.large:
+        out["large"] = large_measurement(steps=10, adj_steps=10, k=5)
     if args.cpu_rhs > 0:
+        log("oracle baseline")
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_rhs)
     print(json.dumps(out))
 

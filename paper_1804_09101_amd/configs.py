@@ -17,6 +17,8 @@ benchmarks use:
                      shell, L in {7,11,15,23} per hole (seeded)
   large_20shell      Kerr chi = 0.9, M = 1, 20 shells r in [1.4, 400], N_r = 33,
                      L = 31 (32 x 64), smooth random perturbation 1e-6
+  large_20shell_batch  4 instances of the large domain (perturbation seeds 5..8),
+                     the batch its adjoint is measured on
 
 Time steps use the Courant factor of the single-shell case,
 dt = 0.128 * (smallest radial spacing of the instance).
@@ -145,5 +147,15 @@ def large_20shell(seed=5):
                     None, 2000, pert)
 
 
+def large_20shell_batch(n_inst=4, seed=5):
+    """n_inst copies of the large domain, instance i perturbed with seed + i."""
+    one = large_20shell(seed)
+    shells = [(i,) + tuple(sh[1:]) for i in range(n_inst) for sh in one.shells]
+    pert = lambda xyz, inst: inputs.smooth_random_field(xyz, 1e-6, seed + inst, 10, 8.0)
+    return Workload("large_20shell_batch", shells, [one.holes[0]] * n_inst, [GAMMA_DEFAULT] * n_inst,
+                    [one.dt[0]] * n_inst, None, one.n_steps, pert)
+
+
 WORKLOADS = {"single_shell": single_shell, "pulse_8shell": pulse_8shell,
-             "batched_64": batched_64, "large_20shell": large_20shell}
+             "batched_64": batched_64, "large_20shell": large_20shell,
+             "large_20shell_batch": large_20shell_batch}
