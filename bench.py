@@ -39,31 +39,35 @@ def log(msg):
 
 
 PROFILE = os.path.join(ROOT, "profiles", "pulse_8shell_step_kernels.md")
-KERNEL_SOURCES = ["ghmi_kernels.hip", "ghmi_capi.hip", "ghmi_internal.h"]
+KERNEL_SOURCES = ["ghmi_gemm.hip", "ghmi_internal.h"]
 
 
 def gemm_traffic(variant, order):
-    """HBM bytes per launch of the derivative GEMM from the committed PMC record.
+    """HBM bytes per launch of the derivative GEMM from the committed PMC records.
 
-    The record (a `traffic-record:` line of the profile summary) holds
-    FETCH_SIZE and WRITE_SIZE per dispatch scaled by a plain copy's counts,
-    the kernel variant and tile order it was taken with, and a hash of the
-    kernel sources.  Returns None unless all three match the running library.
+    The profile summary lists, for every kernel variant and tile order,
+    FETCH_SIZE and WRITE_SIZE per dispatch scaled by a plain copy's counts
+    (`traffic-record:` lines), and the hash of the GEMM sources they were
+    measured with (`traffic-sources:`).  Returns None unless the hash matches
+    the sources of the running library and a record for (variant, order) exists.
     """
     import hashlib
     try:
-        line = next(l for l in open(PROFILE) if l.startswith("traffic-record:"))
-    except (OSError, StopIteration):
+        lines = open(PROFILE).read().splitlines()
+    except OSError:
         return None
-    rec = dict(kv.split("=", 1) for kv in line.split()[1:])
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1804_09101_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if rec.get("sources_sha256") != h.hexdigest() or int(rec.get("variant", -1)) != variant \
-            or int(rec.get("order", -1)) != order:
+    if f"traffic-sources: sha256={h.hexdigest()}" not in lines:
         return None
-    return int(rec["bytes_per_launch"])
+    for line in lines:
+        if line.startswith("traffic-record:"):
+            rec = dict(kv.split("=", 1) for kv in line.split()[1:])
+            if int(rec["variant"]) == variant and int(rec["order"]) == order:
+                return int(rec["bytes_per_launch"])
+    return None
 
 
 def cpu_baseline(wl, n_rhs):

@@ -6,7 +6,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libghmi.so")
-SOURCES = ["csrc/ghmi_capi.hip", "csrc/ghmi_kernels.hip", "csrc/ghmi_setup.cpp"]
+SOURCES = ["csrc/ghmi_capi.hip", "csrc/ghmi_gemm.hip", "csrc/ghmi_kernels.hip", "csrc/ghmi_setup.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -19,11 +19,24 @@ FLAGS = [
 
 
 def build(verbose=False):
-    """Compile every source into libghmi.so; raises CalledProcessError on failure."""
-    srcs = [os.path.join(HERE, s) for s in SOURCES]
+    """Compile every source (in parallel) and link libghmi.so; raises
+    CalledProcessError on failure."""
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    jobs, objs = [], []
+    for s in SOURCES:
+        obj = os.path.join(objdir, os.path.basename(s) + ".o")
+        objs.append(obj)
+        cmd = [HIPCC] + FLAGS + inc + ["-c", os.path.join(HERE, s), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        jobs.append((cmd, subprocess.Popen(cmd)))
+    for cmd, p in jobs:
+        if p.wait() != 0:
+            raise subprocess.CalledProcessError(p.returncode, cmd)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-                             "-o", tmp] + srcs
+    cmd = [HIPCC] + FLAGS + ["-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -207,39 +207,8 @@ int upload(gh_ctx* c, T** p, const std::vector<T>& h) {
 // Order tiles so that, with workgroups dispatched round-robin over the 8 XCDs,
 // all tiles of one n-column block land on one XCD (its L2 then holds that
 // slice of the operator while the field rows stream past).
-// Tile list of one grouped GEMM launch.  Workgroups are dispatched
-// round-robin over the 8 XCDs, so list position p runs on XCD p % 8; the list
-// interleaves 8 per-XCD sequences.  order 0: each XCD takes whole n-column
-// blocks (its slice of the operator stays in its L2 while the field rows
-// stream past); order 1: each XCD takes whole row blocks (the field rows are
-// fetched once, every XCD reads the operator).
-std::vector<GemmTile> build_tiles(const std::vector<GemmGroup>& groups, int shape, int order) {
-  int bm, bn;
-  ghk::tile_dims(shape, &bm, &bn);
-  const int NX = 8;
-  std::vector<std::vector<GemmTile>> per(NX);
-  int block = 0;
-  for (size_t g = 0; g < groups.size(); ++g) {
-    int mt = (groups[g].M + bm - 1) / bm, nt = (groups[g].N + bn - 1) / bn;
-    if (order == 0) {
-      for (int j = 0; j < nt; ++j, ++block)
-        for (int i = 0; i < mt; ++i) per[block % NX].push_back(GemmTile{int(g), i * bm, j * bn, 0});
-    } else {
-      for (int i = 0; i < mt; ++i, ++block)
-        for (int j = 0; j < nt; ++j) per[block % NX].push_back(GemmTile{int(g), i * bm, j * bn, 0});
-    }
-  }
-  std::vector<GemmTile> out;
-  size_t longest = 0;
-  for (auto& v : per) longest = std::max(longest, v.size());
-  for (size_t q = 0; q < longest; ++q)
-    for (int x = 0; x < NX; ++x)
-      if (q < per[x].size()) out.push_back(per[x][q]);
-  return out;
-}
-
 int plan_upload(gh_ctx* c, GemmPlan& pl, int shape, int order) {
-  std::vector<GemmTile> tiles = build_tiles(pl.groups, shape, order);
+  std::vector<GemmTile> tiles = ghk::build_tiles(pl.groups, shape, order);
   pl.shape = shape;
   pl.order = order;
   pl.n_tiles = int(tiles.size());

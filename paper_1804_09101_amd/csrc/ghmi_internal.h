@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 // One shell as the kernels see it.
 struct ShellDev {
   long long pt_off;   // first collocation point of the shell
@@ -40,15 +42,19 @@ struct GemmTile {
   int pad;
 };
 
-// Kernel launchers (ghmi_kernels.hip).  All are asynchronous on `st`.
+// Kernel launchers (ghmi_gemm.hip, ghmi_kernels.hip).  All are asynchronous on `st`.
 namespace ghk {
 
+// Grouped GEMM (ghmi_gemm.hip).  shape: index of a kernel variant (tile
+// BM x BN, wave layout, LDS layout of A); order: 0 column blocks or 1 row
+// blocks per XCD.  role: 0 angular derivative, 1 filter, 2 transposed
+// derivative (C += A B), 3 transposed filter (separate kernel symbols).
 enum { NUM_TILE_SHAPES = 10 };
 void tile_dims(int shape, int* bm, int* bn);
-
-// role: 0 angular derivative, 1 filter, 2 transposed derivative (separate kernel symbols).
+std::vector<GemmTile> build_tiles(const std::vector<GemmGroup>& groups, int shape, int order);
 hipError_t gemm(int shape, const GemmTile* tiles, int n_tiles, const GemmGroup* groups,
                 const double* Abase, double* Cbase, hipStream_t st, int role);
+
 hipError_t fill_pattern(double* x, long long n, hipStream_t st);
 
 hipError_t radial(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* dtab,

@@ -20,157 +20,6 @@ __host__ __device__ constexpr int SYM3(int i, int j) {
 }
 
 // ---------------------------------------------------------------------------
-// Grouped FP64 GEMM on the matrix cores: C = A * B for every group of a tile
-// list.  One workgroup of WGM x WGN waves computes a BM x BN tile; each wave
-// owns a (BM/WGM) x (BN/WGN) sub-tile made of 16x16 blocks of
-// v_mfma_f64_16x16x4_f64.  A and B k-slices (BK = 16) are staged through LDS,
-// double buffered.  B is stored k-major ([BK][BN]); A either k-major
-// ([BK][BM], AROW = false) or row-major with a one-double pad per row
-// ([BM][BK+1], AROW = true: the global-to-LDS store is then a plain row copy
-// and the padded rows keep the fragment reads free of bank conflicts).
-//
-// Fragment layout of v_mfma_f64_16x16x4_f64 (64 lanes):
-//   A (16x4): lane l holds A[l % 16][l / 16]
-//   B (4x16): lane l holds B[l / 16][l % 16]
-//   C (16x16): lane l holds C[l/16 + 4*v][l % 16], v = 0..3 (checked on gfx950)
-// ---------------------------------------------------------------------------
-// ROLE separates the kernel symbols of the different uses (0: angular
-// derivative, 1: filter, 2: transposed derivative of the adjoint, 3: transposed
-// filter) so that profiles attribute time to each.  ROLE 2 adds into C
-// (C += A B); the others overwrite C.
-template <int BM, int BN, int WGM, int WGN, bool AROW, int ROLE>
-__global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(const GemmTile* __restrict__ tiles,
-                                                         const GemmGroup* __restrict__ groups,
-                                                         const double* __restrict__ Abase,
-                                                         double* __restrict__ Cbase) {
-  constexpr int NT = 64 * WGM * WGN;
-  constexpr int BK = 16;
-  constexpr int WM = BM / WGM, WN = BN / WGN;
-  constexpr int TM = WM / 16, TN = WN / 16;
-  static_assert(TM * 16 == WM && TN * 16 == WN, "wave sub-tile must be whole 16x16 blocks");
-  constexpr int AGRP = BM * BK / 4;     // 4-double groups of one A slice
-  constexpr int BGRP = BK * BN / 4;     // 4-double groups of one B slice
-  constexpr int APASS = (AGRP + NT - 1) / NT;
-  constexpr int BPASS = (BGRP + NT - 1) / NT;
-  constexpr int ALD = BK + 1;           // padded row length of row-major A
-  __shared__ double As[2][AROW ? BM * ALD : BK * BM];
-  __shared__ double Bs[2][BK][BN];
-
-  const GemmTile t = tiles[blockIdx.x];
-  const GemmGroup G = groups[t.g];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave / WGN) * WM, wn = (wave % WGN) * WN;
-  const int M = G.M, N = G.N, K = G.K;
-  const double* __restrict__ Ag = Abase + G.a_off;
-  double* __restrict__ Cg = Cbase + G.c_off;
-
-  d4 acc[TM][TN];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-
-  double ra[APASS][4], rb[BPASS][4];
-
-  auto load_global = [&](int k0) {
-#pragma unroll
-    for (int p = 0; p < APASS; ++p) {
-      int idx = p * NT + tid;
-      if (AGRP % NT != 0 && idx >= AGRP) break;
-      int row = t.m0 + idx / 4, kq = k0 + (idx % 4) * 4;
-      const double* src = Ag + (long long)row * G.lda + kq;
-      if (row < M && kq + 3 < K) {
-        double2 v0 = *reinterpret_cast<const double2*>(src);
-        double2 v1 = *reinterpret_cast<const double2*>(src + 2);
-        ra[p][0] = v0.x; ra[p][1] = v0.y; ra[p][2] = v1.x; ra[p][3] = v1.y;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) ra[p][e] = (row < M && kq + e < K) ? src[e] : 0.0;
-      }
-    }
-#pragma unroll
-    for (int p = 0; p < BPASS; ++p) {
-      int idx = p * NT + tid;
-      if (BGRP % NT != 0 && idx >= BGRP) break;
-      int krow = k0 + idx / (BN / 4), col = t.n0 + (idx % (BN / 4)) * 4;
-      const double* src = G.B + (long long)krow * G.ldb + col;
-      if (krow < K && col + 3 < N) {
-        double2 v0 = *reinterpret_cast<const double2*>(src);
-        double2 v1 = *reinterpret_cast<const double2*>(src + 2);
-        rb[p][0] = v0.x; rb[p][1] = v0.y; rb[p][2] = v1.x; rb[p][3] = v1.y;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) rb[p][e] = (krow < K && col + e < N) ? src[e] : 0.0;
-      }
-    }
-  };
-  auto store_lds = [&](int buf) {
-#pragma unroll
-    for (int p = 0; p < APASS; ++p) {
-      int idx = p * NT + tid;
-      if (AGRP % NT != 0 && idx >= AGRP) break;
-      int row = idx / 4, kq = (idx % 4) * 4;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if (AROW) As[buf][row * ALD + kq + e] = ra[p][e];
-        else As[buf][(kq + e) * BM + row] = ra[p][e];
-      }
-    }
-#pragma unroll
-    for (int p = 0; p < BPASS; ++p) {
-      int idx = p * NT + tid;
-      if (BGRP % NT != 0 && idx >= BGRP) break;
-      int krow = idx / (BN / 4), col = (idx % (BN / 4)) * 4;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) Bs[buf][krow][col + e] = rb[p][e];
-    }
-  };
-
-  const int nk = (K + BK - 1) / BK;
-  load_global(0);
-  store_lds(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) load_global((kt + 1) * BK);
-#pragma unroll
-    for (int kk = 0; kk < BK / 4; ++kk) {
-      const int kr = kk * 4 + lane / 16;
-      double af[TM], bf[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        const int m = wm + i * 16 + (lane & 15);
-        af[i] = AROW ? As[buf][m * ALD + kr] : As[buf][kr * BM + m];
-      }
-#pragma unroll
-      for (int j = 0; j < TN; ++j) bf[j] = Bs[buf][kr][wn + j * 16 + (lane & 15)];
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
-    }
-    if (kt + 1 < nk) store_lds(buf ^ 1);
-    __syncthreads();
-  }
-
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int col = t.n0 + wn + j * 16 + (lane & 15);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = t.m0 + wm + i * 16 + (lane / 16) + 4 * v;
-        if (row < M && col < N) {
-          if (ROLE == 2) Cg[(long long)row * G.ldc + col] += acc[i][j][v];
-          else Cg[(long long)row * G.ldc + col] = acc[i][j][v];
-        }
-      }
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Radial derivative: dR[f][r][a] = dscale * sum_r' D[r][r'] u[f][r'][a].
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_radial(const ShellDev* __restrict__ sh,
@@ -1079,58 +928,6 @@ __global__ __launch_bounds__(256) void k_nonfinite(const double* __restrict__ x,
 
 namespace ghk {
 
-// Kernel variants the autotuner chooses from: tile BM x BN, WGM x WGN waves,
-// A layout in LDS (row-major padded or k-major).
-struct TileShape {
-  int bm, bn, wgm, wgn;
-  bool arow;
-};
-static const TileShape kTiles[NUM_TILE_SHAPES] = {
-    {64, 64, 2, 2, false},  {64, 128, 2, 2, false}, {128, 64, 2, 2, false}, {128, 128, 2, 2, false},
-    {96, 64, 2, 2, false},  {96, 64, 2, 2, true},   {128, 64, 4, 2, true},  {128, 128, 4, 2, true},
-    {64, 128, 2, 4, true},  {192, 64, 4, 2, true}};
-
-void tile_dims(int shape, int* bm, int* bn) {
-  *bm = kTiles[shape].bm;
-  *bn = kTiles[shape].bn;
-}
-
-template <int ROLE>
-static hipError_t gemm_role(int shape, const GemmTile* tiles, int n_tiles, const GemmGroup* groups,
-                            const double* Abase, double* Cbase, hipStream_t st) {
-  dim3 grid(n_tiles);
-#define GH_GEMM_CASE(i, BM_, BN_, WGM_, WGN_, AROW_)                                                  \
-  case i:                                                                                             \
-    hipLaunchKernelGGL((k_gemm<BM_, BN_, WGM_, WGN_, AROW_, ROLE>), grid, dim3(64 * WGM_ * WGN_), 0, st, \
-                       tiles, groups, Abase, Cbase);                                                  \
-    break;
-  switch (shape) {
-    GH_GEMM_CASE(0, 64, 64, 2, 2, false)
-    GH_GEMM_CASE(1, 64, 128, 2, 2, false)
-    GH_GEMM_CASE(2, 128, 64, 2, 2, false)
-    GH_GEMM_CASE(3, 128, 128, 2, 2, false)
-    GH_GEMM_CASE(4, 96, 64, 2, 2, false)
-    GH_GEMM_CASE(5, 96, 64, 2, 2, true)
-    GH_GEMM_CASE(6, 128, 64, 4, 2, true)
-    GH_GEMM_CASE(7, 128, 128, 4, 2, true)
-    GH_GEMM_CASE(8, 64, 128, 2, 4, true)
-    GH_GEMM_CASE(9, 192, 64, 4, 2, true)
-    default: return hipErrorInvalidValue;
-  }
-#undef GH_GEMM_CASE
-  return hipGetLastError();
-}
-
-hipError_t gemm(int shape, const GemmTile* tiles, int n_tiles, const GemmGroup* groups,
-                const double* Abase, double* Cbase, hipStream_t st, int role) {
-  if (n_tiles <= 0) return hipSuccess;
-  switch (role) {
-    case 0: return gemm_role<0>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
-    case 1: return gemm_role<1>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
-    case 2: return gemm_role<2>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
-    default: return gemm_role<3>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
-  }
-}
 
 // Deterministic non-zero fill (bounded values in [-0.5, 0.5)), used so that the
 // autotuner times the matrix cores on data of realistic activity.
