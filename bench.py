@@ -11,8 +11,9 @@ The timed region runs with per-kernel HIP-event timing on, which gives the
 angular GEMM's average launch duration for the roofline figure.  Further
 measurements on the same GPU: the same steps replayed from a captured HIP
 graph; the adjoint/forward cost ratio of a 200-step evolution with gradients
-of the final constraint norm (checkpoint every 20 steps); with --batched, 64
-heterogeneous Kerr holes in one context against one context per hole.
+of the final constraint norm (checkpoint every 20 steps); 64 heterogeneous
+Kerr holes in one context against one context per hole; the 20-shell L = 31
+domain (forward rate, and the adjoint/forward ratio on a 4-instance batch).
 
 Prints one JSON line (rank 0).  With --gpus > 1 it exits: this build runs on
 one GPU.
@@ -255,9 +256,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-rhs", type=int, default=3, help="oracle RHS evaluations for cpu_baseline (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward measurement")
-    ap.add_argument("--batched", action="store_true", help="also run the 64-hole batched comparison")
-    ap.add_argument("--large", action="store_true",
-                    help="also measure the 20-shell L = 31 domain (forward, and the adjoint of a 4-instance batch)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-hole batched comparison")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 20-shell L = 31 domain (forward, and the adjoint of a 4-instance batch)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -359,11 +360,11 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = adjoint_ratio(solver, dev(u0), wl)
         log(f"adjoint ratio {out['adjoint']['ratio']:.2f}")
-    if args.batched:
+    if not args.no_batched:
         out["batched"] = batched_comparison(max(5, args.steps // 10))
         log(f"batched speedup eager {out['batched']['eager']['speedup']:.2f}, "
             f"graph {out['batched']['graph']['speedup']:.2f}")
-    if args.large:
+    if not args.no_large:
         out["large"] = large_measurement(steps=10, adj_steps=10, k=5)
     if args.cpu_rhs > 0:
         log("oracle baseline")

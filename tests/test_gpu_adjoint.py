@@ -177,3 +177,56 @@ def test_stage_saving_step_and_vjp_match_plain_ones():
     g3 = torch.zeros(3, dtype=torch.float64, device="cuda:0")
     l3 = s.step_vjp_stages(dev(u0), v1, v2, lam, g_gamma=g3, derivs=d)
     assert torch.equal(l1, l3) and torch.equal(g1, g3)
+
+
+def test_pulse_8shell_200_step_gradient_matches_central_differences():
+    """The adjoint workload at full size: the 8-shell pulse domain (filter on),
+    200 RK3 steps, checkpoint every 20, loss = final constraint norm.  The
+    derivatives with respect to gamma0, gamma1, gamma2 and along two initial
+    Pi directions (the seeded pulse itself and a smooth random Pi field) are
+    compared with central differences, h = 1e-6, through the same GPU forward
+    path, to 1e-6 of the norm of the five."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    wl = configs.pulse_8shell()
+    print(f"\n[case] pulse_8shell adjoint: {len(wl.shells)} shells, P={wl.npoints}, 200 steps", flush=True)
+    xyz = ghmi.grid_coords(wl.shells)
+    offs = np.concatenate([[0], np.cumsum([s[1] * 2 * (s[2] + 1) ** 2 for s in wl.shells])])
+    u0, ubg, H, dH = wl.initial_data(xyz, offs, device="cuda:0")
+    pulse = configs.to_layout(inputs.gaussian_pulse_Pi(xyz, 1e-3, 10.0, 2.0, 0), wl.shells, offs)
+    rnd = inputs.smooth_random_field(xyz, 1e-3, 11, 4, 3.0)
+    rnd[:10] = 0.0
+    rnd[20:] = 0.0
+    rnd = configs.to_layout(rnd, wl.shells, offs)
+    s = ghmi.GHSolver(wl.shells, wl.n_inst, wl.filter_params)
+    s.set_background(dev(H), dev(dH), dev(ubg))
+    n = 200
+    dirs = [dev(pulse), dev(rnd)]
+
+    def loss(gamma_np, d=None, h=0.0):
+        s.set_params(gamma_np, wl.dt)
+        u = dev(u0)
+        if d is not None:
+            u += h * d
+        s.step(u, n)
+        return float(s.constraints(u, want_C=False)[1].cpu().numpy()[0])
+
+    gamma = torch.tensor(wl.gamma, dtype=torch.float64, requires_grad=True)
+    ua = dev(u0).requires_grad_(True)
+    un = gha.evolve(ua, gamma, s, wl.dt, n, checkpoint_every=20)
+    gha.constraint_norm(un, s).sum().backward()
+    g_adj = np.concatenate([gamma.grad.numpy().ravel(), [float((ua.grad * d).sum()) for d in dirs]])
+    h = 1e-6
+    g_fd = []
+    for c in range(3):
+        gp, gm = wl.gamma.copy(), wl.gamma.copy()
+        gp[0, c] += h
+        gm[0, c] -= h
+        g_fd.append((loss(gp) - loss(gm)) / (2 * h))
+    for d in dirs:
+        g_fd.append((loss(wl.gamma, d, h) - loss(wl.gamma, d, -h)) / (2 * h))
+    g_fd = np.array(g_fd)
+    gn = np.linalg.norm(g_fd)
+    err = np.max(np.abs(g_adj - g_fd)) / gn
+    print(f"  adjoint {g_adj}\n  FD      {g_fd}\n  max |adj-FD|/|g| {err:.2e}", flush=True)
+    assert err <= 1e-6

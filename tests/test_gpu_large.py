@@ -25,8 +25,9 @@ import numpy as np
 import pytest
 
 torch = pytest.importorskip("torch")
-from oracle import domain, spectral  # noqa: E402
+from oracle import domain  # noqa: E402
 from paper_1804_09101_amd import configs, ghmi  # noqa: E402
+from parity_util import rounding_scale as _rounding_scale  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -53,26 +54,6 @@ def large():
 
 def _slice(a, ncomp, offs, k0, k1):
     return a[ncomp * offs[k0]: ncomp * offs[k1]]
-
-
-def _traced(fn, n):
-    return np.stack([fn(np.eye(n)[k]) for k in range(n)], axis=1)
-
-
-def _rounding_scale(d, j, ublk):
-    """kappa of one shell block [50, n_r, N_theta, N_phi] of domain d."""
-    g = d.grids[j]
-    sph = d.spheres[g.L]
-    S = sph.S
-    eye = np.eye(S).reshape(S, sph.nth, sph.nph)
-    Th = np.abs(sph.d_dtheta(eye).reshape(S, S))          # [input, output]
-    Ph = np.abs(sph.d_dphi(eye).reshape(S, S))
-    Dr = np.abs(_traced(spectral.d_dxi, g.n_r)) * (2.0 / (g.r_out - g.r_in))
-    U = np.abs(ublk).reshape(50, g.n_r, S)
-    k_r = np.einsum("ij,fjs->fis", Dr, U)
-    k_t = (U @ Th) / g.R.reshape(1, g.n_r, S)
-    k_p = (U @ Ph) / (g.R * np.sin(g.TH)).reshape(1, g.n_r, S)
-    return float(np.max(k_r + k_t + k_p))
 
 
 @pytest.mark.parametrize("k", [0, 10, 19])
