@@ -16,6 +16,7 @@ import numpy as np
 
 from . import grid as _grid
 from . import spectral as _spec
+from . import dp5 as _dp5
 from . import gh as _gh
 
 
@@ -221,6 +222,36 @@ class Domain:
         u2 = 0.75 * u + 0.25 * (u1 + h * L(u1))
         un = (1.0 / 3.0) * u + (2.0 / 3.0) * (u2 + h * L(u2))
         return self.apply_filter(un)
+
+    def instance_of_value(self):
+        """Instance index of every value of a [50*P] field, layout order."""
+        return self.join([np.full((50, g.npts), self.shells[k].instance)
+                          for k, g in enumerate(self.grids)])
+
+    def dp5_attempt(self, u, H, dH, u_bg, gammas, dt, atol, rtol, prev_rejected, rhs_fn=None):
+        """One Dormand-Prince 5(4) attempt per instance with its own step dt[i].
+
+        Every instance takes the seven stages with its dt; its error norm
+        decides whether its fifth-order solution (filtered, if the filter is
+        enabled) replaces its values, and sets its next dt (oracle/dp5.py).
+        Returns (u_next, accepted[n_inst], dt_next[n_inst], err[n_inst]).
+        """
+        L = rhs_fn or (lambda v: self.rhs(v, H, dH, u_bg, gammas))
+        h = self.dt_per_point(dt)
+        u5, k = _dp5.stages(u, h, L)
+        ev = _dp5.error_vector(k, h)
+        owner = self.instance_of_value()
+        acc = np.zeros(self.n_inst, dtype=bool)
+        dt_next = np.array(dt, dtype=float).copy()
+        errs = np.zeros(self.n_inst)
+        for i in range(self.n_inst):
+            m = owner == i
+            errs[i] = _dp5.error_norm(ev[m], u[m], u5[m], atol, rtol)
+            acc[i], scale = _dp5.control(errs[i], bool(prev_rejected[i]))
+            dt_next[i] = dt[i] * scale
+        new = self.apply_filter(u5)
+        u_next = np.where(acc[owner], new, u)
+        return u_next, acc, dt_next, errs
 
     # -- constraints ------------------------------------------------------------
     def constraints(self, u, H):
