@@ -118,6 +118,29 @@ int gh_rhs(gh_ctx* ctx, const double* u, double* dudt);
  *   u <- 1/3 u + 2/3 (u2 + dt L(u2)), then the filter if enabled. */
 int gh_step(gh_ctx* ctx, double* u, int n_steps);
 
+/* Adaptive Dormand-Prince 5(4) stepping (the paper evolves with a
+ * Dormand-Prince stepper, section "The Spectral Einstein Code"): n_attempts
+ * step attempts in place on u (device [50] layout).  Every instance takes its
+ * own step dt[i] (device [n_inst], in/out) from t[i] (device [n_inst],
+ * in/out).  An attempt forms the seven stages of the Dormand & Prince (1980)
+ * RK5(4) pair (each stage a full RHS with boundary treatment) and per
+ * instance the RMS over its values of err / (atol + rtol max(|u_old|, |u_new|)),
+ * err the difference of the fifth- and fourth-order solutions.  At most 1:
+ * the instance takes the fifth-order solution (then the filter, if enabled)
+ * and t[i] += dt[i]; otherwise its values are kept.  Either way dt[i] is
+ * multiplied by min(10, max(0.2, 0.9 err^-1/5)) (10 for err = 0), capped at 1
+ * right after a rejection (Numerical Recipes' controller).  rejected (device
+ * int [n_inst], in/out, may be NULL) holds whether each instance's last
+ * attempt was rejected, so that consecutive calls continue one integration
+ * (NULL: all zero at the start of the call).  n_accepted (device int
+ * [n_inst], may be NULL) is incremented per accepted step; err (device
+ * [n_inst], may be NULL) receives the last attempt's error norms.
+ * Needs gh_set_params (gamma; its dt is not used).  The first call allocates
+ * about 10 further [50] arrays.  GH_ERR_ARG for n_attempts < 0, negative or
+ * non-finite tolerances, or atol + rtol == 0. */
+int gh_step_dp5(gh_ctx* ctx, double* u, int n_attempts, double atol, double rtol, double* t, double* dt,
+                int* rejected, int* n_accepted, double* err);
+
 /* Graph mode for gh_step (default off).  When on, the first gh_step on a
  * state pointer captures one whole SSP-RK3 step (every kernel of the three
  * stages and the filter, for all shells of all instances) into a HIP graph on

@@ -71,6 +71,13 @@ struct gh_ctx {
   double *d_gpart = nullptr, *d_bcg = nullptr;
   double *d_C = nullptr, *d_norm = nullptr;   // constraint values and norms for gh_constraints_vjp
 
+  // Dormand-Prince work space (allocated on first use): seven stage
+  // derivatives, the stage state, the fifth-order solution, its filtered copy,
+  // per-instance flags and value counts
+  bool have_dp5 = false;
+  double *d_dpk = nullptr, *d_dpy = nullptr, *d_dpu5 = nullptr, *d_dpf = nullptr, *d_dpnval = nullptr;
+  int *d_dprej = nullptr, *d_dpacc = nullptr;
+
   // reductions
   int* d_inst_range = nullptr;
   double *d_wsum = nullptr, *d_partial = nullptr;
@@ -173,6 +180,9 @@ void free_domain(gh_ctx* c) {
   c->d_u1 = c->d_u2 = c->d_lam3 = c->d_mu1 = c->d_mu2 = nullptr;
   c->d_gpart = c->d_bcg = nullptr;
   c->d_C = c->d_norm = nullptr;
+  c->have_dp5 = false;
+  c->d_dpk = c->d_dpy = c->d_dpu5 = c->d_dpf = c->d_dpnval = nullptr;
+  c->d_dprej = c->d_dpacc = nullptr;
   c->d_sh = nullptr; c->d_blk = nullptr; c->d_cblk = nullptr; c->d_fblk = nullptr;
   c->d_dtab = c->d_angtab = c->d_radtab = c->d_bctab = nullptr;
   c->d_inst_range = nullptr; c->d_wsum = c->d_partial = nullptr;
@@ -204,9 +214,7 @@ int upload(gh_ctx* c, T** p, const std::vector<T>& h) {
   return GH_OK;
 }
 
-// Order tiles so that, with workgroups dispatched round-robin over the 8 XCDs,
-// all tiles of one n-column block land on one XCD (its L2 then holds that
-// slice of the operator while the field rows stream past).
+// Build the tile list of a plan for one kernel variant and tile order and upload it.
 int plan_upload(gh_ctx* c, GemmPlan& pl, int shape, int order) {
   std::vector<GemmTile> tiles = ghk::build_tiles(pl.groups, shape, order);
   pl.shape = shape;
@@ -923,6 +931,38 @@ int gh_step_vjp_stages(gh_ctx* c, const double* u_n, const double* u1, const dou
   return queue_step_vjp(c, u_n, u1, u2, lam_np1, lam_n, g_gamma, derivs);
 }
 
+// Dormand-Prince 5(4) tableau (Dormand & Prince 1980): stage weights a_ij,
+// fifth-order weights (row 7) and error weights (fifth minus embedded fourth order).
+namespace dp5c {
+const double A[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5, 0, 0, 0, 0, 0},
+    {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+    {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+    {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+const double E[7] = {35.0 / 384 - 5179.0 / 57600, 0, 500.0 / 1113 - 7571.0 / 16695, 125.0 / 192 - 393.0 / 640,
+                     -2187.0 / 6784 + 92097.0 / 339200, 11.0 / 84 - 187.0 / 2100, -1.0 / 40};
+}  // namespace dp5c
+
+int ensure_dp5(gh_ctx* c) {
+  if (c->have_dp5) return GH_OK;
+  const size_t F50 = size_t(50) * c->P;
+  int rc;
+  if ((rc = dalloc(c, &c->d_dpk, 7 * F50))) return rc;
+  if ((rc = dalloc(c, &c->d_dpy, F50))) return rc;
+  if ((rc = dalloc(c, &c->d_dpu5, F50))) return rc;
+  if (c->filter_kind == 1 && (rc = dalloc(c, &c->d_dpf, F50))) return rc;
+  if ((rc = dalloc(c, &c->d_dprej, size_t(c->n_inst)))) return rc;
+  if ((rc = dalloc(c, &c->d_dpacc, size_t(c->n_inst)))) return rc;
+  std::vector<double> nval(c->n_inst, 0.0);
+  for (int k = 0; k < c->n_shells; ++k) nval[c->shells[k].instance] += 50.0 * double(c->offs[k + 1] - c->offs[k]);
+  if ((rc = upload(c, &c->d_dpnval, nval))) return rc;
+  c->have_dp5 = true;
+  return GH_OK;
+}
+
 int gh_constraints_vjp(gh_ctx* c, const double* u, const double* lam_norm, double* lam_u) {
   if (!c) return GH_ERR_ARG;
   if (!c->have_domain) return fail(c, GH_ERR_ORDER, "gh_set_domain has not been called");
@@ -1051,3 +1091,55 @@ int gh_host_operator(int kind, int n, const double* params, double* out) {
 }
 
 }  // extern "C"
+
+int gh_step_dp5(gh_ctx* c, double* u, int n_attempts, double atol, double rtol, double* t, double* dt,
+                int* rejected, int* n_accepted, double* err) {
+  if (!c) return GH_ERR_ARG;
+  if (!c->have_domain) return fail(c, GH_ERR_ORDER, "gh_set_domain has not been called");
+  if (!c->have_bg) return fail(c, GH_ERR_ORDER, "gh_set_background has not been called");
+  if (!c->have_gamma) return fail(c, GH_ERR_ORDER, "gh_set_params has not been called");
+  if (!u || !t || !dt || n_attempts < 0 || !(atol >= 0.0) || !(rtol >= 0.0) || !(atol + rtol > 0.0) ||
+      !std::isfinite(atol) || !std::isfinite(rtol))
+    return fail(c, GH_ERR_ARG, "need device u, t, dt, n_attempts >= 0, atol, rtol >= 0 finite, atol + rtol > 0");
+  HIPCHK(c, hipSetDevice(c->device));
+  int rc = ensure_dp5(c);
+  if (rc) return rc;
+  if (n_attempts == 0) return GH_OK;
+  const size_t F50 = size_t(50) * c->P;
+  double* K[7];
+  for (int j = 0; j < 7; ++j) K[j] = c->d_dpk + j * F50;
+  const bool filt = c->filter_kind == 1;
+  int* rej = rejected;
+  if (!rej) {
+    rej = c->d_dprej;
+    HIPCHK(c, ghk::fill_int(rej, c->n_inst, 0, c->stream));
+  }
+  for (int a = 0; a < n_attempts; ++a) {
+    // first stage: at the call's start, and after every filtered step (the
+    // filtered state is not the last stage's), else the last stage's value
+    if (a == 0 || filt)
+      if ((rc = queue_rhs(c, u, K[0]))) return rc;
+    for (int i = 1; i < 7; ++i) {
+      double coef[7] = {0, 0, 0, 0, 0, 0, 0};
+      for (int j = 0; j < i; ++j) coef[j] = dp5c::A[i][j];
+      double* y = (i == 6) ? c->d_dpu5 : c->d_dpy;
+      HIPCHK(c, ghk::dp_combine(c->d_sh, c->d_blk, c->n_blk, dt, u, K, coef, i, y, c->stream));
+      if ((rc = queue_rhs(c, y, K[i]))) return rc;
+    }
+    HIPCHK(c, ghk::dp_error(c->d_sh, c->d_blk, c->n_blk, dt, u, c->d_dpu5, K, dp5c::E, atol, rtol, c->d_partial,
+                            c->stream));
+    HIPCHK(c, ghk::dp_control(c->d_inst_range, c->n_inst, c->d_dpnval, c->d_partial, dt, t, rej, c->d_dpacc,
+                              n_accepted, err, c->stream));
+    if (filt) {
+      {
+        Timed tm(c, 1);
+        HIPCHK(c, ghk::gemm(c->filter.shape, c->filter.d_tiles, c->filter.n_tiles, c->filter.d_groups, c->d_dpu5,
+                            c->d_dpf, c->stream, 1));
+      }
+      HIPCHK(c, ghk::dp_accept(c->d_sh, c->d_blk, c->n_blk, c->d_dpacc, c->d_dpf, u, nullptr, nullptr, c->stream));
+    } else {
+      HIPCHK(c, ghk::dp_accept(c->d_sh, c->d_blk, c->n_blk, c->d_dpacc, c->d_dpu5, u, K[6], K[0], c->stream));
+    }
+  }
+  return GH_OK;
+}

@@ -55,6 +55,22 @@ std::vector<GemmTile> build_tiles(const std::vector<GemmGroup>& groups, int shap
 hipError_t gemm(int shape, const GemmTile* tiles, int n_tiles, const GemmGroup* groups,
                 const double* Abase, double* Cbase, hipStream_t st, int role);
 
+// Dormand-Prince pieces.  dp_combine: out = u + dt (sum_{j<nk} c_j k_j);
+// dp_error: per point block, sum over values of (dt sum_j e_j k_j / (atol +
+// rtol max(|u|, |u5|)))^2 into partial[block]; dp_control: per instance the
+// RMS error, accept flag, t and dt update (Numerical Recipes' controller);
+// dp_accept: dst = src (and dst2 = src2) on the values of accepted instances.
+hipError_t dp_combine(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* dt, const double* u,
+                      double* const k[7], const double c[7], int nk, double* out, hipStream_t st);
+hipError_t dp_error(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* dt, const double* u,
+                    const double* u5, double* const k[7], const double e[7], double atol, double rtol,
+                    double* partial, hipStream_t st);
+hipError_t dp_control(const int* blk_range, int n_inst, const double* nval, const double* partial, double* dt,
+                      double* t, int* rejected, int* accepted, int* n_accepted, double* err, hipStream_t st);
+hipError_t dp_accept(const ShellDev* sh, const PtBlock* blk, int n_blk, const int* accepted, const double* src,
+                     double* dst, const double* src2, double* dst2, hipStream_t st);
+hipError_t fill_int(int* x, int n, int value, hipStream_t st);
+
 hipError_t fill_pattern(double* x, long long n, hipStream_t st);
 
 hipError_t radial(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* dtab,

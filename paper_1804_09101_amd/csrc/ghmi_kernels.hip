@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void k_radial(const ShellDev* __restrict__ sh,
 // Radial derivative, one thread per (field, angular point) column: the n_r
 // values of the column are loaded once into registers and all n_r outputs are
 // formed from them, so u and dR each cross HBM once.  The CGL matrix entries
-// are uniform across the workgroup (scalar loads).  TRANS applies D^T instead
+// are staged in LDS and read as broadcasts.  TRANS applies D^T instead
 // of D; ACC adds into dR instead of overwriting it.
 template <int MAXR, bool TRANS, bool ACC>
 __global__ __launch_bounds__(256) void k_radial_col(const ShellDev* __restrict__ sh,
@@ -55,12 +55,16 @@ __global__ __launch_bounds__(256) void k_radial_col(const ShellDev* __restrict__
                                                     double* __restrict__ dR, int f0) {
   const PtBlock b = cblk[blockIdx.x];
   const ShellDev s = sh[b.shell];
+  const int n = s.n_r;
+  // the n x n matrix is the same for every thread: stage it in LDS once and
+  // read it with broadcast loads
+  __shared__ double D[MAXR * MAXR];
+  for (int i = threadIdx.x; i < n * n; i += blockDim.x) D[i] = dtab[s.d_off + i];
+  __syncthreads();
   const int a = b.q0 + threadIdx.x;
   if (a >= s.S) return;
-  const int n = s.n_r;
   const int f = f0 + blockIdx.y;
   const long long base = 50LL * s.pt_off + (long long)f * n * s.S + a;
-  const double* __restrict__ D = dtab + s.d_off;
   double col[MAXR];
 #pragma unroll
   for (int r = 0; r < MAXR; ++r) col[r] = (r < n) ? u[base + (long long)r * s.S] : 0.0;
@@ -924,6 +928,130 @@ __global__ __launch_bounds__(256) void k_nonfinite(const double* __restrict__ x,
   if (c) atomicAdd(count, c);
 }
 
+// ---------------------------------------------------------------------------
+// Dormand-Prince 5(4) stepping: stage combinations, scaled error, per-instance
+// step control, masked acceptance.  blockIdx.y = field where present.
+// ---------------------------------------------------------------------------
+struct DpTerms {
+  const double* k[7];
+  double c[7];
+};
+
+__global__ __launch_bounds__(256) void k_dp_combine(const ShellDev* __restrict__ sh,
+                                                    const PtBlock* __restrict__ blk,
+                                                    const double* __restrict__ dt,
+                                                    const double* __restrict__ u, DpTerms T, int nk,
+                                                    double* __restrict__ out) {
+  const PtBlock b = blk[blockIdx.x];
+  const ShellDev s = sh[b.shell];
+  const int P = s.n_r * s.S;
+  const int q = b.q0 + threadIdx.x;
+  if (q >= P) return;
+  const long long e = 50LL * s.pt_off + (long long)blockIdx.y * P + q;
+  double acc = 0.0;
+#pragma unroll
+  for (int j = 0; j < 7; ++j)
+    if (j < nk && T.c[j] != 0.0) acc += T.c[j] * T.k[j][e];
+  out[e] = u[e] + dt[s.instance] * acc;
+}
+
+// Sum over the 50 values of each point of the block of (err / sk)^2, with
+// err = dt sum_j e_j k_j and sk = atol + rtol max(|u|, |u5|).
+__global__ __launch_bounds__(256) void k_dp_error(const ShellDev* __restrict__ sh,
+                                                  const PtBlock* __restrict__ blk,
+                                                  const double* __restrict__ dt,
+                                                  const double* __restrict__ u,
+                                                  const double* __restrict__ u5, DpTerms T, double atol,
+                                                  double rtol, double* __restrict__ partial) {
+  __shared__ double red[256];
+  const PtBlock b = blk[blockIdx.x];
+  const ShellDev s = sh[b.shell];
+  const int P = s.n_r * s.S;
+  const int q = b.q0 + threadIdx.x;
+  double sum = 0.0;
+  if (q < P) {
+    const double h = dt[s.instance];
+    const long long e0 = 50LL * s.pt_off + q;
+    for (int f = 0; f < 50; ++f) {
+      const long long e = e0 + (long long)f * P;
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < 7; ++j)
+        if (T.c[j] != 0.0) acc += T.c[j] * T.k[j][e];
+      const double err = h * acc;
+      const double sk = atol + rtol * fmax(fabs(u[e]), fabs(u5[e]));
+      const double r = err / sk;
+      sum += r * r;
+    }
+  }
+  red[threadIdx.x] = sum;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// One block per instance: RMS scaled error over its values, accept when <= 1,
+// next step h min(10, max(0.2, 0.9 err^-1/5)) (10 for err = 0), not growing
+// after a rejection; t advances by the step taken.
+__global__ __launch_bounds__(256) void k_dp_control(const int* __restrict__ range,
+                                                    const double* __restrict__ nval,
+                                                    const double* __restrict__ partial, double* dt, double* t,
+                                                    int* rejected, int* accepted, int* n_accepted,
+                                                    double* err_out) {
+  __shared__ double red[256];
+  const int i = blockIdx.x;
+  double s = 0.0;
+  for (int b = range[2 * i] + threadIdx.x; b < range[2 * i + 1]; b += 256) s += partial[b];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double err = sqrt(red[0] / nval[i]);
+  const double h = dt[i];
+  double scale;
+  int acc;
+  if (err <= 1.0) {
+    acc = 1;
+    scale = (err == 0.0) ? 10.0 : fmin(10.0, fmax(0.2, 0.9 * pow(err, -0.2)));
+    if (rejected[i]) scale = fmin(scale, 1.0);
+    t[i] += h;
+    if (n_accepted) n_accepted[i] += 1;
+  } else {
+    acc = 0;
+    scale = fmax(0.2, 0.9 * pow(err, -0.2));
+  }
+  rejected[i] = 1 - acc;
+  accepted[i] = acc;
+  dt[i] = h * scale;
+  if (err_out) err_out[i] = err;
+}
+
+__global__ __launch_bounds__(256) void k_dp_accept(const ShellDev* __restrict__ sh,
+                                                   const PtBlock* __restrict__ blk,
+                                                   const int* __restrict__ accepted,
+                                                   const double* __restrict__ src, double* __restrict__ dst,
+                                                   const double* __restrict__ src2, double* __restrict__ dst2) {
+  const PtBlock b = blk[blockIdx.x];
+  const ShellDev s = sh[b.shell];
+  const int P = s.n_r * s.S;
+  const int q = b.q0 + threadIdx.x;
+  if (q >= P || !accepted[s.instance]) return;
+  const long long e = 50LL * s.pt_off + (long long)blockIdx.y * P + q;
+  dst[e] = src[e];
+  if (dst2) dst2[e] = src2[e];
+}
+
+__global__ __launch_bounds__(256) void k_fill_int(int* __restrict__ x, int n, int v) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
 }  // namespace
 
 namespace ghk {
@@ -1078,6 +1206,47 @@ hipError_t nonfinite_count(const double* x, long long n, int* count, hipStream_t
   long long nb = (n + 255) / 256;
   int grid = (int)(nb < 4096 ? nb : 4096);
   hipLaunchKernelGGL(k_nonfinite, dim3(grid), dim3(256), 0, st, x, n, count);
+  return hipGetLastError();
+}
+
+hipError_t dp_combine(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* dt, const double* u,
+                      double* const k[7], const double c[7], int nk, double* out, hipStream_t st) {
+  DpTerms T;
+  for (int j = 0; j < 7; ++j) {
+    T.k[j] = k[j];
+    T.c[j] = (j < nk) ? c[j] : 0.0;
+  }
+  hipLaunchKernelGGL(k_dp_combine, dim3(n_blk, 50), dim3(256), 0, st, sh, blk, dt, u, T, nk, out);
+  return hipGetLastError();
+}
+
+hipError_t dp_error(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* dt, const double* u,
+                    const double* u5, double* const k[7], const double e[7], double atol, double rtol,
+                    double* partial, hipStream_t st) {
+  DpTerms T;
+  for (int j = 0; j < 7; ++j) {
+    T.k[j] = k[j];
+    T.c[j] = e[j];
+  }
+  hipLaunchKernelGGL(k_dp_error, dim3(n_blk), dim3(256), 0, st, sh, blk, dt, u, u5, T, atol, rtol, partial);
+  return hipGetLastError();
+}
+
+hipError_t dp_control(const int* blk_range, int n_inst, const double* nval, const double* partial, double* dt,
+                      double* t, int* rejected, int* accepted, int* n_accepted, double* err, hipStream_t st) {
+  hipLaunchKernelGGL(k_dp_control, dim3(n_inst), dim3(256), 0, st, blk_range, nval, partial, dt, t, rejected,
+                     accepted, n_accepted, err);
+  return hipGetLastError();
+}
+
+hipError_t dp_accept(const ShellDev* sh, const PtBlock* blk, int n_blk, const int* accepted, const double* src,
+                     double* dst, const double* src2, double* dst2, hipStream_t st) {
+  hipLaunchKernelGGL(k_dp_accept, dim3(n_blk, 50), dim3(256), 0, st, sh, blk, accepted, src, dst, src2, dst2);
+  return hipGetLastError();
+}
+
+hipError_t fill_int(int* x, int n, int value, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, st, x, n, value);
   return hipGetLastError();
 }
 

@@ -25,7 +25,7 @@ EXPORTS = [
     "gh_set_background", "gh_set_params", "gh_rhs", "gh_step", "gh_constraints",
     "gh_last_error", "gh_grid_coords", "gh_host_operator", "gh_set_timing", "gh_kernel_stats",
     "gh_query", "gh_rhs_vjp", "gh_step_vjp", "gh_constraints_vjp",
-    "gh_set_graph", "gh_step_stages", "gh_step_vjp_stages",
+    "gh_set_graph", "gh_step_stages", "gh_step_vjp_stages", "gh_step_dp5",
 ]
 
 KERNEL_KINDS = {"deriv_gemm": 0, "filter_gemm": 1, "radial": 2, "pointwise": 3, "boundary": 4,
@@ -81,6 +81,7 @@ def load_library(path=LIB_PATH):
         "gh_constraints_vjp": (i, [vp, vp, vp, vp]),
         "gh_set_graph": (i, [vp, i]),
         "gh_step_stages": (i, [vp, vp, vp, vp, vp]),
+        "gh_step_dp5": (i, [vp, vp, i, d, d, vp, vp, vp, vp, vp]),
         "gh_step_vjp_stages": (i, [vp, vp, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -255,6 +256,28 @@ class GHSolver:
         self._check(self.lib.gh_step_vjp(self.h, self._dev(u_n, 50, "u_n"), self._dev(lam_np1, 50, "lam_np1"),
                                          self._dev(out, 50, "lam_n"), g))
         return out
+
+    def step_dp5(self, u, n_attempts, atol, rtol, t, dt, rejected=None, n_accepted=None, err=None):
+        """n_attempts adaptive Dormand-Prince 5(4) attempts in place on u.
+
+        t, dt: float64 CUDA [n_inst] (updated); rejected: int32 CUDA [n_inst]
+        (in/out: last attempt rejected); n_accepted: int32 CUDA [n_inst]
+        (incremented); err: float64 CUDA [n_inst] (last attempt's error norms).
+        """
+        torch = self._torch
+        for name, x, dtype in (("t", t, torch.float64), ("dt", dt, torch.float64),
+                               ("rejected", rejected, torch.int32),
+                               ("n_accepted", n_accepted, torch.int32), ("err", err, torch.float64)):
+            if x is None and name in ("t", "dt"):
+                raise TypeError(f"{name} is required")
+            if x is not None and (not x.is_cuda or x.dtype != dtype or x.numel() != self.n_inst
+                                  or not x.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor with n_inst elements")
+        self._sync_stream()
+        ptr = lambda x: ctypes.c_void_p(x.data_ptr()) if x is not None else None
+        self._check(self.lib.gh_step_dp5(self.h, self._dev(u, 50, "u"), int(n_attempts), float(atol), float(rtol),
+                                         ptr(t), ptr(dt), ptr(rejected), ptr(n_accepted), ptr(err)))
+        return u
 
     def step_stages(self, u, u1, u2, derivs=None):
         """One step in place on u, storing the stage states into u1, u2 and,
