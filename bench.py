@@ -13,7 +13,8 @@ measurements on the same GPU: the same steps replayed from a captured HIP
 graph; the adjoint/forward cost ratio of a 200-step evolution with gradients
 of the final constraint norm (checkpoint every 20 steps); 64 heterogeneous
 Kerr holes in one context against one context per hole; the 20-shell L = 31
-domain (forward rate, and the adjoint/forward ratio on a 4-instance batch).
+domain (forward rate, and the adjoint/forward ratio on a 4-instance batch);
+adaptive Dormand-Prince 5(4) stepping of the 8-shell workload.
 
 Prints one JSON line (rank 0).  With --gpus > 1 it exits: this build runs on
 one GPU.
@@ -40,7 +41,7 @@ def log(msg):
 
 
 PROFILE = os.path.join(ROOT, "profiles", "pulse_8shell_step_kernels.md")
-KERNEL_SOURCES = ["ghmi_gemm.hip", "ghmi_internal.h"]
+KERNEL_SOURCES = ["ghmi_gemm.hip", "ghmi_gemm.h"]
 
 
 def gemm_traffic(variant, order):
@@ -181,6 +182,32 @@ def batched_comparison(steps):
     return out
 
 
+def dp5_measurement(solver, u0_dev, wl, attempts=40, atol=1e-8, rtol=1e-8):
+    """Adaptive Dormand-Prince 5(4) on the same workload: RHS evaluations per
+    second and physical time advanced per second, next to the fixed-step RK3."""
+    import torch
+    n = wl.n_inst
+    u = u0_dev.clone()
+    t = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+    dt = torch.tensor(wl.dt, dtype=torch.float64, device="cuda:0")
+    rej = torch.zeros(n, dtype=torch.int32, device="cuda:0")
+    na = torch.zeros(n, dtype=torch.int32, device="cuda:0")
+    solver.step_dp5(u, 5, atol, rtol, t, dt, rejected=rej, n_accepted=na)
+    torch.cuda.synchronize()
+    t0v, na0 = t.clone(), na.clone()
+    t0 = time.perf_counter()
+    solver.step_dp5(u, attempts, atol, rtol, t, dt, rejected=rej, n_accepted=na)
+    torch.cuda.synchronize()
+    w = time.perf_counter() - t0
+    rhs_per_attempt = 7 if wl.filter_params else 6
+    acc = int((na - na0).sum())
+    adv = float((t - t0v).sum())
+    return {"attempts": attempts, "accepted": acc, "atol": atol, "rtol": rtol, "ms_per_attempt": w / attempts * 1e3,
+            "rhs_per_attempt": rhs_per_attempt, "value": solver.P * rhs_per_attempt * attempts / w,
+            "unit": "grid-point RHS evals/s", "mean_accepted_dt": adv / max(acc, 1),
+            "physical_time_per_s": adv / w, "rk3_dt": float(wl.dt[0])}
+
+
 def warm_adjoint(solver, u):
     """One RHS transpose before timing: its first call allocates the reverse
     work space and tunes the transposed GEMMs (setup, like the forward's
@@ -257,6 +284,7 @@ def main():
     ap.add_argument("--cpu-rhs", type=int, default=3, help="oracle RHS evaluations for cpu_baseline (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-hole batched comparison")
+    ap.add_argument("--no-dp5", action="store_true", help="skip the adaptive Dormand-Prince measurement")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 20-shell L = 31 domain (forward, and the adjoint of a 4-instance batch)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -357,6 +385,11 @@ def main():
         "graph_value": P * 3 * args.steps / t_graph,
     }
     log(f"timed {args.steps} steps: {t * 1e3 / args.steps:.3f} ms/step; graph {t_graph * 1e3 / args.steps:.3f} ms/step")
+    out["rk3_physical_time_per_s"] = float(wl.dt[0]) * args.steps / t
+    if not args.no_dp5:
+        out["dp5"] = dp5_measurement(solver, dev(u0), wl)
+        log(f"dp5: {out['dp5']['ms_per_attempt']:.3f} ms/attempt, {out['dp5']['accepted']} of "
+            f"{out['dp5']['attempts']} accepted, mean dt {out['dp5']['mean_accepted_dt']:.3e}")
     if not args.no_adjoint:
         out["adjoint"] = adjoint_ratio(solver, dev(u0), wl)
         log(f"adjoint ratio {out['adjoint']['ratio']:.2f}")

@@ -1,0 +1,37 @@
+// Grouped FP64 GEMM of the derivative and filter operators (ghmi_gemm.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+// One GEMM problem of a grouped launch: C[M x N] = A[M x K] * B[K x N], row-major,
+// with A = Abase + a_off and C = Cbase + c_off (the bases are launch arguments,
+// so one tile list serves any state / work-space pair).
+struct GemmGroup {
+  long long a_off;
+  long long c_off;
+  const double* B;
+  int M, N, K;
+  int lda, ldb, ldc;
+};
+
+// One output tile of a grouped GEMM launch.
+struct GemmTile {
+  int g;              // group index
+  int m0, n0;         // tile origin
+  int pad;
+};
+
+namespace ghk {
+
+// Grouped GEMM (ghmi_gemm.hip).  shape: index of a kernel variant (tile
+// BM x BN, wave layout, LDS layout of A); order: 0 column blocks or 1 row
+// blocks per XCD.  role: 0 angular derivative, 1 filter, 2 transposed
+// derivative (C += A B), 3 transposed filter (separate kernel symbols).
+enum { NUM_TILE_SHAPES = 10 };
+void tile_dims(int shape, int* bm, int* bn);
+std::vector<GemmTile> build_tiles(const std::vector<GemmGroup>& groups, int shape, int order);
+hipError_t gemm(int shape, const GemmTile* tiles, int n_tiles, const GemmGroup* groups,
+                const double* Abase, double* Cbase, hipStream_t st, int role);
+
+}  // namespace ghk

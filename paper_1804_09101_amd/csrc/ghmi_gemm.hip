@@ -6,7 +6,7 @@
 #include <algorithm>
 #include <vector>
 
-#include "ghmi_internal.h"
+#include "ghmi_gemm.h"
 
 namespace {
 
