@@ -208,6 +208,39 @@ def dp5_measurement(solver, u0_dev, wl, attempts=40, atol=1e-8, rtol=1e-8):
             "physical_time_per_s": adv / w, "rk3_dt": float(wl.dt[0])}
 
 
+def transform_measurement(solver, u0_dev, steps):
+    """The same RK3 steps with the angular operators applied by transforms
+    (gh_set_angular 1): eager with per-kind timing, and from a graph."""
+    import torch
+    from paper_1804_09101_amd import ghmi
+    solver.set_angular(1)
+    u = u0_dev.clone()
+    solver.step(u, 5)
+    torch.cuda.synchronize()
+    solver.set_timing(True)
+    t0 = time.perf_counter()
+    solver.step(u, steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    stats = {k: solver.kernel_stats(k) for k in ghmi.KERNEL_KINDS}
+    solver.set_timing(False)
+    solver.set_graph(True)
+    ug = u0_dev.clone()
+    solver.step(ug, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.step(ug, steps)
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    solver.set_graph(False)
+    solver.set_angular(0)
+    P = solver.P
+    return {"value": P * 3 * steps / t, "graph_value": P * 3 * steps / tg, "unit": "grid-point RHS evals/s",
+            "ms_per_step": t / steps * 1e3, "steps": steps,
+            "kernels": {k: {"launches": n, "avg_us": (ms / n * 1e3 if n else None)} for k, (n, ms) in stats.items()
+                        if n}}
+
+
 def warm_adjoint(solver, u):
     """One RHS transpose before timing: its first call allocates the reverse
     work space and tunes the transposed GEMMs (setup, like the forward's
@@ -251,6 +284,18 @@ def large_measurement(steps, adj_steps, k):
                "deriv_gemm_avg_us": ms_g / n_g * 1e3, "deriv_gemm_tflops": flops / (ms_g / n_g / 1e3) / 1e12,
                "deriv_variant": s.query(6), "deriv_order": s.query(4)}
         log(f"large {name}: {steps} steps in {t:.2f} s")
+        s.set_angular(1)
+        ut = dev(u0)
+        s.step(ut, 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(ut, steps)
+        torch.cuda.synchronize()
+        tt = time.perf_counter() - t0
+        s.set_angular(0)
+        del ut
+        rec["transform"] = {"ms_per_step": tt / steps * 1e3, "value": s.P * 3 * steps / tt}
+        log(f"large {name}: transform {steps} steps in {tt:.2f} s")
         if name == "batch4":
             warm_adjoint(s, u)
             gamma = torch.tensor(wl.gamma, dtype=torch.float64, requires_grad=True)
@@ -386,6 +431,9 @@ def main():
     }
     log(f"timed {args.steps} steps: {t * 1e3 / args.steps:.3f} ms/step; graph {t_graph * 1e3 / args.steps:.3f} ms/step")
     out["rk3_physical_time_per_s"] = float(wl.dt[0]) * args.steps / t
+    out["transform"] = transform_measurement(solver, dev(u0), args.steps)
+    log(f"transform: {out['transform']['ms_per_step']:.3f} ms/step, graph "
+        f"{P * 3 * args.steps / out['transform']['graph_value'] / args.steps * 1e3:.3f} ms/step")
     if not args.no_dp5:
         out["dp5"] = dp5_measurement(solver, dev(u0), wl)
         log(f"dp5: {out['dp5']['ms_per_attempt']:.3f} ms/attempt, {out['dp5']['accepted']} of "

@@ -141,6 +141,20 @@ int gh_step(gh_ctx* ctx, double* u, int n_steps);
 int gh_step_dp5(gh_ctx* ctx, double* u, int n_attempts, double atol, double rtol, double* t, double* dt,
                 int* rejected, int* n_accepted, double* err);
 
+/* How the angular derivatives and the angular filter are applied.
+ * method 0 (default): the dense S x S operators as one grouped FP64-MFMA GEMM
+ * (eq. DifferentiatorI1S2).  method 1: the same operators factorised by
+ * azimuthal order (the paper's transform route: PhysToSpec, coefficient
+ * operation, SpecToPhys): a Fourier analysis along phi (GEMM with a
+ * [2n x 2n] table, n = L+1), per order m the n x n theta kernels of
+ * d/dtheta, d/dphi or the filter, and a Fourier synthesis (GEMM), about
+ * 4 (L+1)^3 instead of 4 (L+1)^4 multiply-adds per field and radius.  Both
+ * give the same values up to rounding.  The reverse pass (the *_vjp calls)
+ * uses the dense transposed operators in either method.  The first call with
+ * method 1 builds its tables and tunes its GEMMs (synchronous); a step graph
+ * is recaptured after a change. */
+int gh_set_angular(gh_ctx* ctx, int method);
+
 /* Graph mode for gh_step (default off).  When on, the first gh_step on a
  * state pointer captures one whole SSP-RK3 step (every kernel of the three
  * stages and the filter, for all shells of all instances) into a HIP graph on
@@ -209,8 +223,10 @@ int gh_constraints_vjp(gh_ctx* ctx, const double* u, const double* lam_norm, dou
  * kind 0: angular derivative GEMM; 1: filter GEMM; 2: radial derivative;
  *      3: pointwise GH RHS; 4: boundary treatment (in gh_step together with
  *      the RK3 stage update); 5: RK3 stage combinations of the reverse pass;
- *      6: pointwise reverse pass; 7: transposed angular derivative GEMM. */
-#define GH_NUM_KERNEL_KINDS 8
+ *      6: pointwise reverse pass; 7: transposed angular derivative GEMM;
+ *      8: angular derivatives by transforms (gh_set_angular 1: the three
+ *      launches of one derivative pass counted as one). */
+#define GH_NUM_KERNEL_KINDS 9
 int gh_set_timing(gh_ctx* ctx, int enable);
 int gh_kernel_stats(gh_ctx* ctx, int kind, long long* launches, double* total_ms);
 
@@ -221,7 +237,7 @@ int gh_kernel_stats(gh_ctx* ctx, int kind, long long* launches, double* total_ms
  * (0: each XCD takes whole column blocks, 1: whole row blocks); 5: the same
  * for the filter GEMM; 6: kernel variant of the derivative GEMM (index into
  * the library's list of tile shape, wave layout and LDS layout); 7: the same
- * for the filter GEMM (-1 without filter). */
+ * for the filter GEMM (-1 without filter); 8: the angular method (gh_set_angular). */
 int gh_query(const gh_ctx* ctx, int what, long long* value);
 
 /* Message of the last error on this context (never NULL). */

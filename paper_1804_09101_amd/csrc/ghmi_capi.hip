@@ -74,6 +74,15 @@ struct gh_ctx {
   // Dormand-Prince work space (allocated on first use): seven stage
   // derivatives, the stage state, the fifth-order solution, its filtered copy,
   // per-instance flags and value counts
+  // transform path of the angular operators (gh_set_angular 1, built on first use)
+  int ang_method = 0;
+  bool have_tr = false;
+  double *d_ktab = nullptr, *d_X = nullptr;
+  PtBlock* d_tblk = nullptr;                 // blocks of the theta step: 16 rows x 256 (node, column) pairs
+  int n_tblk = 0, tr_nmax = 0;
+  std::map<int, double*> d_fana, d_fsyn;    // per L: Fourier analysis [2n][2n] and synthesis (its transpose)
+  GemmPlan tr_ana, tr_syn, tr_fsyn;
+
   bool have_dp5 = false;
   double *d_dpk = nullptr, *d_dpy = nullptr, *d_dpu5 = nullptr, *d_dpf = nullptr, *d_dpnval = nullptr;
   int *d_dprej = nullptr, *d_dpacc = nullptr;
@@ -180,6 +189,16 @@ void free_domain(gh_ctx* c) {
   c->d_u1 = c->d_u2 = c->d_lam3 = c->d_mu1 = c->d_mu2 = nullptr;
   c->d_gpart = c->d_bcg = nullptr;
   c->d_C = c->d_norm = nullptr;
+  c->ang_method = 0;
+  c->have_tr = false;
+  c->d_ktab = c->d_X = nullptr;
+  c->d_tblk = nullptr;
+  c->n_tblk = c->tr_nmax = 0;
+  c->d_fana.clear();
+  c->d_fsyn.clear();
+  c->tr_ana = GemmPlan();
+  c->tr_syn = GemmPlan();
+  c->tr_fsyn = GemmPlan();
   c->have_dp5 = false;
   c->d_dpk = c->d_dpy = c->d_dpu5 = c->d_dpf = c->d_dpnval = nullptr;
   c->d_dprej = c->d_dpacc = nullptr;
@@ -304,7 +323,16 @@ int validate_shells(int n_inst, int n_shells, const gh_shell* s, std::string& wh
 int queue_derivs(gh_ctx* c, const double* u, double* dR = nullptr, double* dA = nullptr) {
   if (!dR) dR = c->d_dR;
   if (!dA) dA = c->d_dA;
-  {
+  if (c->ang_method == 1) {
+    // Fourier analysis into the RHS work space (free until the pointwise
+    // kernel), theta kernels, synthesis into dA
+    Timed t(c, 8);
+    HIPCHK(c, ghk::gemm(c->tr_ana.shape, c->tr_ana.d_tiles, c->tr_ana.n_tiles, c->tr_ana.d_groups, u, c->d_W,
+                        c->stream, 4));
+    HIPCHK(c, ghk::ang_theta(c->tr_nmax, c->d_sh, c->d_tblk, c->n_tblk, c->d_ktab, c->d_W, c->d_X, 0, c->stream));
+    HIPCHK(c, ghk::gemm(c->tr_syn.shape, c->tr_syn.d_tiles, c->tr_syn.n_tiles, c->tr_syn.d_groups, c->d_X, dA,
+                        c->stream, 5));
+  } else {
     Timed t(c, 0);
     HIPCHK(c, ghk::gemm(c->deriv.shape, c->deriv.d_tiles, c->deriv.n_tiles, c->deriv.d_groups, u, dA, c->stream,
                         0));
@@ -316,6 +344,23 @@ int queue_derivs(gh_ctx* c, const double* u, double* dR = nullptr, double* dA = 
                                 c->stream));
     else
       HIPCHK(c, ghk::radial(c->d_sh, c->d_blk, c->n_blk, c->d_dtab, u, dR, 0, 50, c->stream));
+  }
+  return GH_OK;
+}
+
+// The angular filter of a whole state, src -> dst (distinct); uses the RHS work
+// space in the transform method.
+int queue_filter(gh_ctx* c, const double* src, double* dst) {
+  Timed t(c, 1);
+  if (c->ang_method == 1) {
+    HIPCHK(c, ghk::gemm(c->tr_ana.shape, c->tr_ana.d_tiles, c->tr_ana.n_tiles, c->tr_ana.d_groups, src, c->d_W,
+                        c->stream, 4));
+    HIPCHK(c, ghk::ang_theta(c->tr_nmax, c->d_sh, c->d_tblk, c->n_tblk, c->d_ktab, c->d_W, c->d_X, 1, c->stream));
+    HIPCHK(c, ghk::gemm(c->tr_fsyn.shape, c->tr_fsyn.d_tiles, c->tr_fsyn.n_tiles, c->tr_fsyn.d_groups, c->d_X, dst,
+                        c->stream, 5));
+  } else {
+    HIPCHK(c, ghk::gemm(c->filter.shape, c->filter.d_tiles, c->filter.n_tiles, c->filter.d_groups, src, dst,
+                        c->stream, 1));
   }
   return GH_OK;
 }
@@ -365,11 +410,8 @@ int queue_step(gh_ctx* c, double* u) {
   if ((rc = queue_stage(c, 0.75, u, 0.25, c->d_ua, c->d_ub))) return rc;
   double* dst = filt ? c->d_ua : u;
   if ((rc = queue_stage(c, 1.0 / 3.0, u, 2.0 / 3.0, c->d_ub, dst))) return rc;
-  if (filt) {
-    Timed t(c, 1);
-    HIPCHK(c, ghk::gemm(c->filter.shape, c->filter.d_tiles, c->filter.n_tiles, c->filter.d_groups, c->d_ua, u,
-                        c->stream, 1));
-  }
+  if (filt)
+    if ((rc = queue_filter(c, c->d_ua, u))) return rc;
   return GH_OK;
 }
 
@@ -540,6 +582,7 @@ int gh_set_domain(gh_ctx* c, int n_inst, int n_shells, const gh_shell* shells, i
     d.ang_off = ang_off[s.L];
     d.rad_off = int(radtab.size() / 2);
     d.dscale = 2.0 / (s.r_out - s.r_in);
+    d.kt_off = -1;
     bool last = (k == n_shells - 1) || shells[k + 1].instance != s.instance;
     bool first = (k == 0) || shells[k - 1].instance != s.instance;
     d.outer = last ? 1 : 0;
@@ -815,6 +858,106 @@ int gh_step(gh_ctx* c, double* u, int n_steps) {
   return GH_OK;
 }
 
+namespace {
+
+// Tables, work space and tuned GEMM plans of the transform path.
+int ensure_transform(gh_ctx* c) {
+  if (c->have_tr) return GH_OK;
+  int rc;
+  std::map<int, long long> kt_off;
+  std::vector<double> ktab;
+  for (int k = 0; k < c->n_shells; ++k) {
+    const int L = c->shells[k].L;
+    if (kt_off.count(L)) continue;
+    kt_off[L] = (long long)ktab.size();
+    std::vector<double> none;
+    for (int which = 0; which < 3; ++which) {
+      std::vector<double> sig = (which == 2 && c->filter_kind == 1)
+                                    ? ghsetup::exp_filter_sigma(L, c->filt[0], c->filt[1], c->filt[2])
+                                    : std::vector<double>(L + 1, 1.0);
+      auto K = ghsetup::sphere_factors(L, which, sig);
+      ktab.insert(ktab.end(), K.begin(), K.end());
+    }
+    const int n = L + 1;
+    auto T = ghsetup::fourier_table(L);
+    std::vector<double> TT(T.size());
+    for (int a = 0; a < 2 * n; ++a)
+      for (int b = 0; b < 2 * n; ++b) TT[size_t(b) * 2 * n + a] = T[size_t(a) * 2 * n + b];
+    double *dA = nullptr, *dS = nullptr;
+    if ((rc = upload(c, &dA, T))) return rc;
+    if ((rc = upload(c, &dS, TT))) return rc;
+    c->d_fana[L] = dA;
+    c->d_fsyn[L] = dS;
+  }
+  if ((rc = upload(c, &c->d_ktab, ktab))) return rc;
+  for (int k = 0; k < c->n_shells; ++k) c->h_sh[k].kt_off = kt_off[c->shells[k].L];
+  HIPCHK(c, hipMemcpy(c->d_sh, c->h_sh.data(), c->h_sh.size() * sizeof(ShellDev), hipMemcpyHostToDevice));
+  if ((rc = dalloc(c, &c->d_X, size_t(100) * c->P))) return rc;
+  // theta-step blocks: per shell, chunks of 16 (field, radius) rows x 256 (node, column) pairs
+  std::vector<PtBlock> tb;
+  int maxn = 0;
+  for (int k = 0; k < c->n_shells; ++k) {
+    const int S = c->h_sh[k].S, rows = 50 * c->shells[k].n_r;
+    maxn = std::max(maxn, c->shells[k].L + 1);
+    for (int r0 = 0; r0 < rows; r0 += 16)
+      for (int a0 = 0; a0 < S; a0 += 256) tb.push_back(PtBlock{k, r0 * S + a0});
+  }
+  c->tr_nmax = maxn <= 16 ? 16 : (maxn <= 32 ? 32 : 64);
+  c->n_tblk = int(tb.size());
+  if ((rc = upload(c, &c->d_tblk, tb))) return rc;
+  // plans over maximal runs of consecutive shells with the same L: a state is
+  // a [rows * n x 2n] matrix (rows = (field, radius) pairs), the theta output a
+  // [rows * 2n x 2n] one laid out like the angular derivatives
+  for (int k = 0; k < c->n_shells;) {
+    const int L = c->shells[k].L, n = L + 1;
+    int k1 = k, rows = 0;
+    while (k1 < c->n_shells && c->shells[k1].L == L) { rows += 50 * c->shells[k1].n_r; ++k1; }
+    GemmGroup ga;
+    ga.a_off = 50LL * c->offs[k];
+    ga.c_off = 50LL * c->offs[k];
+    ga.B = c->d_fana[L];
+    ga.M = rows * n; ga.N = 2 * n; ga.K = 2 * n;
+    ga.lda = 2 * n; ga.ldb = 2 * n; ga.ldc = 2 * n;
+    c->tr_ana.groups.push_back(ga);
+    GemmGroup gs = ga;
+    gs.a_off = 100LL * c->offs[k];
+    gs.c_off = 100LL * c->offs[k];
+    gs.B = c->d_fsyn[L];
+    gs.M = rows * 2 * n;
+    c->tr_syn.groups.push_back(gs);
+    GemmGroup gf = ga;
+    gf.B = c->d_fsyn[L];
+    c->tr_fsyn.groups.push_back(gf);
+    k = k1;
+  }
+  const size_t F50 = size_t(50) * c->P;
+  HIPCHK(c, ghk::fill_pattern(c->d_ua, (long long)F50, c->stream));
+  HIPCHK(c, ghk::fill_pattern(c->d_X, (long long)(2 * F50), c->stream));
+  if ((rc = autotune(c, c->tr_ana, c->d_ua, c->d_ub, 4))) return rc;
+  if ((rc = autotune(c, c->tr_syn, c->d_X, c->d_dA, 5))) return rc;
+  if (c->filter_kind == 1)
+    if ((rc = autotune(c, c->tr_fsyn, c->d_X, c->d_ub, 5))) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->have_tr = true;
+  return GH_OK;
+}
+
+}  // namespace
+
+int gh_set_angular(gh_ctx* c, int method) {
+  if (!c) return GH_ERR_ARG;
+  if (!c->have_domain) return fail(c, GH_ERR_ORDER, "gh_set_domain has not been called");
+  if (method != 0 && method != 1) return fail(c, GH_ERR_ARG, "method must be 0 (dense) or 1 (transform)");
+  HIPCHK(c, hipSetDevice(c->device));
+  if (method == 1) {
+    int rc = ensure_transform(c);
+    if (rc) return rc;
+  }
+  if (method != c->ang_method) drop_graph(c);
+  c->ang_method = method;
+  return GH_OK;
+}
+
 int gh_set_graph(gh_ctx* c, int enable) {
   if (!c) return GH_ERR_ARG;
   HIPCHK(c, hipSetDevice(c->device));
@@ -911,11 +1054,8 @@ int gh_step_stages(gh_ctx* c, double* u, double* u1, double* u2, double* derivs)
   if ((rc = queue_stage(c, 0.75, u, 0.25, u1, u2, derivs ? derivs + F150 : nullptr))) return rc;
   double* dst = filt ? c->d_ua : u;
   if ((rc = queue_stage(c, 1.0 / 3.0, u, 2.0 / 3.0, u2, dst, derivs ? derivs + 2 * F150 : nullptr))) return rc;
-  if (filt) {
-    Timed t(c, 1);
-    HIPCHK(c, ghk::gemm(c->filter.shape, c->filter.d_tiles, c->filter.n_tiles, c->filter.d_groups, c->d_ua, u,
-                        c->stream, 1));
-  }
+  if (filt)
+    if ((rc = queue_filter(c, c->d_ua, u))) return rc;
   return GH_OK;
 }
 
@@ -1002,6 +1142,7 @@ int gh_query(const gh_ctx* c, int what, long long* value) {
     case 5: *value = c->filter_kind == 1 ? c->filter.order : 0; break;
     case 6: *value = c->deriv.shape; break;
     case 7: *value = c->filter_kind == 1 ? c->filter.shape : -1; break;
+    case 8: *value = c->ang_method; break;
     default: return GH_ERR_ARG;
   }
   return GH_OK;
@@ -1131,11 +1272,7 @@ int gh_step_dp5(gh_ctx* c, double* u, int n_attempts, double atol, double rtol, 
     HIPCHK(c, ghk::dp_control(c->d_inst_range, c->n_inst, c->d_dpnval, c->d_partial, dt, t, rej, c->d_dpacc,
                               n_accepted, err, c->stream));
     if (filt) {
-      {
-        Timed tm(c, 1);
-        HIPCHK(c, ghk::gemm(c->filter.shape, c->filter.d_tiles, c->filter.n_tiles, c->filter.d_groups, c->d_dpu5,
-                            c->d_dpf, c->stream, 1));
-      }
+      if ((rc = queue_filter(c, c->d_dpu5, c->d_dpf))) return rc;
       HIPCHK(c, ghk::dp_accept(c->d_sh, c->d_blk, c->n_blk, c->d_dpacc, c->d_dpf, u, nullptr, nullptr, c->stream));
     } else {
       HIPCHK(c, ghk::dp_accept(c->d_sh, c->d_blk, c->n_blk, c->d_dpacc, c->d_dpu5, u, K[6], K[0], c->stream));

@@ -18,6 +18,7 @@ struct ShellDev {
   int outer;          // 1: outer face is the outer boundary of its instance
   int inner;          // 1: inner face is an excision boundary
   double dscale;      // d/dr = dscale * d/dxi, dscale = 2/(r_out - r_in)
+  long long kt_off;   // offset of this L's per-order theta kernels in the transform table (-1: none)
 };
 
 // A block of up to 256 consecutive points inside one shell.
@@ -45,6 +46,17 @@ hipError_t dp_control(const int* blk_range, int n_inst, const double* nval, cons
 hipError_t dp_accept(const ShellDev* sh, const PtBlock* blk, int n_blk, const int* accepted, const double* src,
                      double* dst, const double* src2, double* dst2, hipStream_t st);
 hipError_t fill_int(int* x, int n, int value, hipStream_t st);
+
+// Per-order theta kernels of the transform path of the angular operators.
+// AB: Fourier coefficients of every row ([50] layout, per (field, radius)
+// row the [n][2n] array of cos | sin coefficients).  mode 0: X ([100] layout)
+// receives per row the d/dtheta coefficients and the d/dphi ones with the
+// cos and sin halves exchanged and negated as the synthesis needs;
+// mode 1: X ([50] layout) receives the filtered coefficients.  tblk: blocks
+// (shell, q0 = first row * S + first (theta node, column) pair) of 16 rows x
+// 256 pairs; nmax: 16, 32 or 64 >= L + 1 of every shell.
+hipError_t ang_theta(int nmax, const ShellDev* sh, const PtBlock* tblk, int n_tblk, const double* ktab,
+                     const double* AB, double* X, int mode, hipStream_t st);
 
 hipError_t fill_pattern(double* x, long long n, hipStream_t st);
 

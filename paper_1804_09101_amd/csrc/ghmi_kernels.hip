@@ -59,22 +59,26 @@ __global__ __launch_bounds__(256) void k_radial_col(const ShellDev* __restrict__
   // the n x n matrix is the same for every thread: stage it in LDS once and
   // read it with broadcast loads
   __shared__ double D[MAXR * MAXR];
-  for (int i = threadIdx.x; i < n * n; i += blockDim.x) D[i] = dtab[s.d_off + i];
+  for (int i = threadIdx.x; i < MAXR * MAXR; i += blockDim.x) {
+    const int r = i / MAXR, rp = i - r * MAXR;
+    const int src = TRANS ? rp * n + r : r * n + rp;      // (row r, column rp) of D or D^T
+    D[i] = (r < n && rp < n) ? dtab[s.d_off + src] : 0.0;
+  }
   __syncthreads();
   const int a = b.q0 + threadIdx.x;
   if (a >= s.S) return;
   const int f = f0 + blockIdx.y;
   const long long base = 50LL * s.pt_off + (long long)f * n * s.S + a;
   double col[MAXR];
+  // unconditional loads (index clamped; the padded matrix entries are zero)
 #pragma unroll
-  for (int r = 0; r < MAXR; ++r) col[r] = (r < n) ? u[base + (long long)r * s.S] : 0.0;
+  for (int r = 0; r < MAXR; ++r) col[r] = u[base + (long long)min(r, n - 1) * s.S];
 #pragma unroll
   for (int r = 0; r < MAXR; ++r) {
     if (r < n) {
       double acc = 0.0;
 #pragma unroll
-      for (int rp = 0; rp < MAXR; ++rp)
-        if (rp < n) acc += (TRANS ? D[rp * n + r] : D[r * n + rp]) * col[rp];
+      for (int rp = 0; rp < MAXR; ++rp) acc += D[r * MAXR + rp] * col[rp];
       double* o = dR + base + (long long)r * s.S;
       if (ACC) *o += s.dscale * acc;
       else *o = s.dscale * acc;
@@ -1052,6 +1056,67 @@ __global__ __launch_bounds__(256) void k_fill_int(int* __restrict__ x, int n, in
   if (i < n) x[i] = v;
 }
 
+// ---------------------------------------------------------------------------
+// Transform path of the angular operators: the theta step.  Per (field,
+// radius) row the Fourier coefficients AB[i'][m'] (n = L+1 theta nodes i',
+// columns m' < n the cos(m phi) coefficients, m' >= n the sin(m phi) ones,
+// m = m' mod n) are mapped by the per-order theta kernels K_m[i][i'].  One
+// thread owns a (theta node i, column m') pair: it keeps the kernel rows it
+// needs in registers and sweeps a chunk of ROWS rows, so the kernel table is
+// read once per thread and the coefficient loads are coalesced over m'.
+// Block (shell, q0 = r0 * S + a0): rows r0.., pairs a0 .. a0 + 255.
+// ktab (per L at kt_off): [3][n][n][n] = d/dtheta, d/dphi, filter kernels.
+// ---------------------------------------------------------------------------
+template <int NMAX, int MODE>
+__global__ __launch_bounds__(256) void k_ang_theta(const ShellDev* __restrict__ sh,
+                                                   const PtBlock* __restrict__ tblk,
+                                                   const double* __restrict__ ktab,
+                                                   const double* __restrict__ AB, double* __restrict__ X) {
+  constexpr int ROWS = 16;
+  const PtBlock b = tblk[blockIdx.x];
+  const ShellDev s = sh[b.shell];
+  const int n = s.L + 1, nc = 2 * n;
+  const int r0 = b.q0 / s.S;
+  const int a = b.q0 - r0 * s.S + threadIdx.x;
+  if (a >= s.S) return;
+  const int i = a / nc, mp = a - i * nc, m = mp % n;
+  const int nrows = 50 * s.n_r;
+  const long long nn = (long long)n * n;
+  double k0[NMAX], k1[NMAX];
+  const double* __restrict__ K0 = ktab + s.kt_off + (MODE == 0 ? 0 : 2 * (long long)n * nn) + m * nn +
+                                  (long long)i * n;
+#pragma unroll
+  for (int ip = 0; ip < NMAX; ++ip) {
+    k0[ip] = (ip < n) ? K0[ip] : 0.0;
+    k1[ip] = (MODE == 0 && ip < n) ? K0[(long long)n * nn + ip] : 0.0;
+  }
+  const int r1 = min(nrows, r0 + ROWS);
+  for (int r = r0; r < r1; ++r) {
+    const double* __restrict__ col = AB + 50LL * s.pt_off + (long long)r * s.S + mp;
+    // every load is issued unconditionally (index clamped to the last node;
+    // the kernel entries past n are zero) so that they can all be in flight
+    double v[NMAX];
+#pragma unroll
+    for (int ip = 0; ip < NMAX; ++ip) v[ip] = col[(long long)min(ip, n - 1) * nc];
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int ip = 0; ip < NMAX; ++ip) {
+      a0 += k0[ip] * v[ip];
+      if (MODE == 0) a1 += k1[ip] * v[ip];
+    }
+    if (MODE == 0) {
+      double* __restrict__ out = X + 100LL * s.pt_off + (long long)r * 2 * s.S;
+      out[i * nc + mp] = a0;
+      // d/dphi: the cos(m phi) coefficient (m' < n) multiplies sin(m phi) in
+      // the synthesis and the sin one multiplies -cos(m phi)
+      if (mp < n) out[s.S + i * nc + mp + n] = a1;
+      else out[s.S + i * nc + mp - n] = -a1;
+    } else {
+      X[50LL * s.pt_off + (long long)r * s.S + i * nc + mp] = a0;
+    }
+  }
+}
+
 }  // namespace
 
 namespace ghk {
@@ -1247,6 +1312,22 @@ hipError_t dp_accept(const ShellDev* sh, const PtBlock* blk, int n_blk, const in
 
 hipError_t fill_int(int* x, int n, int value, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, st, x, n, value);
+  return hipGetLastError();
+}
+
+hipError_t ang_theta(int nmax, const ShellDev* sh, const PtBlock* tblk, int n_tblk, const double* ktab,
+                     const double* AB, double* X, int mode, hipStream_t st) {
+  dim3 grid(n_tblk), block(256);
+#define GH_ANG(NM)                                                                                        \
+  if (mode == 0) hipLaunchKernelGGL((k_ang_theta<NM, 0>), grid, block, 0, st, sh, tblk, ktab, AB, X);   \
+  else hipLaunchKernelGGL((k_ang_theta<NM, 1>), grid, block, 0, st, sh, tblk, ktab, AB, X);
+  switch (nmax) {
+    case 16: GH_ANG(16) break;
+    case 32: GH_ANG(32) break;
+    case 64: GH_ANG(64) break;
+    default: return hipErrorInvalidValue;
+  }
+#undef GH_ANG
   return hipGetLastError();
 }
 

@@ -166,7 +166,7 @@ std::vector<double> exp_filter_sigma(int L, double eta_c, double alpha, double o
   return sig;
 }
 
-std::vector<double> sphere_operator(int L, int which, const std::vector<double>& sigma) {
+std::vector<double> sphere_factors(int L, int which, const std::vector<double>& sigma) {
   // M = Syn * Ana with Ana[lm][a] = W_a Y_lm(a).  For a fixed order m the two real
   // harmonics of that order combine into a function of the azimuth difference:
   //   sum_{+-m} Y_lm(j) Y_lm(a) = c_m P_l^m(x_j) P_l^m(x_a) cos(m (phi_j - phi_a)),
@@ -175,13 +175,12 @@ std::vector<double> sphere_operator(int L, int which, const std::vector<double>&
   //   d/dphi:    M[j][a] = -W_a sum_m c_m m K_m(i_j, i_a) sin(m dphi)
   //   filter:    M[j][a] = W_a sum_m c_m Ks_m(i_j, i_a) cos(m dphi)
   // with theta kernels K_m = sum_l P_l^m P_l^m, Kd_m = sum_l dP_l^m/dtheta P_l^m and
-  // Ks_m = sum_l sigma_l P_l^m P_l^m.  Cost S^2 (L+1) instead of S^2 (L+1)^2.
+  // Ks_m = sum_l sigma_l P_l^m P_l^m.  Returned: c_m (-m) K_m(i, i') W_i' as [m][i][i'].
   std::vector<double> x, w;
   gauss_legendre(L, x, w);
-  const int nth = L + 1, nph = 2 * (L + 1), S = nth * nph, n = L + 1;
+  const int nth = L + 1, nph = 2 * (L + 1), n = L + 1;
   std::vector<std::vector<double>> P(nth), dP(nth);
   for (int i = 0; i < nth; ++i) legendre_normalised(L, x[i], P[i], dP[i]);
-  // kernels [m][i][i']
   std::vector<double> K(size_t(n) * nth * nth, 0.0);
   for (int m = 0; m <= L; ++m)
     for (int i = 0; i < nth; ++i)
@@ -192,8 +191,28 @@ std::vector<double> sphere_operator(int L, int which, const std::vector<double>&
           const double f = (which == 2) ? sigma[l] : 1.0;
           acc += f * left * P[ip][size_t(l) * n + m];
         }
-        K[(size_t(m) * nth + i) * nth + ip] = acc * (m == 0 ? 1.0 : 2.0) * (which == 1 ? -double(m) : 1.0);
+        K[(size_t(m) * nth + i) * nth + ip] =
+            acc * (m == 0 ? 1.0 : 2.0) * (which == 1 ? -double(m) : 1.0) * (w[ip] * 2.0 * kPi / nph);
       }
+  return K;
+}
+
+std::vector<double> fourier_table(int L) {
+  const int n = L + 1, nph = 2 * n;
+  std::vector<double> T(size_t(nph) * 2 * n);
+  for (int k = 0; k < nph; ++k)
+    for (int m = 0; m < n; ++m) {
+      const double ang = 2.0 * kPi * double((m * k) % nph) / nph;
+      T[size_t(k) * 2 * n + m] = std::cos(ang);
+      T[size_t(k) * 2 * n + n + m] = std::sin(ang);
+    }
+  return T;
+}
+
+std::vector<double> sphere_operator(int L, int which, const std::vector<double>& sigma) {
+  // assembled from the per-order factors: cost S^2 (L+1) instead of S^2 (L+1)^2
+  const int nth = L + 1, nph = 2 * (L + 1), S = nth * nph, n = L + 1;
+  const std::vector<double> K = sphere_factors(L, which, sigma);
   // azimuthal factors for every difference d = k - k' (mod nph)
   std::vector<double> trig(size_t(n) * nph);
   for (int m = 0; m <= L; ++m)
@@ -205,15 +224,13 @@ std::vector<double> sphere_operator(int L, int which, const std::vector<double>&
   for (int ij = 0; ij < nth; ++ij)
     for (int kj = 0; kj < nph; ++kj) {
       double* row = &M[size_t(ij * nph + kj) * S];
-      for (int ia = 0; ia < nth; ++ia) {
-        const double wa = w[ia] * 2.0 * kPi / nph;
+      for (int ia = 0; ia < nth; ++ia)
         for (int ka = 0; ka < nph; ++ka) {
           const int d = ((kj - ka) % nph + nph) % nph;
           double acc = 0.0;
           for (int m = 0; m <= L; ++m) acc += K[(size_t(m) * nth + ij) * nth + ia] * trig[size_t(m) * nph + d];
-          row[ia * nph + ka] = wa * acc;
+          row[ia * nph + ka] = acc;
         }
-      }
     }
   return M;
 }

@@ -23,6 +23,17 @@ void gauss_legendre(int L, std::vector<double>& x, std::vector<double>& w);
 //   which 0: d/dtheta, 1: d/dphi, 2: filter with factors sigma_l (sigma has L+1 entries).
 std::vector<double> sphere_operator(int L, int which, const std::vector<double>& sigma);
 
+// The same operators factorised by azimuthal order m (n = L+1):
+//   M u (i, k) = sum_m sum_i' K_m[i][i'] (cos(m phi_k) A_m(i') + sin(m phi_k) B_m(i'))   (which 0, 2)
+//   M u (i, k) = sum_m sum_i' K_m[i][i'] (sin(m phi_k) A_m(i') - cos(m phi_k) B_m(i'))   (which 1)
+// with A_m(i') = sum_k' cos(m phi_k') u(i', k'), B_m(i') = sum_k' sin(m phi_k') u(i', k').
+// sphere_factors returns K as [m][i][i'] (quadrature weight, c_m and -m folded in).
+std::vector<double> sphere_factors(int L, int which, const std::vector<double>& sigma);
+
+// Fourier table T[k][m'] (N_phi x 2n): cos(m' phi_k) for m' < n, sin((m'-n) phi_k)
+// for m' >= n, at exactly reduced angles.
+std::vector<double> fourier_table(int L);
+
 // Filter factors sigma_l = 1 (l/L <= eta_c), else exp(-alpha((l/L-eta_c)/(1-eta_c))^order).
 std::vector<double> exp_filter_sigma(int L, double eta_c, double alpha, double order);
 

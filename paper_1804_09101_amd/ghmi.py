@@ -25,11 +25,12 @@ EXPORTS = [
     "gh_set_background", "gh_set_params", "gh_rhs", "gh_step", "gh_constraints",
     "gh_last_error", "gh_grid_coords", "gh_host_operator", "gh_set_timing", "gh_kernel_stats",
     "gh_query", "gh_rhs_vjp", "gh_step_vjp", "gh_constraints_vjp",
-    "gh_set_graph", "gh_step_stages", "gh_step_vjp_stages", "gh_step_dp5",
+    "gh_set_graph", "gh_step_stages", "gh_step_vjp_stages", "gh_step_dp5", "gh_set_angular",
 ]
 
 KERNEL_KINDS = {"deriv_gemm": 0, "filter_gemm": 1, "radial": 2, "pointwise": 3, "boundary": 4,
-                "rk_combine_vjp": 5, "pointwise_vjp": 6, "deriv_gemm_T": 7}
+                "rk_combine_vjp": 5, "pointwise_vjp": 6, "deriv_gemm_T": 7,
+                "angular_transform": 8}
 
 
 class GHError(RuntimeError):
@@ -82,6 +83,7 @@ def load_library(path=LIB_PATH):
         "gh_set_graph": (i, [vp, i]),
         "gh_step_stages": (i, [vp, vp, vp, vp, vp]),
         "gh_step_dp5": (i, [vp, vp, i, d, d, vp, vp, vp, vp, vp]),
+        "gh_set_angular": (i, [vp, i]),
         "gh_step_vjp_stages": (i, [vp, vp, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -257,6 +259,10 @@ class GHSolver:
                                          self._dev(out, 50, "lam_n"), g))
         return out
 
+    def set_angular(self, method):
+        """0: dense angular operators (GEMM); 1: factorised by azimuthal order (transforms)."""
+        self._check(self.lib.gh_set_angular(self.h, int(method)))
+
     def step_dp5(self, u, n_attempts, atol, rtol, t, dt, rejected=None, n_accepted=None, err=None):
         """n_attempts adaptive Dormand-Prince 5(4) attempts in place on u.
 
@@ -310,7 +316,7 @@ class GHSolver:
     def query(self, what):
         """0: derivative GEMM tile (BM*1000+BN), 1: filter GEMM tile, 2: derivative tiles, 3: points,
         4: derivative GEMM tile order, 5: filter GEMM tile order, 6: derivative GEMM kernel variant,
-        7: filter GEMM kernel variant."""
+        7: filter GEMM kernel variant, 8: angular method."""
         v = ctypes.c_longlong()
         self._check(self.lib.gh_query(self.h, int(what), ctypes.byref(v)))
         return int(v.value)
