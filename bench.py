@@ -209,11 +209,13 @@ def dp5_measurement(solver, u0_dev, wl, attempts=40, atol=1e-8, rtol=1e-8):
 
 
 def transform_measurement(solver, u0_dev, steps):
-    """The same RK3 steps with the angular operators applied by transforms
-    (gh_set_angular 1): eager with per-kind timing, and from a graph."""
+    """The same RK3 steps with the angular derivatives and filter each applied
+    in the faster of the dense and the transform form on this domain
+    (gh_set_angular 2): eager with per-kind timing, and from a graph."""
     import torch
     from paper_1804_09101_amd import ghmi
-    solver.set_angular(1)
+    solver.set_angular(2)
+    choice = (solver.query(9), solver.query(10))
     u = u0_dev.clone()
     solver.step(u, 5)
     torch.cuda.synchronize()
@@ -235,7 +237,9 @@ def transform_measurement(solver, u0_dev, steps):
     solver.set_graph(False)
     solver.set_angular(0)
     P = solver.P
-    return {"value": P * 3 * steps / t, "graph_value": P * 3 * steps / tg, "unit": "grid-point RHS evals/s",
+    return {"method": "faster of dense and transform per operation (gh_set_angular 2)",
+            "derivatives_by_transform": bool(choice[0]), "filter_by_transform": bool(choice[1]),
+            "value": P * 3 * steps / t, "graph_value": P * 3 * steps / tg, "unit": "grid-point RHS evals/s",
             "ms_per_step": t / steps * 1e3, "steps": steps,
             "kernels": {k: {"launches": n, "avg_us": (ms / n * 1e3 if n else None)} for k, (n, ms) in stats.items()
                         if n}}
@@ -284,7 +288,7 @@ def large_measurement(steps, adj_steps, k):
                "deriv_gemm_avg_us": ms_g / n_g * 1e3, "deriv_gemm_tflops": flops / (ms_g / n_g / 1e3) / 1e12,
                "deriv_variant": s.query(6), "deriv_order": s.query(4)}
         log(f"large {name}: {steps} steps in {t:.2f} s")
-        s.set_angular(1)
+        s.set_angular(2)
         ut = dev(u0)
         s.step(ut, 2)
         torch.cuda.synchronize()
@@ -292,9 +296,11 @@ def large_measurement(steps, adj_steps, k):
         s.step(ut, steps)
         torch.cuda.synchronize()
         tt = time.perf_counter() - t0
+        by_transform = bool(s.query(9))
         s.set_angular(0)
         del ut
-        rec["transform"] = {"ms_per_step": tt / steps * 1e3, "value": s.P * 3 * steps / tt}
+        rec["transform"] = {"ms_per_step": tt / steps * 1e3, "value": s.P * 3 * steps / tt,
+                            "method": "gh_set_angular 2", "derivatives_by_transform": by_transform}
         log(f"large {name}: transform {steps} steps in {tt:.2f} s")
         if name == "batch4":
             warm_adjoint(s, u)

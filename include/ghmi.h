@@ -149,10 +149,12 @@ int gh_step_dp5(gh_ctx* ctx, double* u, int n_attempts, double atol, double rtol
  * [2n x 2n] table, n = L+1), per order m the n x n theta kernels of
  * d/dtheta, d/dphi or the filter, and a Fourier synthesis (GEMM), about
  * 4 (L+1)^3 instead of 4 (L+1)^4 multiply-adds per field and radius.  Both
- * give the same values up to rounding.  The reverse pass (the *_vjp calls)
- * uses the dense transposed operators in either method.  The first call with
- * method 1 builds its tables and tunes its GEMMs (synchronous); a step graph
- * is recaptured after a change. */
+ * give the same values up to rounding.  method 2: for the derivative pass and
+ * for the filter separately, whichever of the two forms is faster on this
+ * domain (both timed on the GPU during the call).  The reverse pass (the *_vjp
+ * calls) uses the dense transposed operators in every method.  The first call
+ * with method 1 or 2 builds the transform tables and tunes their GEMMs
+ * (synchronous); a step graph is recaptured after a change. */
 int gh_set_angular(gh_ctx* ctx, int method);
 
 /* Graph mode for gh_step (default off).  When on, the first gh_step on a
@@ -237,7 +239,8 @@ int gh_kernel_stats(gh_ctx* ctx, int kind, long long* launches, double* total_ms
  * (0: each XCD takes whole column blocks, 1: whole row blocks); 5: the same
  * for the filter GEMM; 6: kernel variant of the derivative GEMM (index into
  * the library's list of tile shape, wave layout and LDS layout); 7: the same
- * for the filter GEMM (-1 without filter); 8: the angular method (gh_set_angular). */
+ * for the filter GEMM (-1 without filter); 8: the angular method (gh_set_angular);
+ * 9, 10: whether the derivative pass / the filter use the transform form. */
 int gh_query(const gh_ctx* ctx, int what, long long* value);
 
 /* Message of the last error on this context (never NULL). */

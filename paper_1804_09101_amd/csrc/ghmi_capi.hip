@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
@@ -76,6 +77,7 @@ struct gh_ctx {
   // per-instance flags and value counts
   // transform path of the angular operators (gh_set_angular 1, built on first use)
   int ang_method = 0;
+  bool deriv_tr = false, filt_tr = false;    // effective choices (method 2 picks each by timing)
   bool have_tr = false;
   double *d_ktab = nullptr, *d_X = nullptr;
   PtBlock* d_tblk = nullptr;                 // blocks of the theta step: 16 rows x 256 (node, column) pairs
@@ -190,6 +192,7 @@ void free_domain(gh_ctx* c) {
   c->d_gpart = c->d_bcg = nullptr;
   c->d_C = c->d_norm = nullptr;
   c->ang_method = 0;
+  c->deriv_tr = c->filt_tr = false;
   c->have_tr = false;
   c->d_ktab = c->d_X = nullptr;
   c->d_tblk = nullptr;
@@ -323,7 +326,7 @@ int validate_shells(int n_inst, int n_shells, const gh_shell* s, std::string& wh
 int queue_derivs(gh_ctx* c, const double* u, double* dR = nullptr, double* dA = nullptr) {
   if (!dR) dR = c->d_dR;
   if (!dA) dA = c->d_dA;
-  if (c->ang_method == 1) {
+  if (c->deriv_tr) {
     // Fourier analysis into the RHS work space (free until the pointwise
     // kernel), theta kernels, synthesis into dA
     Timed t(c, 8);
@@ -352,7 +355,7 @@ int queue_derivs(gh_ctx* c, const double* u, double* dR = nullptr, double* dA = 
 // space in the transform method.
 int queue_filter(gh_ctx* c, const double* src, double* dst) {
   Timed t(c, 1);
-  if (c->ang_method == 1) {
+  if (c->filt_tr) {
     HIPCHK(c, ghk::gemm(c->tr_ana.shape, c->tr_ana.d_tiles, c->tr_ana.n_tiles, c->tr_ana.d_groups, src, c->d_W,
                         c->stream, 4));
     HIPCHK(c, ghk::ang_theta(c->tr_nmax, c->d_sh, c->d_tblk, c->n_tblk, c->d_ktab, c->d_W, c->d_X, 1, c->stream));
@@ -944,17 +947,60 @@ int ensure_transform(gh_ctx* c) {
 
 }  // namespace
 
+namespace {
+
+// Average time of 5 launches of op (after one untimed) on the context's stream.
+int time_op(gh_ctx* c, const std::function<int()>& op, float* ms) {
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  int rc = op();
+  if (rc) return rc;
+  HIPCHK(c, hipEventRecord(e0, c->stream));
+  for (int it = 0; it < 5; ++it)
+    if ((rc = op())) return rc;
+  HIPCHK(c, hipEventRecord(e1, c->stream));
+  HIPCHK(c, hipEventSynchronize(e1));
+  HIPCHK(c, hipEventElapsedTime(ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return GH_OK;
+}
+
+}  // namespace
+
 int gh_set_angular(gh_ctx* c, int method) {
   if (!c) return GH_ERR_ARG;
   if (!c->have_domain) return fail(c, GH_ERR_ORDER, "gh_set_domain has not been called");
-  if (method != 0 && method != 1) return fail(c, GH_ERR_ARG, "method must be 0 (dense) or 1 (transform)");
+  if (method < 0 || method > 2) return fail(c, GH_ERR_ARG, "method must be 0 (dense), 1 (transform) or 2 (faster)");
   HIPCHK(c, hipSetDevice(c->device));
-  if (method == 1) {
-    int rc = ensure_transform(c);
-    if (rc) return rc;
+  int rc;
+  if (method >= 1 && (rc = ensure_transform(c))) return rc;
+  bool dtr = method == 1, ftr = method == 1;
+  if (method == 2) {
+    // time both forms of each operation on this domain (non-zero data in the work arrays)
+    const bool timing = c->timing;
+    c->timing = false;
+    HIPCHK(c, ghk::fill_pattern(c->d_ua, (long long)(size_t(50) * c->P), c->stream));
+    float t_dense = 0, t_tr = 0;
+    c->deriv_tr = false;
+    if ((rc = time_op(c, [&]() { return queue_derivs(c, c->d_ua); }, &t_dense))) return rc;
+    c->deriv_tr = true;
+    if ((rc = time_op(c, [&]() { return queue_derivs(c, c->d_ua); }, &t_tr))) return rc;
+    dtr = t_tr < t_dense;
+    if (c->filter_kind == 1) {
+      c->filt_tr = false;
+      if ((rc = time_op(c, [&]() { return queue_filter(c, c->d_ua, c->d_ub); }, &t_dense))) return rc;
+      c->filt_tr = true;
+      if ((rc = time_op(c, [&]() { return queue_filter(c, c->d_ua, c->d_ub); }, &t_tr))) return rc;
+      ftr = t_tr < t_dense;
+    }
+    c->timing = timing;
   }
-  if (method != c->ang_method) drop_graph(c);
+  if (method != c->ang_method || dtr != c->deriv_tr || ftr != c->filt_tr) drop_graph(c);
   c->ang_method = method;
+  c->deriv_tr = dtr;
+  c->filt_tr = ftr;
   return GH_OK;
 }
 
@@ -1143,6 +1189,8 @@ int gh_query(const gh_ctx* c, int what, long long* value) {
     case 6: *value = c->deriv.shape; break;
     case 7: *value = c->filter_kind == 1 ? c->filter.shape : -1; break;
     case 8: *value = c->ang_method; break;
+    case 9: *value = c->deriv_tr ? 1 : 0; break;
+    case 10: *value = c->filt_tr ? 1 : 0; break;
     default: return GH_ERR_ARG;
   }
   return GH_OK;

@@ -260,7 +260,8 @@ class GHSolver:
         return out
 
     def set_angular(self, method):
-        """0: dense angular operators (GEMM); 1: factorised by azimuthal order (transforms)."""
+        """0: dense angular operators (GEMM); 1: factorised by azimuthal order (transforms);
+        2: the faster of the two for the derivatives and for the filter, timed on this domain."""
         self._check(self.lib.gh_set_angular(self.h, int(method)))
 
     def step_dp5(self, u, n_attempts, atol, rtol, t, dt, rejected=None, n_accepted=None, err=None):
@@ -316,7 +317,7 @@ class GHSolver:
     def query(self, what):
         """0: derivative GEMM tile (BM*1000+BN), 1: filter GEMM tile, 2: derivative tiles, 3: points,
         4: derivative GEMM tile order, 5: filter GEMM tile order, 6: derivative GEMM kernel variant,
-        7: filter GEMM kernel variant, 8: angular method."""
+        7: filter GEMM kernel variant, 8: angular method, 9/10: derivative / filter in transform form."""
         v = ctypes.c_longlong()
         self._check(self.lib.gh_query(self.h, int(what), ctypes.byref(v)))
         return int(v.value)

@@ -148,3 +148,26 @@ def test_transform_large_sampled_shells(large_transform, k):
     diff = np.max(np.abs(g - r))
     print(f"  transform shell {k}: max diff {diff:.3e} / term scale {kappa:.3e} = {diff / kappa:.3e}", flush=True)
     assert diff < 1e-14 * kappa
+
+
+def test_fastest_method_matches_dense_and_rejects_unknown_methods():
+    """Method 2 picks each operation's form by timing; whatever it picks, a
+    filtered multi-shell step equals the dense one to rounding."""
+    rs = configs.geometric_radii(1.8, 12.0, 3)
+    shells = [(0, 9, 7, rs[i], rs[i + 1]) for i in range(3)]
+    wl = _wl("auto_3shell", shells, [(1.0, 0.3, (0.2, 0.3, 0.4))], dt=[0.004], filt=configs.FILTER_DEFAULT)
+    c = Case(wl, pert_amp=1e-3, seed=3)
+    a = dev(c.u0)
+    c.s.step(a, 3)
+    c.s.set_angular(2)
+    assert c.s.query(8) == 2 and c.s.query(9) in (0, 1) and c.s.query(10) in (0, 1)
+    b = dev(c.u0)
+    c.s.step(b, 3)
+    err = float((a - b).abs().max()) / float((a - dev(c.u0)).abs().max())
+    print(f"  method 2 (deriv {c.s.query(9)}, filter {c.s.query(10)}): 3 steps vs dense, err/change {err:.3e}",
+          flush=True)
+    assert err < 1e-10
+    for bad in (-1, 3):
+        with pytest.raises(ghmi.GHError) as ei:
+            c.s.set_angular(bad)
+        assert ei.value.code == -1
