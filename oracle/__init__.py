@@ -20,9 +20,11 @@ Modules:
   gh        pointwise GH algebra: RHS, constraints, characteristic fields
   domain    a stack of shells: Cartesian gradient, boundary treatment,
             SSP-RK3 step, filter, constraint norm
+  tensor_filter  the tensor-coupled angular filter (total angular momentum)
+  dp5       Dormand-Prince 5(4) tableau and step control
 
 All functions accept complex128 inputs so that complex-step differentiation
 gives exact directional derivatives (used as the reference gradient).
 """
 
-from . import grid, spectral, gh, domain  # noqa: F401
+from . import grid, spectral, gh, domain, tensor_filter  # noqa: F401

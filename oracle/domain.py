@@ -18,6 +18,7 @@ from . import grid as _grid
 from . import spectral as _spec
 from . import dp5 as _dp5
 from . import gh as _gh
+from . import tensor_filter as _tf
 
 
 class Shell:
@@ -30,7 +31,10 @@ class Shell:
 class Domain:
     """Shells of one or more independent instances (black holes)."""
 
-    def __init__(self, shells, filter_params=None):
+    def __init__(self, shells, filter_params=None, filter_kind=1):
+        """filter_kind (with filter_params): 1 angular exponential filter of every
+        component, (eta_c, alpha, order); 2 tensor-coupled ExpCheb filter,
+        (eta_c, alpha, order); 3 tensor-coupled Heaviside filter, (eta_c,)."""
         self.shells = list(shells)
         self.grids = [_grid.ShellGrid(s.n_r, s.L, s.r_in, s.r_out) for s in self.shells]
         self.spheres = {}
@@ -42,6 +46,7 @@ class Domain:
         self.offsets = np.concatenate([[0], np.cumsum(self.npts)])
         self.P = int(self.offsets[-1])
         self.filter_params = filter_params
+        self.filter_kind = filter_kind if filter_params is not None else 0
         # interfaces: consecutive shells of one instance
         self.interfaces = []
         for k in range(len(self.shells) - 1):
@@ -193,15 +198,21 @@ class Domain:
 
     # -- filter -------------------------------------------------------------
     def apply_filter(self, u):
-        """Angular exponential filter on every component of every shell."""
+        """The domain's angular filter on every shell: the exponential filter of
+        every component (kind 1) or the tensor-coupled filter (kinds 2, 3)."""
         if self.filter_params is None:
             return u
-        eta_c, alpha, order = self.filter_params
         blocks = self.split(u, 50)
         out = []
         for k, g in enumerate(self.grids):
-            sig = _spec.exp_filter_sigma(g.L, eta_c, alpha, order)
-            out.append(self.spheres[g.L].filter(blocks[k], sig))
+            if self.filter_kind == 1:
+                eta_c, alpha, order = self.filter_params
+                sig = _spec.exp_filter_sigma(g.L, eta_c, alpha, order)
+                out.append(self.spheres[g.L].filter(blocks[k], sig))
+            else:
+                kind = "expcheb" if self.filter_kind == 2 else "heaviside"
+                key = _tf.sigma_function(kind, g.L, self.filter_params)
+                out.append(_tf.apply(self.spheres[g.L], blocks[k], key))
         return self.join(out)
 
     # -- time step ------------------------------------------------------------
