@@ -34,11 +34,9 @@ parameters are.  Readings used here:
   pair); the stored pair components are expanded to the full index range,
   filtered, and read back.
 
-Here the projectors are Lagrange products over the possible eigenvalues,
-P_j = prod_{i != j} (J^2 - i(i+1)) / (j(j+1) - i(i+1)), on dense blocks (one per
-degree l and tensor), and (r x grad)_k is obtained by applying the differential
-operator to every basis function on the grid and taking it back to
-coefficients (exact: it maps degree l to degree l).
+Here the projectors come from the eigendecomposition of J^2 on dense blocks
+(one per degree l and tensor), and the matrices of (r x grad)_k on the real
+Y_lm are the angular-momentum ladder matrices carried to the real basis.
 """
 
 import functools
@@ -56,18 +54,60 @@ GH_TENSORS = [(0, (4, 4), 10), (10, (4, 4), 10), (20, (3, 4, 4), 30)]
 
 @functools.lru_cache(maxsize=None)
 def orbital_generators(L):
-    """Matrices of (r x grad)_k, k = x, y, z, on the real Y_lm coefficients.
+    """Matrices of (r x grad)_k, k = x, y, z, on the real Y_lm coefficients
+    (out, in), [3, (L+1)^2, (L+1)^2].
 
+    (r x grad)_k = i L_k with the angular momentum L = -i r x grad, whose
+    action on the Condon-Shortley harmonics is the textbook one:
+    L_z Y_l^m = m Y_l^m, L_+- Y_l^m = sqrt(l(l+1) - m(m+-1)) Y_l^{m+-1},
+    L_x = (L_+ + L_-)/2, L_y = (L_+ - L_-)/(2i).  The real harmonics of this
+    package (no Condon-Shortley phase) are Y_l0 = Y_l^0 and, for m > 0,
+    sqrt2 Re / Im of (-1)^m Y_l^m; the matrices are carried over by that
+    change of basis.  (Applying the differential operators on the grid gives
+    the same matrices up to quadrature rounding; a test checks it.)"""
+    n = (L + 1) ** 2
+    out = np.zeros((3, n, n))
+    for l in range(L + 1):
+        d = 2 * l + 1
+        ms = np.arange(-l, l + 1)
+        Lp = np.zeros((d, d))
+        for a, m in enumerate(ms[:-1]):
+            Lp[a + 1, a] = np.sqrt(l * (l + 1) - m * (m + 1.0))
+        Lm = Lp.T
+        Lz = np.diag(ms.astype(float))
+        Lc = [0.5 * (Lp + Lm), (Lp - Lm) / 2j, Lz]
+        # columns: real harmonic (index m + l) in terms of Y_l^m
+        C = np.zeros((d, d), dtype=complex)
+        C[l, l] = 1.0
+        for m in range(1, l + 1):
+            ph = (-1.0) ** m
+            # sqrt2 Re((-1)^m Y^m) = ((-1)^m Y^m + Y^-m)/sqrt2, since Y^-m = (-1)^m conj(Y^m)
+            C[l + m, l + m] = ph / np.sqrt(2.0)
+            C[l - m, l + m] = 1.0 / np.sqrt(2.0)
+            # sqrt2 Im((-1)^m Y^m) = ((-1)^m Y^m - Y^-m)/(sqrt2 i)
+            C[l + m, l - m] = ph / (np.sqrt(2.0) * 1j)
+            C[l - m, l - m] = -1.0 / (np.sqrt(2.0) * 1j)
+        Cinv = np.linalg.inv(C)
+        sl = slice(l * l, (l + 1) * (l + 1))
+        for k in range(3):
+            M = Cinv @ (1j * Lc[k]) @ C
+            out[k, sl, sl] = M.real
+    return out
+
+
+def orbital_generators_on_grid(L):
+    """The same matrices from the differential operators applied to every basis
+    function on the grid and taken back to coefficients (quadrature):
     (r x grad)_x = -sin(phi) d_theta - cot(theta) cos(phi) d_phi,
     (r x grad)_y =  cos(phi) d_theta - cot(theta) sin(phi) d_phi,
-    (r x grad)_z =  d_phi.  Returns [3, (L+1)^2, (L+1)^2] (out, in)."""
+    (r x grad)_z =  d_phi."""
     sp = _spec.Sphere(L)
     x, _ = _grid.gauss_legendre(L)
     th = np.arccos(x)
     ph = _grid.phi_nodes(L)
     TH, PH = np.meshgrid(th, ph, indexing="ij")
     cot = np.cos(TH) / np.sin(TH)
-    Y, dT, dP = sp.Y, sp.dY_dth, sp.dY_dph
+    dT, dP = sp.dY_dth, sp.dY_dph
     fields = [-np.sin(PH) * dT - cot * np.cos(PH) * dP,
               np.cos(PH) * dT - cot * np.sin(PH) * dP,
               dP]
@@ -123,36 +163,32 @@ def _spin_range(l, dims):
 
 @functools.lru_cache(maxsize=None)
 def filter_block(L, l, dims, sigma_key):
-    """sum_j sigma(j) P_j on the degree-l block, P_j by Lagrange products.
+    """sum_j sigma(j) P_j on the degree-l block.
 
-    J^2 is block diagonal after a permutation (time indices do not rotate, and
-    the real basis splits further); the products are taken on each connected
-    block of its sparsity pattern (entries below 1e-12 of the largest are the
-    rounding of exact zeros)."""
+    The projectors come from the eigendecomposition of the symmetric J^2
+    (numpy's eigh): every eigenvalue must be j(j+1) for an integer j, and the
+    eigenvectors of j span P_j.  J^2 is block diagonal after a permutation
+    (time indices do not rotate, and the real basis splits further), so the
+    decomposition is taken on each connected block of its sparsity pattern
+    (entries below 1e-12 of the largest are the rounding of exact zeros)."""
     from scipy.sparse import csr_matrix
     from scipy.sparse.csgraph import connected_components
     sigma = _SIGMAS[sigma_key]
     J2 = total_j2(L, l, dims)
     js = _spin_range(l, dims)
-    lam = [j * (j + 1.0) for j in js]
     mask = np.abs(J2) > 1e-12 * np.abs(J2).max()
     _, label = connected_components(csr_matrix(mask), directed=False)
     F = np.zeros_like(J2)
     for comp in np.unique(label):
         idx = np.where(label == comp)[0]
         A = J2[np.ix_(idx, idx)]
-        eye = np.eye(len(idx))
-        Fc = np.zeros_like(A)
-        for a, j in enumerate(js):
-            s = sigma(j)
-            if s == 0.0:
-                continue
-            P = eye
-            for b, jb in enumerate(js):
-                if b != a:
-                    P = P @ (A - lam[b] * eye) / (lam[a] - lam[b])
-            Fc = Fc + s * P
-        F[np.ix_(idx, idx)] = Fc
+        lam, V = np.linalg.eigh(0.5 * (A + A.T))
+        j = np.rint((np.sqrt(1.0 + 4.0 * np.maximum(lam, 0.0)) - 1.0) / 2.0)
+        if np.max(np.abs(lam - j * (j + 1.0))) > 1e-8 * (1.0 + np.max(np.abs(lam))):
+            raise ArithmeticError("J^2 has an eigenvalue that is not j(j+1)")
+        if not set(j.astype(int)) <= set(js):
+            raise ArithmeticError("J^2 has an eigenvalue outside the range of j")
+        F[np.ix_(idx, idx)] = (V * np.array([sigma(int(x)) for x in j])) @ V.T
     return F
 
 

@@ -1,8 +1,9 @@
 """Pins of the oracle's tensor-coupled angular filter (filtering in total
 angular momentum), against facts that do not depend on the oracle's code:
 
-* the orbital generators (r x grad)_k are antisymmetric, obey the rotation
-  algebra [A_x, A_y] = -A_z (cyclic) and sum to -l(l+1) in square on degree l;
+* the orbital generators (r x grad)_k equal the differential operators
+  applied on the grid, are antisymmetric, obey the rotation algebra
+  [A_x, A_y] = -A_z (cyclic) and sum to -l(l+1) in square on degree l;
   the index generators obey [S_x, S_y] = S_z (cross products);
 * J^2 on a vector field of degree l >= 1 has the eigenvalues j(j+1),
   j = l-1, l, l+1, each 2j+1 times (addition of angular momenta);
@@ -76,6 +77,15 @@ def test_orbital_generators_algebra():
     sq = sum(A[k] @ A[k] for k in range(3))
     lm = spectral.l_of_mode(L)
     assert np.abs(sq + np.diag(lm * (lm + 1.0))).max() < 1e-11
+
+
+def test_orbital_generators_equal_the_differential_operators_on_the_grid():
+    """The ladder-formula matrices equal (r x grad)_k applied to every basis
+    function on the grid and analysed back (quadrature rounding only)."""
+    for Lg in (3, L, 11):
+        A = tf.orbital_generators(Lg)
+        G = tf.orbital_generators_on_grid(Lg)
+        assert np.abs(A - G).max() < 1e-13 * Lg
 
 
 def test_index_generators_algebra():
