@@ -182,6 +182,61 @@ def batched_comparison(steps):
     return out
 
 
+def tensor_filter_measurement(wl, steps, applications=50):
+    """The tensor-coupled ExpCheb filter (filter_kind 2, the exponential
+    factors of the default filter in total angular momentum j) on the same
+    domain: time per application (PhysToSpec GEMM, coupling, SpecToPhys GEMM),
+    the coupling kernel against the HBM roofline, and RK3 steps with it."""
+    import torch
+    from paper_1804_09101_amd import configs, ghmi
+    xyz = ghmi.grid_coords(wl.shells)
+    offs = np.concatenate([[0], np.cumsum([s[1] * 2 * (s[2] + 1) ** 2 for s in wl.shells])])
+    u0, ubg, H, dH = wl.initial_data(xyz, offs, device="cuda:0")
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    params = configs.FILTER_DEFAULT
+    s = ghmi.GHSolver(wl.shells, wl.n_inst, params, filter_kind=2)
+    s.set_background(dev(H), dev(dH), dev(ubg))
+    s.set_params(wl.gamma, wl.dt)
+    u = dev(u0)
+    out = s.new_field()
+    for _ in range(3):
+        s.filter(u, out)
+    torch.cuda.synchronize()
+    s.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(applications):
+        s.filter(u, out)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    n_all, ms_all = s.kernel_stats("filter_gemm")
+    n_c, ms_c = s.kernel_stats("tensor_coupling")
+    s.set_timing(False)
+    # algorithmic HBM bytes of one coupling launch: the coefficient arrays in
+    # and out once, the matrix (values, input positions, row pointers) once
+    nnz = s.query(11)
+    coeff = sum(50 * sh[1] * (sh[2] + 1) ** 2 for sh in wl.shells)
+    rows = sum(50 * (L + 1) ** 2 for L in sorted({sh[2] for sh in wl.shells}))
+    alg_bytes = 2 * 8 * coeff + 12 * nnz + 8 * (rows + 1)
+    avg_c = ms_c / n_c / 1e3
+    gbs = alg_bytes / avg_c / 1e9
+    # RK3 steps with the tensor filter
+    ust = dev(u0)
+    s.step(ust, 5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(ust, steps)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    return {"filter": "tensor-coupled ExpCheb (filter_kind 2)", "params": list(params),
+            "couplings": nnz, "density": nnz / sum((50 * (L + 1) ** 2) ** 2 for L in {sh[2] for sh in wl.shells}),
+            "work_items": s.query(12), "ms_per_application": tf / applications * 1e3,
+            "filter_avg_us": ms_all / n_all * 1e3,
+            "coupling": {"bound": "hbm", "avg_launch_us": avg_c * 1e6, "algorithmic_bytes": alg_bytes,
+                         "achieved": gbs, "peak": MI355X_HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / MI355X_HBM_PEAK_GBS},
+            "rk3_ms_per_step": ts / steps * 1e3, "value": s.P * 3 * steps / ts, "unit": "grid-point RHS evals/s"}
+
+
 def dp5_measurement(solver, u0_dev, wl, attempts=40, atol=1e-8, rtol=1e-8):
     """Adaptive Dormand-Prince 5(4) on the same workload: RHS evaluations per
     second and physical time advanced per second, next to the fixed-step RK3."""
@@ -336,6 +391,10 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-hole batched comparison")
     ap.add_argument("--no-dp5", action="store_true", help="skip the adaptive Dormand-Prince measurement")
+    ap.add_argument("--no-transform", action="store_true",
+                    help="skip the angular transform method (gh_set_angular 2) measurement")
+    ap.add_argument("--no-tensor-filter", action="store_true",
+                    help="skip the tensor-coupled filter measurement")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 20-shell L = 31 domain (forward, and the adjoint of a 4-instance batch)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -437,9 +496,16 @@ def main():
     }
     log(f"timed {args.steps} steps: {t * 1e3 / args.steps:.3f} ms/step; graph {t_graph * 1e3 / args.steps:.3f} ms/step")
     out["rk3_physical_time_per_s"] = float(wl.dt[0]) * args.steps / t
-    out["transform"] = transform_measurement(solver, dev(u0), args.steps)
-    log(f"transform: {out['transform']['ms_per_step']:.3f} ms/step, graph "
-        f"{P * 3 * args.steps / out['transform']['graph_value'] / args.steps * 1e3:.3f} ms/step")
+    if not args.no_transform:
+        out["transform"] = transform_measurement(solver, dev(u0), args.steps)
+        log(f"transform: {out['transform']['ms_per_step']:.3f} ms/step, graph "
+            f"{P * 3 * args.steps / out['transform']['graph_value'] / args.steps * 1e3:.3f} ms/step")
+    if not args.no_tensor_filter:
+        out["tensor_filter"] = tensor_filter_measurement(wl, min(args.steps, 50))
+        tfm = out["tensor_filter"]
+        log(f"tensor filter: {tfm['ms_per_application']:.3f} ms per application, coupling "
+            f"{tfm['coupling']['avg_launch_us']:.1f} us ({tfm['coupling']['achieved']:.0f} GB/s), "
+            f"RK3 with it {tfm['rk3_ms_per_step']:.3f} ms/step")
     if not args.no_dp5:
         out["dp5"] = dp5_measurement(solver, dev(u0), wl)
         log(f"dp5: {out['dp5']['ms_per_attempt']:.3f} ms/attempt, {out['dp5']['accepted']} of "

@@ -18,7 +18,10 @@
  *      interfaces, Dirichlet d_t u = 0 at the outer boundary, nothing at the
  *      excision (inner) boundary.
  * A step is one SSP-RK3 step (three RHS evaluations) followed, if enabled, by
- * the angular exponential filter ("Filter" module).
+ * an angular filter ("Filter" module): the exponential filter of every
+ * component, or the tensor-coupled filter of the section on spectral filtering
+ * on I1 x S2 (PhysToSpec, a sparse matrix coupling the tensor components,
+ * SpecToPhys).
  *
  * Conventions for every function:
  *  - Return value: GH_OK (0) or a negative GH_ERR_* code; gh_last_error()
@@ -81,9 +84,14 @@ int gh_set_stream(gh_ctx* ctx, void* hip_stream);
  * Shells must be grouped by instance (instances in increasing order) and
  * ordered inner to outer; consecutive shells of one instance must share L and
  * satisfy r_out(k) == r_in(k+1) exactly (GH_ERR_SHAPE otherwise).
- * filter_kind 0: no filter; 1: angular exponential filter after every step,
- * sigma_l = 1 for l/L <= eta_c else exp(-alpha ((l/L - eta_c)/(1 - eta_c))^order),
- * filter_params = {eta_c, alpha, order} (host pointer, ignored for kind 0).
+ * filter_kind 0: no filter; 1: angular exponential filter of every component
+ * after every step, sigma_l = 1 for l/L <= eta_c else
+ * exp(-alpha ((l/L - eta_c)/(1 - eta_c))^order), filter_params = {eta_c,
+ * alpha, order}; 2, 3: the tensor-coupled filter (see gh_tensor_filter_matrix)
+ * after every step with the ExpCheb factors of kind 1 in j instead of l
+ * (kind 2, filter_params = {eta_c, alpha, order}) or the Heaviside factors
+ * sigma(j) = 1 for j <= eta_c L, else 0 (kind 3, filter_params = {eta_c}).
+ * filter_params is a host pointer, ignored for kind 0.
  * Builds and uploads the derivative and filter operators (cached per L and
  * per n_r) and allocates all work space.  Invalidates background and params. */
 int gh_set_domain(gh_ctx* ctx, int n_inst, int n_shells, const gh_shell* shells,
@@ -227,8 +235,9 @@ int gh_constraints_vjp(gh_ctx* ctx, const double* u, const double* lam_norm, dou
  *      the RK3 stage update); 5: RK3 stage combinations of the reverse pass;
  *      6: pointwise reverse pass; 7: transposed angular derivative GEMM;
  *      8: angular derivatives by transforms (gh_set_angular 1: the three
- *      launches of one derivative pass counted as one). */
-#define GH_NUM_KERNEL_KINDS 9
+ *      launches of one derivative pass counted as one); 9: the coupling
+ *      kernel of the tensor-coupled filter (also inside kind 1). */
+#define GH_NUM_KERNEL_KINDS 10
 int gh_set_timing(gh_ctx* ctx, int enable);
 int gh_kernel_stats(gh_ctx* ctx, int kind, long long* launches, double* total_ms);
 
@@ -242,6 +251,33 @@ int gh_kernel_stats(gh_ctx* ctx, int kind, long long* launches, double* total_ms
  * for the filter GEMM (-1 without filter); 8: the angular method (gh_set_angular);
  * 9, 10: whether the derivative pass / the filter use the transform form. */
 int gh_query(const gh_ctx* ctx, int what, long long* value);
+/* (continued) 11: number of stored couplings of the tensor-coupled filter
+ * (kinds 2, 3; summed over the distinct L of the domain, else 0); 12: work
+ * items of one launch of its coupling kernel. */
+
+/* Apply the domain's angular filter (filter_kind 1-3) once: out = F u.
+ * Device pointers, [50 P] each, distinct (GH_ERR_ARG if out == u, or if the
+ * domain has no filter).  Asynchronous; uses the RHS work space. */
+int gh_filter(gh_ctx* ctx, const double* u, double* out);
+
+/* The coupling matrix of the tensor-coupled angular filter on one sphere of
+ * degree L (section on spectral filtering on I1 x S2: the (N_e N_s) x
+ * (N_e N_s) matrix between PhysToSpec and SpecToPhys, N_e = 50 stored fields,
+ * N_s = (L+1)^2), in CSR form.  Rows and columns are e (L+1)^2 + s with e the
+ * stored field and s = l*l + l + m the real orthonormal Y_lm (m > 0:
+ * sqrt2 P_l^m cos(m phi), m < 0: sqrt2 P_l^|m| sin(|m| phi), m = 0: P_l, no
+ * Condon-Shortley phase).  The paper does not say what the coupling is; here
+ * it is the filter in total angular momentum: psi_ab, Pi_ab and Phi_iab rotate
+ * as tensors (positions and spatial indices together), J^2 = -sum_k G_k^2 with
+ * G_k = -(r x grad)_k + (e_k x) on every spatial index, and
+ * F = sum_j sigma(j) P_j, P_j the projector onto J^2 = j(j+1); F keeps the
+ * degree l and mixes components and orders within it.  kind 2 (ExpCheb) and 3
+ * (Heaviside) as in gh_set_domain; transpose != 0 gives F^T.
+ * Host memory, no GPU needed.  Call with row_ptr = col = val = NULL to get
+ * *nnz; then with row_ptr[50 (L+1)^2 + 1], col[*nnz], val[*nnz] (*nnz at
+ * least the count).  GH_ERR_ARG for L outside 1..63 or invalid params. */
+int gh_tensor_filter_matrix(int L, int kind, const double* params, int transpose, long long* nnz,
+                            long long* row_ptr, int* col, double* val);
 
 /* Message of the last error on this context (never NULL). */
 const char* gh_last_error(const gh_ctx* ctx);

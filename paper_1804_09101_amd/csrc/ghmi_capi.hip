@@ -15,6 +15,7 @@
 #include "ghmi.h"
 #include "ghmi_internal.h"
 #include "ghmi_setup.h"
+#include "ghmi_tensor_filter.h"
 
 namespace {
 
@@ -84,6 +85,23 @@ struct gh_ctx {
   int n_tblk = 0, tr_nmax = 0;
   std::map<int, double*> d_fana, d_fsyn;    // per L: Fourier analysis [2n][2n] and synthesis (its transpose)
   GemmPlan tr_ana, tr_syn, tr_fsyn;
+
+  // tensor-coupled filter (filter_kind 2, 3): PhysToSpec GEMM into the
+  // coefficient array X (per shell [field][radius][nsp], nsp = (L+1)^2 rounded
+  // up to even so that rows stay 16-byte aligned), coupling into Y,
+  // SpecToPhys GEMM; the adjoint uses the transposed matrices
+  std::map<int, double*> d_anaT, d_synT, d_syn, d_ana;   // per L: B operands [S][nsp], [ns][S], [S][nsp], [ns][S]
+  double *d_tfx = nullptr, *d_tfy = nullptr;
+  GemmPlan tf_p2s, tf_s2p, tf_p2sT, tf_s2pT;
+  TfItem* d_tf_items = nullptr;
+  TfSeg* d_tf_segs = nullptr;
+  TfCol* d_tf_cols = nullptr;
+  long long *d_tf_soff = nullptr, *d_tfT_soff = nullptr;   // sliced-ELL of F and of F^T
+  int *d_tf_swid = nullptr, *d_tfT_swid = nullptr;
+  int *d_tf_lidx = nullptr, *d_tfT_lidx = nullptr;
+  double *d_tf_val = nullptr, *d_tfT_val = nullptr;
+  int n_tf_wide = 0, n_tf_narrow = 0;
+  long long tf_nnz = 0;
 
   bool have_dp5 = false;
   double *d_dpk = nullptr, *d_dpy = nullptr, *d_dpu5 = nullptr, *d_dpf = nullptr, *d_dpnval = nullptr;
@@ -202,6 +220,24 @@ void free_domain(gh_ctx* c) {
   c->tr_ana = GemmPlan();
   c->tr_syn = GemmPlan();
   c->tr_fsyn = GemmPlan();
+  c->d_anaT.clear();
+  c->d_synT.clear();
+  c->d_syn.clear();
+  c->d_ana.clear();
+  c->tf_p2s = GemmPlan();
+  c->tf_s2p = GemmPlan();
+  c->tf_p2sT = GemmPlan();
+  c->tf_s2pT = GemmPlan();
+  c->d_tfx = c->d_tfy = nullptr;
+  c->d_tf_items = nullptr;
+  c->d_tf_segs = nullptr;
+  c->d_tf_cols = nullptr;
+  c->d_tf_soff = c->d_tfT_soff = nullptr;
+  c->d_tf_swid = c->d_tfT_swid = nullptr;
+  c->d_tf_lidx = c->d_tfT_lidx = nullptr;
+  c->d_tf_val = c->d_tfT_val = nullptr;
+  c->n_tf_wide = c->n_tf_narrow = 0;
+  c->tf_nnz = 0;
   c->have_dp5 = false;
   c->d_dpk = c->d_dpy = c->d_dpu5 = c->d_dpf = c->d_dpnval = nullptr;
   c->d_dprej = c->d_dpacc = nullptr;
@@ -351,10 +387,30 @@ int queue_derivs(gh_ctx* c, const double* u, double* dR = nullptr, double* dA = 
   return GH_OK;
 }
 
+// The tensor-coupled filter (or its transpose) of a whole state, src -> dst:
+// PhysToSpec of every component, the component coupling, SpecToPhys.
+int queue_tensor_filter(gh_ctx* c, const double* src, double* dst, bool transpose) {
+  double* X = c->d_tfx;
+  double* Y = c->d_tfy;
+  const GemmPlan& p2s = transpose ? c->tf_p2sT : c->tf_p2s;
+  const GemmPlan& s2p = transpose ? c->tf_s2pT : c->tf_s2p;
+  HIPCHK(c, ghk::gemm(p2s.shape, p2s.d_tiles, p2s.n_tiles, p2s.d_groups, src, X, c->stream, 6));
+  {
+    Timed t(c, 9);
+    HIPCHK(c, ghk::tensor_couple(c->d_tf_items, c->n_tf_wide, c->n_tf_narrow, c->d_tf_segs, c->d_tf_cols,
+                                 transpose ? c->d_tfT_soff : c->d_tf_soff, transpose ? c->d_tfT_swid : c->d_tf_swid,
+                                 transpose ? c->d_tfT_lidx : c->d_tf_lidx, transpose ? c->d_tfT_val : c->d_tf_val, X,
+                                 Y, c->stream));
+  }
+  HIPCHK(c, ghk::gemm(s2p.shape, s2p.d_tiles, s2p.n_tiles, s2p.d_groups, Y, dst, c->stream, 7));
+  return GH_OK;
+}
+
 // The angular filter of a whole state, src -> dst (distinct); uses the RHS work
-// space in the transform method.
+// space in the transform method and for the tensor-coupled filter.
 int queue_filter(gh_ctx* c, const double* src, double* dst) {
   Timed t(c, 1);
+  if (c->filter_kind >= 2) return queue_tensor_filter(c, src, dst, false);
   if (c->filt_tr) {
     HIPCHK(c, ghk::gemm(c->tr_ana.shape, c->tr_ana.d_tiles, c->tr_ana.n_tiles, c->tr_ana.d_groups, src, c->d_W,
                         c->stream, 4));
@@ -408,7 +464,7 @@ int queue_stage(gh_ctx* c, double c0, const double* u0, double c1, const double*
 // One SSP-RK3 step (three stages, then the filter) in place on u.
 int queue_step(gh_ctx* c, double* u) {
   int rc;
-  const bool filt = c->filter_kind == 1;
+  const bool filt = c->filter_kind != 0;
   if ((rc = queue_stage(c, 0.0, nullptr, 1.0, u, c->d_ua))) return rc;
   if ((rc = queue_stage(c, 0.75, u, 0.25, c->d_ua, c->d_ub))) return rc;
   double* dst = filt ? c->d_ua : u;
@@ -441,6 +497,10 @@ int ensure_adjoint(gh_ctx* c) {
   if ((rc = autotune(c, c->derivT, c->d_dAb, c->d_T, 2))) return rc;
   if (c->filter_kind == 1)
     if ((rc = autotune(c, c->filterT, c->d_T, c->d_Lb, 3))) return rc;
+  if (c->filter_kind >= 2) {
+    if ((rc = autotune(c, c->tf_p2sT, c->d_T, c->d_tfx, 6))) return rc;
+    if ((rc = autotune(c, c->tf_s2pT, c->d_tfx, c->d_Lb, 7))) return rc;
+  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->have_adj = true;
   return GH_OK;
@@ -522,26 +582,205 @@ int gh_set_stream(gh_ctx* c, void* hip_stream) {
 
 const char* gh_last_error(const gh_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
+namespace {
+
+// Tensor-coupled filter of the domain (filter_kind 2, 3): per L the analysis /
+// synthesis operands and the coupling matrix (and its transpose) cut into
+// segments; per L group the columns (shell, radius) of the coefficient array;
+// the work list of the coupling kernel; the GEMM groups of PhysToSpec and
+// SpecToPhys (maximal runs of consecutive shells with one L).
+int build_tensor_filter(gh_ctx* c) {
+  int rc;
+  const int tens[3][2] = {{0, 10}, {10, 10}, {20, 30}};
+  std::vector<TfSeg> segs;
+  std::vector<TfCol> colv;
+  std::vector<long long> soff[2];
+  std::vector<int> swid[2], lidx[2];
+  std::vector<double> val[2];
+  struct Work {
+    int seg, col_begin, ncols;
+    double cost;
+  };
+  std::vector<Work> work;
+  std::map<int, bool> done;
+  // coefficient array offsets per shell
+  auto nsp_of = [](int L) { return ((L + 1) * (L + 1) + 1) & ~1; };
+  std::vector<long long> xoff(c->n_shells + 1, 0);
+  for (int k = 0; k < c->n_shells; ++k) xoff[k + 1] = xoff[k] + 50LL * c->shells[k].n_r * nsp_of(c->shells[k].L);
+  if ((rc = dalloc(c, &c->d_tfx, size_t(xoff[c->n_shells])))) return rc;
+  if ((rc = dalloc(c, &c->d_tfy, size_t(xoff[c->n_shells])))) return rc;
+  for (int k0 = 0; k0 < c->n_shells; ++k0) {
+    const int L = c->shells[k0].L;
+    if (done.count(L)) continue;
+    done[L] = true;
+    const int ns = (L + 1) * (L + 1), S = 2 * ns, nsp = nsp_of(L);
+    // B operands: PhysToSpec X = u Ana^T, SpecToPhys u = Y Syn^T; transposes: X = u Syn, u = Y Ana
+    const std::vector<double> ana = ghtf::sphere_analysis(L), syn = ghtf::sphere_synthesis(L);
+    std::vector<double> anaT(size_t(S) * nsp, 0.0), synT(size_t(ns) * S), synP(size_t(S) * nsp, 0.0);
+    for (int s = 0; s < ns; ++s)
+      for (int a = 0; a < S; ++a) {
+        anaT[size_t(a) * nsp + s] = ana[size_t(s) * S + a];
+        synT[size_t(s) * S + a] = syn[size_t(a) * ns + s];
+        synP[size_t(a) * nsp + s] = syn[size_t(a) * ns + s];
+      }
+    double* d = nullptr;
+    if ((rc = upload(c, &d, anaT))) return rc;
+    c->d_anaT[L] = d;
+    if ((rc = upload(c, &d, synT))) return rc;
+    c->d_synT[L] = d;
+    if ((rc = upload(c, &d, synP))) return rc;
+    c->d_syn[L] = d;
+    if ((rc = upload(c, &d, ana))) return rc;
+    c->d_ana[L] = d;
+    const ghtf::Csr F = ghtf::coupling_matrix(L, c->filter_kind, c->filt, false);
+    const ghtf::Csr FT = ghtf::transpose(F);
+    c->tf_nnz += F.row_ptr.back();
+    // columns of this L: every (shell with this L, radius)
+    const int col_begin = int(colv.size());
+    for (int k = 0; k < c->n_shells; ++k)
+      if (c->shells[k].L == L)
+        for (int r = 0; r < c->shells[k].n_r; ++r)
+          colv.push_back(TfCol{xoff[k] + (long long)r * nsp, (long long)c->shells[k].n_r * nsp});
+    const int ncols = int(colv.size()) - col_begin;
+    // segments: per tensor, consecutive degrees while the rows fit one wide item
+    for (auto& tz : tens) {
+      const int e0 = tz[0], ne = tz[1];
+      for (int l0 = 0; l0 <= L;) {
+        int l1 = l0 + 1;
+        while (l1 <= L && ne * ((l1 + 1) * (l1 + 1) - l0 * l0) <= TF_WIDE_ROWS) ++l1;
+        const int s0 = l0 * l0, nsg = l1 * l1 - s0, n = ne * nsg;
+        if (n > TF_MAX_ROWS) return fail(c, GH_ERR_ARG, "tensor filter: L too large for the coupling kernel");
+        const int seg_id = int(segs.size());
+        segs.push_back(TfSeg{e0, ne, s0, nsg, int(soff[0].size()), 0});
+        double cost = 0.0;
+        for (int pass = 0; pass < 2; ++pass) {
+          const ghtf::Csr& M = pass ? FT : F;
+          for (int q0 = 0; q0 < n; q0 += 64) {
+            // one slice: rows q0 .. q0 + 63 of the segment
+            int w = 0;
+            for (int lane = 0; lane < 64 && q0 + lane < n; ++lane) {
+              const int i = q0 + lane, e = e0 + i / nsg, sl = s0 + i % nsg;
+              const long long row = (long long)e * ns + sl;
+              w = std::max<int>(w, int(M.row_ptr[row + 1] - M.row_ptr[row]));
+            }
+            const long long off = (long long)val[pass].size();
+            soff[pass].push_back(off);
+            swid[pass].push_back(w);
+            if (!pass) cost += w;
+            val[pass].resize(size_t(off) + size_t(64) * w, 0.0);
+            lidx[pass].resize(size_t(off) + size_t(64) * w, 0);
+            for (int lane = 0; lane < 64 && q0 + lane < n; ++lane) {
+              const int i = q0 + lane, e = e0 + i / nsg, sl = s0 + i % nsg;
+              const long long row = (long long)e * ns + sl;
+              int k = 0;
+              for (long long p = M.row_ptr[row]; p < M.row_ptr[row + 1]; ++p, ++k) {
+                const int e2 = M.col[p] / ns, s2 = M.col[p] % ns;
+                if (e2 < e0 || e2 >= e0 + ne || s2 < s0 || s2 >= s0 + nsg)
+                  return fail(c, GH_ERR_DEVICE, "tensor filter: a coupling leaves its segment");
+                val[pass][size_t(off) + size_t(64) * k + lane] = M.val[p];
+                lidx[pass][size_t(off) + size_t(64) * k + lane] = (e2 - e0) * nsg + (s2 - s0);
+              }
+            }
+          }
+        }
+        work.push_back(Work{seg_id, col_begin, ncols, cost});
+        l0 = l1;
+      }
+    }
+  }
+  // work items: wide (TF_WIDE columns) for segments of at most TF_WIDE_ROWS
+  // rows, narrow otherwise; the items of one segment go to one XCD (its part
+  // of the matrix stays in that XCD's L2), segments balanced over the 8 XCDs
+  // by their slice widths times the columns; list position p runs on XCD p % 8.
+  std::vector<TfItem> items;
+  for (int cls = 0; cls < 2; ++cls) {
+    const int per = cls ? TF_NARROW : TF_WIDE;
+    std::vector<Work> ws;
+    for (auto& w : work) {
+      const bool wide = segs[w.seg].ne * segs[w.seg].nsg <= TF_WIDE_ROWS;
+      if (wide == (cls == 0)) ws.push_back(w);
+    }
+    std::sort(ws.begin(), ws.end(), [](const Work& a, const Work& b) { return a.cost * a.ncols > b.cost * b.ncols; });
+    std::vector<std::vector<TfItem>> px(8);
+    double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (auto& w : ws) {
+      const int x = int(std::min_element(load, load + 8) - load);
+      load[x] += w.cost * w.ncols;
+      for (int c0 = 0; c0 < w.ncols; c0 += per)
+        px[x].push_back(TfItem{w.seg, w.col_begin + c0, std::min(per, w.ncols - c0), 0});
+    }
+    size_t longest = 0;
+    for (auto& v : px) longest = std::max(longest, v.size());
+    const size_t before = items.size();
+    for (size_t q = 0; q < longest; ++q)
+      for (int x = 0; x < 8; ++x)
+        if (q < px[x].size()) items.push_back(px[x][q]);
+    (cls ? c->n_tf_narrow : c->n_tf_wide) = int(items.size() - before);
+  }
+  if ((rc = upload(c, &c->d_tf_segs, segs))) return rc;
+  if ((rc = upload(c, &c->d_tf_cols, colv))) return rc;
+  if ((rc = upload(c, &c->d_tf_items, items))) return rc;
+  if ((rc = upload(c, &c->d_tf_soff, soff[0]))) return rc;
+  if ((rc = upload(c, &c->d_tf_swid, swid[0]))) return rc;
+  if ((rc = upload(c, &c->d_tf_lidx, lidx[0]))) return rc;
+  if ((rc = upload(c, &c->d_tf_val, val[0]))) return rc;
+  if ((rc = upload(c, &c->d_tfT_soff, soff[1]))) return rc;
+  if ((rc = upload(c, &c->d_tfT_swid, swid[1]))) return rc;
+  if ((rc = upload(c, &c->d_tfT_lidx, lidx[1]))) return rc;
+  if ((rc = upload(c, &c->d_tfT_val, val[1]))) return rc;
+  // GEMM groups
+  for (int k = 0; k < c->n_shells;) {
+    const int L = c->shells[k].L, ns = (L + 1) * (L + 1), S = 2 * ns, nsp = nsp_of(L);
+    int k1 = k, rows = 0;
+    while (k1 < c->n_shells && c->shells[k1].L == L) { rows += 50 * c->shells[k1].n_r; ++k1; }
+    GemmGroup g;
+    g.a_off = 50LL * c->offs[k];
+    g.c_off = xoff[k];
+    g.B = c->d_anaT[L];
+    g.M = rows; g.N = ns; g.K = S;
+    g.lda = S; g.ldb = nsp; g.ldc = nsp;
+    c->tf_p2s.groups.push_back(g);
+    g.B = c->d_syn[L];
+    c->tf_p2sT.groups.push_back(g);
+    GemmGroup h;
+    h.a_off = xoff[k];
+    h.c_off = 50LL * c->offs[k];
+    h.B = c->d_synT[L];
+    h.M = rows; h.N = S; h.K = ns;
+    h.lda = nsp; h.ldb = S; h.ldc = S;
+    c->tf_s2p.groups.push_back(h);
+    h.B = c->d_ana[L];
+    c->tf_s2pT.groups.push_back(h);
+    k = k1;
+  }
+  return GH_OK;
+}
+
+}  // namespace
+
 int gh_set_domain(gh_ctx* c, int n_inst, int n_shells, const gh_shell* shells, int filter_kind,
                   const double* filter_params) {
   if (!c) return GH_ERR_ARG;
   std::string why;
   int rc = validate_shells(n_inst, n_shells, shells, why);
   if (rc) return fail(c, rc, why);
-  if (filter_kind != 0 && filter_kind != 1) return fail(c, GH_ERR_ARG, "filter_kind must be 0 or 1");
-  if (filter_kind == 1) {
-    if (!filter_params) return fail(c, GH_ERR_ARG, "filter_params required for filter_kind 1");
+  if (filter_kind < 0 || filter_kind > 3) return fail(c, GH_ERR_ARG, "filter_kind must be 0, 1, 2 or 3");
+  if (filter_kind != 0 && !filter_params) return fail(c, GH_ERR_ARG, "filter_params required for filter_kind 1-3");
+  if (filter_kind == 1 || filter_kind == 2) {
     if (!(filter_params[0] >= 0.0 && filter_params[0] < 1.0) || !(filter_params[1] >= 0.0) ||
         !(filter_params[2] > 0.0))
       return fail(c, GH_ERR_ARG, "filter_params: need 0 <= eta_c < 1, alpha >= 0, order > 0");
   }
+  if (filter_kind == 3 && !(filter_params[0] >= 0.0))
+    return fail(c, GH_ERR_ARG, "filter_params: need eta_c >= 0 for the Heaviside filter");
   HIPCHK(c, hipSetDevice(c->device));
   free_domain(c);
   c->n_inst = n_inst;
   c->n_shells = n_shells;
   c->shells.assign(shells, shells + n_shells);
   c->filter_kind = filter_kind;
-  if (filter_kind == 1) std::memcpy(c->filt, filter_params, 3 * sizeof(double));
+  if (filter_kind == 1 || filter_kind == 2) std::memcpy(c->filt, filter_params, 3 * sizeof(double));
+  if (filter_kind == 3) c->filt[0] = filter_params[0];
 
   // layout
   c->offs.assign(n_shells + 1, 0);
@@ -727,6 +966,8 @@ int gh_set_domain(gh_ctx* c, int n_inst, int n_shells, const gh_shell* shells, i
     k = k1;
   }
 
+  if (filter_kind >= 2 && (rc = build_tensor_filter(c))) return rc;
+
   // work space
   size_t F50 = size_t(50) * c->P;
   if ((rc = dalloc(c, &c->d_dR, F50))) return rc;
@@ -743,6 +984,10 @@ int gh_set_domain(gh_ctx* c, int n_inst, int n_shells, const gh_shell* shells, i
   if ((rc = autotune(c, c->deriv, c->d_ua, c->d_dA, 0))) return rc;
   if (filter_kind == 1)
     if ((rc = autotune(c, c->filter, c->d_ua, c->d_ub, 1))) return rc;
+  if (filter_kind >= 2) {
+    if ((rc = autotune(c, c->tf_p2s, c->d_ua, c->d_tfx, 6))) return rc;
+    if ((rc = autotune(c, c->tf_s2p, c->d_tfx, c->d_ub, 7))) return rc;
+  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->have_domain = true;
   return GH_OK;
@@ -976,7 +1221,7 @@ int gh_set_angular(gh_ctx* c, int method) {
   HIPCHK(c, hipSetDevice(c->device));
   int rc;
   if (method >= 1 && (rc = ensure_transform(c))) return rc;
-  bool dtr = method == 1, ftr = method == 1;
+  bool dtr = method == 1, ftr = method == 1 && c->filter_kind == 1;
   if (method == 2) {
     // time both forms of each operation on this domain (non-zero data in the work arrays)
     const bool timing = c->timing;
@@ -1055,6 +1300,9 @@ int queue_step_vjp(gh_ctx* c, const double* u_n, const double* u1, const double*
     HIPCHK(c, ghk::gemm(c->filterT.shape, c->filterT.d_tiles, c->filterT.n_tiles, c->filterT.d_groups, lam_np1,
                         c->d_lam3, c->stream, 3));
     lam3 = c->d_lam3;
+  } else if (c->filter_kind >= 2) {
+    if ((rc = queue_tensor_filter(c, lam_np1, c->d_lam3, true))) return rc;
+    lam3 = c->d_lam3;
   }
   // u3 = 1/3 u + 2/3 (u2 + h L(u2))
   if ((rc = queue_rhs_vjp(c, u2, lam3, c->d_T, 2.0 / 3.0, 1, g_gamma, k2))) return rc;
@@ -1094,7 +1342,7 @@ int gh_step_stages(gh_ctx* c, double* u, double* u1, double* u2, double* derivs)
   if (derivs && (derivs == u || derivs == u1 || derivs == u2))
     return fail(c, GH_ERR_ARG, "derivs must not alias u, u1 or u2");
   HIPCHK(c, hipSetDevice(c->device));
-  const bool filt = c->filter_kind == 1;
+  const bool filt = c->filter_kind != 0;
   const size_t F150 = size_t(150) * c->P;
   if ((rc = queue_stage(c, 0.0, nullptr, 1.0, u, u1, derivs))) return rc;
   if ((rc = queue_stage(c, 0.75, u, 0.25, u1, u2, derivs ? derivs + F150 : nullptr))) return rc;
@@ -1139,7 +1387,7 @@ int ensure_dp5(gh_ctx* c) {
   if ((rc = dalloc(c, &c->d_dpk, 7 * F50))) return rc;
   if ((rc = dalloc(c, &c->d_dpy, F50))) return rc;
   if ((rc = dalloc(c, &c->d_dpu5, F50))) return rc;
-  if (c->filter_kind == 1 && (rc = dalloc(c, &c->d_dpf, F50))) return rc;
+  if (c->filter_kind != 0 && (rc = dalloc(c, &c->d_dpf, F50))) return rc;
   if ((rc = dalloc(c, &c->d_dprej, size_t(c->n_inst)))) return rc;
   if ((rc = dalloc(c, &c->d_dpacc, size_t(c->n_inst)))) return rc;
   std::vector<double> nval(c->n_inst, 0.0);
@@ -1172,6 +1420,35 @@ int gh_constraints_vjp(gh_ctx* c, const double* u, const double* lam_norm, doubl
   return GH_OK;
 }
 
+int gh_filter(gh_ctx* c, const double* u, double* out) {
+  if (!c || !u || !out) return GH_ERR_ARG;
+  if (!c->have_domain) return fail(c, GH_ERR_ORDER, "gh_set_domain has not been called");
+  if (c->filter_kind == 0) return fail(c, GH_ERR_ARG, "the domain has no filter (filter_kind 0)");
+  if (u == out) return fail(c, GH_ERR_ARG, "out must not be u");
+  HIPCHK(c, hipSetDevice(c->device));
+  return queue_filter(c, u, out);
+}
+
+int gh_tensor_filter_matrix(int L, int kind, const double* params, int transpose, long long* nnz,
+                            long long* row_ptr, int* col, double* val) {
+  if (L < 1 || L > 63 || (kind != 2 && kind != 3) || !params || !nnz) return GH_ERR_ARG;
+  if ((kind == 2 && (!(params[0] >= 0.0 && params[0] < 1.0) || !(params[1] >= 0.0) || !(params[2] > 0.0))) ||
+      (kind == 3 && !(params[0] >= 0.0)))
+    return GH_ERR_ARG;
+  const ghtf::Csr m = ghtf::coupling_matrix(L, kind, params, transpose != 0);
+  const long long n = m.row_ptr.back();
+  if (!row_ptr && !col && !val) {
+    *nnz = n;
+    return GH_OK;
+  }
+  if (!row_ptr || !col || !val || *nnz < n) return GH_ERR_ARG;
+  std::copy(m.row_ptr.begin(), m.row_ptr.end(), row_ptr);
+  std::copy(m.col.begin(), m.col.end(), col);
+  std::copy(m.val.begin(), m.val.end(), val);
+  *nnz = n;
+  return GH_OK;
+}
+
 int gh_query(const gh_ctx* c, int what, long long* value) {
   if (!c || !value) return GH_ERR_ARG;
   if (!c->have_domain) return GH_ERR_ORDER;
@@ -1191,6 +1468,8 @@ int gh_query(const gh_ctx* c, int what, long long* value) {
     case 8: *value = c->ang_method; break;
     case 9: *value = c->deriv_tr ? 1 : 0; break;
     case 10: *value = c->filt_tr ? 1 : 0; break;
+    case 11: *value = c->tf_nnz; break;
+    case 12: *value = c->n_tf_wide + c->n_tf_narrow; break;
     default: return GH_ERR_ARG;
   }
   return GH_OK;
@@ -1297,7 +1576,7 @@ int gh_step_dp5(gh_ctx* c, double* u, int n_attempts, double atol, double rtol, 
   const size_t F50 = size_t(50) * c->P;
   double* K[7];
   for (int j = 0; j < 7; ++j) K[j] = c->d_dpk + j * F50;
-  const bool filt = c->filter_kind == 1;
+  const bool filt = c->filter_kind != 0;
   int* rej = rejected;
   if (!rej) {
     rej = c->d_dprej;

@@ -28,7 +28,8 @@ namespace ghk {
 // BM x BN, wave layout, LDS layout of A); order: 0 column blocks or 1 row
 // blocks per XCD.  role: 0 angular derivative, 1 filter, 2 transposed
 // derivative (C += A B), 3 transposed filter, 4 Fourier analysis, 5 Fourier
-// synthesis (separate kernel symbols).
+// synthesis, 6 PhysToSpec and 7 SpecToPhys of the tensor-coupled filter
+// (separate kernel symbols).
 enum { NUM_TILE_SHAPES = 10 };
 void tile_dims(int shape, int* bm, int* bn);
 std::vector<GemmTile> build_tiles(const std::vector<GemmGroup>& groups, int shape, int order);

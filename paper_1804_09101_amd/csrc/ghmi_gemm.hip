@@ -29,8 +29,9 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------
 // ROLE separates the kernel symbols of the different uses (0: angular
 // derivative, 1: filter, 2: transposed derivative of the adjoint, 3: transposed
-// filter, 4: Fourier analysis and 5: synthesis of the transform path) so that
-// profiles attribute time to each.  ROLE 2 adds into C
+// filter, 4: Fourier analysis and 5: synthesis of the transform path, 6:
+// PhysToSpec and 7: SpecToPhys of the tensor-coupled filter) so that profiles
+// attribute time to each.  ROLE 2 adds into C
 // (C += A B); the others overwrite C.
 template <int BM, int BN, int WGM, int WGN, bool AROW, int ROLE>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(const GemmTile* __restrict__ tiles,
@@ -219,7 +220,10 @@ hipError_t gemm(int shape, const GemmTile* tiles, int n_tiles, const GemmGroup* 
     case 2: return gemm_role<2>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
     case 3: return gemm_role<3>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
     case 4: return gemm_role<4>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
-    default: return gemm_role<5>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
+    case 5: return gemm_role<5>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
+    case 6: return gemm_role<6>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
+    case 7: return gemm_role<7>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
+    default: return hipErrorInvalidValue;
   }
 }
 

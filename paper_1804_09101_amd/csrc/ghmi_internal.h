@@ -27,9 +27,32 @@ struct PtBlock {
   int q0;             // first local point index (r*S + a)
 };
 
+// Tensor-coupled filter, the coupling step on the coefficient array X (per
+// shell [field][radius][nsp]): Y = F X for every column (shell, radius).
+// The rows of F come in segments: rows (e, s) with e0 <= e < e0 + ne and
+// s0 <= s < s0 + nsg, numbered e-major, whose couplings all stay in the
+// segment.  A segment's rows are cut into slices of 64 (one per wave), stored
+// sliced-ELL: slice q holds width[q] couplings per row, the k-th of every row
+// contiguous (val/lidx[off[q] + 64 k + lane], zero-padded); lidx is the
+// input's position inside the segment, (e' - e0) * nsg + (s' - s0).  A work
+// item stages its segment's inputs for up to TF_WIDE (segments of at most
+// TF_WIDE_ROWS rows) or TF_NARROW columns in LDS and writes the segment's
+// outputs for them.
+enum { TF_WIDE = 8, TF_NARROW = 2, TF_WIDE_ROWS = 1024, TF_MAX_ROWS = 4096 };
+struct TfSeg {
+  int e0, ne, s0, nsg;
+  int slice0, pad;     // first slice of the segment in the slice tables
+};
+struct TfCol {
+  long long base;     // X offset of (shell, radius, field 0, s = 0)
+  long long fstride;  // distance between fields: n_r nsp
+};
+struct TfItem {
+  int seg, col0, ncol, pad;
+};
+
 // Kernel launchers (ghmi_kernels.hip).  All are asynchronous on `st`.
 namespace ghk {
-
 
 // Dormand-Prince pieces.  dp_combine: out = u + dt (sum_{j<nk} c_j k_j);
 // dp_error: per point block, sum over values of (dt sum_j e_j k_j / (atol +
@@ -59,6 +82,11 @@ hipError_t ang_theta(int nmax, const ShellDev* sh, const PtBlock* tblk, int n_tb
                      const double* AB, double* X, int mode, hipStream_t st);
 
 hipError_t fill_pattern(double* x, long long n, hipStream_t st);
+
+// items[0, n_wide) stage TF_WIDE columns, items[n_wide, n_wide + n_narrow) TF_NARROW.
+hipError_t tensor_couple(const TfItem* items, int n_wide, int n_narrow, const TfSeg* segs, const TfCol* cols,
+                         const long long* soff, const int* swidth, const int* lidx, const double* val,
+                         const double* X, double* Y, hipStream_t st);
 
 hipError_t radial(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* dtab,
                   const double* u, double* dR, int ncomp_lo, int ncomp_hi, hipStream_t st);

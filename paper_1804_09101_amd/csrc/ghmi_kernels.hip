@@ -1117,6 +1117,77 @@ __global__ __launch_bounds__(256) void k_ang_theta(const ShellDev* __restrict__ 
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Tensor-coupled filter: the coupling step Y = F X on the angular
+// coefficients.  One workgroup (4 waves) per (segment, column chunk): the
+// segment's inputs of NC columns (shell, radius) are staged in LDS as
+// [input][column] (runs of nsg consecutive coefficients per field from HBM),
+// then every wave takes 64-row slices: lane = row, the k-th couplings of the
+// 64 rows are one contiguous load of values and one of input positions, and
+// each coupling is applied to the NC staged columns of its input (NC/2
+// 16-byte LDS reads).  Consecutive lanes own consecutive coefficients s, so
+// the stores of Y are contiguous runs per column.
+// ---------------------------------------------------------------------------
+template <int NC>
+__global__ __launch_bounds__(256) void k_tensor_couple(const TfItem* __restrict__ items,
+                                                       const TfSeg* __restrict__ segs,
+                                                       const TfCol* __restrict__ cols,
+                                                       const long long* __restrict__ soff,
+                                                       const int* __restrict__ swidth,
+                                                       const int* __restrict__ lidx,
+                                                       const double* __restrict__ val,
+                                                       const double* __restrict__ X, double* __restrict__ Y) {
+  extern __shared__ double lds[];
+  const TfItem it = items[blockIdx.x];
+  const TfSeg sg = segs[it.seg];
+  const int n = sg.ne * sg.nsg;
+  const int nc = it.ncol;
+  long long cbase[NC], cstr[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const TfCol cc = cols[it.col0 + (c < nc ? c : 0)];
+    cbase[c] = cc.base;
+    cstr[c] = cc.fstride;
+  }
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const int e = i / sg.nsg, s = i - e * sg.nsg;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      lds[i * NC + c] = (c < nc) ? X[cbase[c] + (long long)(sg.e0 + e) * cstr[c] + sg.s0 + s] : 0.0;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nsl = (n + 63) >> 6;
+  for (int q = wave; q < nsl; q += 4) {
+    const long long off = soff[sg.slice0 + q];
+    const int w = swidth[sg.slice0 + q];
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    const double* __restrict__ vq = val + off + lane;
+    const int* __restrict__ iq = lidx + off + lane;
+#pragma unroll 4
+    for (int k = 0; k < w; ++k) {
+      const double v = vq[64 * k];
+      const double2* xp = reinterpret_cast<const double2*>(lds + iq[64 * k] * NC);
+#pragma unroll
+      for (int c2 = 0; c2 < NC / 2; ++c2) {
+        const double2 x = xp[c2];
+        acc[2 * c2] += v * x.x;
+        acc[2 * c2 + 1] += v * x.y;
+      }
+    }
+    const int i = q * 64 + lane;
+    if (i < n) {
+      const int e = i / sg.nsg, s = i - e * sg.nsg;
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        if (c < nc) Y[cbase[c] + (long long)(sg.e0 + e) * cstr[c] + sg.s0 + s] = acc[c];
+    }
+  }
+}
+
 }  // namespace
 
 namespace ghk {
@@ -1136,6 +1207,18 @@ hipError_t fill_pattern(double* x, long long n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   long long nb = (n + 255) / 256;
   hipLaunchKernelGGL(k_fill_pattern, dim3((unsigned)(nb < 8192 ? nb : 8192)), dim3(256), 0, st, x, n);
+  return hipGetLastError();
+}
+
+hipError_t tensor_couple(const TfItem* items, int n_wide, int n_narrow, const TfSeg* segs, const TfCol* cols,
+                         const long long* soff, const int* swidth, const int* lidx, const double* val,
+                         const double* X, double* Y, hipStream_t st) {
+  if (n_wide > 0)
+    hipLaunchKernelGGL(k_tensor_couple<TF_WIDE>, dim3(n_wide), dim3(256), size_t(8) * TF_WIDE * TF_WIDE_ROWS, st,
+                       items, segs, cols, soff, swidth, lidx, val, X, Y);
+  if (n_narrow > 0)
+    hipLaunchKernelGGL(k_tensor_couple<TF_NARROW>, dim3(n_narrow), dim3(256), size_t(8) * TF_NARROW * TF_MAX_ROWS,
+                       st, items + n_wide, segs, cols, soff, swidth, lidx, val, X, Y);
   return hipGetLastError();
 }
 

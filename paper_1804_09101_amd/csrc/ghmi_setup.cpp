@@ -132,7 +132,7 @@ void gauss_legendre(int L, std::vector<double>& x, std::vector<double>& w) {
 
 // Normalised P_l^m(x) (including 1/sqrt(4 pi), no Condon-Shortley phase) and
 // d/dtheta of it, for 0 <= m <= l <= L at one node: arrays [(L+1)*(L+1)], index l*(L+1)+m.
-static void legendre_normalised(int L, double x, std::vector<double>& P, std::vector<double>& dP) {
+void legendre_normalised(int L, double x, std::vector<double>& P, std::vector<double>& dP) {
   int n = L + 1;
   P.assign(size_t(n) * n, 0.0);
   dP.assign(size_t(n) * n, 0.0);

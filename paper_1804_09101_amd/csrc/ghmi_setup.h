@@ -19,6 +19,10 @@ std::vector<double> clenshaw_curtis(int n);
 // Gauss-Legendre nodes (increasing) and weights for L+1 points (Newton on P_{L+1}).
 void gauss_legendre(int L, std::vector<double>& x, std::vector<double>& w);
 
+// Normalised P_l^m(x) (including 1/sqrt(4 pi), no Condon-Shortley phase) and
+// d/dtheta of it, 0 <= m <= l <= L, at one node: arrays [(L+1)*(L+1)], index l*(L+1)+m.
+void legendre_normalised(int L, double x, std::vector<double>& P, std::vector<double>& dP);
+
 // Dense S x S operators on one sphere, row-major (out_j = sum_a M[j*S+a] u_a):
 //   which 0: d/dtheta, 1: d/dphi, 2: filter with factors sigma_l (sigma has L+1 entries).
 std::vector<double> sphere_operator(int L, int which, const std::vector<double>& sigma);

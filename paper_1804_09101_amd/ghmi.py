@@ -26,11 +26,12 @@ EXPORTS = [
     "gh_last_error", "gh_grid_coords", "gh_host_operator", "gh_set_timing", "gh_kernel_stats",
     "gh_query", "gh_rhs_vjp", "gh_step_vjp", "gh_constraints_vjp",
     "gh_set_graph", "gh_step_stages", "gh_step_vjp_stages", "gh_step_dp5", "gh_set_angular",
+    "gh_filter", "gh_tensor_filter_matrix",
 ]
 
 KERNEL_KINDS = {"deriv_gemm": 0, "filter_gemm": 1, "radial": 2, "pointwise": 3, "boundary": 4,
                 "rk_combine_vjp": 5, "pointwise_vjp": 6, "deriv_gemm_T": 7,
-                "angular_transform": 8}
+                "angular_transform": 8, "tensor_coupling": 9}
 
 
 class GHError(RuntimeError):
@@ -85,6 +86,8 @@ def load_library(path=LIB_PATH):
         "gh_step_dp5": (i, [vp, vp, i, d, d, vp, vp, vp, vp, vp]),
         "gh_set_angular": (i, [vp, i]),
         "gh_step_vjp_stages": (i, [vp, vp, vp, vp, vp, vp, vp, vp]),
+        "gh_filter": (i, [vp, vp, vp]),
+        "gh_tensor_filter_matrix": (i, [i, i, pd, i, pll, pll, ctypes.POINTER(ctypes.c_int), pd]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -141,14 +144,40 @@ def host_operator(kind, n, params=None):
     return out
 
 
+def tensor_filter_matrix(L, kind, params, transpose=False):
+    """Coupling matrix of the tensor-coupled filter as CSR arrays (row_ptr,
+    col, val) from the library's host builder (host-only call); kind 2
+    ExpCheb (eta_c, alpha, order), 3 Heaviside (eta_c,); see include/ghmi.h."""
+    lib = load_library()
+    keep, pp = _dptr(list(params) + [0.0] * (3 - len(params)))
+    nnz = ctypes.c_longlong(0)
+    rc = lib.gh_tensor_filter_matrix(int(L), int(kind), pp, int(bool(transpose)), ctypes.byref(nnz), None, None, None)
+    if rc:
+        raise GHError(rc, "gh_tensor_filter_matrix")
+    n = 50 * (L + 1) ** 2
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    col = np.zeros(nnz.value, dtype=np.int32)
+    val = np.zeros(nnz.value)
+    rc = lib.gh_tensor_filter_matrix(int(L), int(kind), pp, int(bool(transpose)), ctypes.byref(nnz),
+                                     row_ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)),
+                                     col.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                     val.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc:
+        raise GHError(rc, "gh_tensor_filter_matrix")
+    return row_ptr, col, val
+
+
 class GHSolver:
     """One context of the library: a domain, its background and parameters.
 
     shells: sequence of (instance, n_r, L, r_in, r_out).
-    filter_params: None, or (eta_c, alpha, order) for the angular exponential filter.
+    filter_params: None, or the parameters of the angular filter of kind
+    filter_kind (1: exponential filter of every component, (eta_c, alpha,
+    order); 2: tensor-coupled ExpCheb filter, (eta_c, alpha, order); 3:
+    tensor-coupled Heaviside filter, (eta_c,)).
     """
 
-    def __init__(self, shells, n_inst=None, filter_params=None, device=0):
+    def __init__(self, shells, n_inst=None, filter_params=None, device=0, filter_kind=1):
         import torch
         self._torch = torch
         self.lib = load_library()
@@ -161,8 +190,9 @@ class GHSolver:
             raise GHError(rc, "gh_create failed (no HIP device?)")
         self.h = h
         arr = _shell_array(self.shells)
-        kind = 0 if filter_params is None else 1
-        self._fp, fpp = _dptr(filter_params if filter_params is not None else [0.0, 0.0, 0.0])
+        kind = 0 if filter_params is None else int(filter_kind)
+        fp = [0.0, 0.0, 0.0] if filter_params is None else list(filter_params) + [0.0] * (3 - len(filter_params))
+        self._fp, fpp = _dptr(fp)
         self._check(self.lib.gh_set_domain(self.h, self.n_inst, len(self.shells), arr, kind, fpp))
         tot = ctypes.c_longlong()
         offs = (ctypes.c_longlong * (len(self.shells) + 1))()
@@ -257,6 +287,14 @@ class GHSolver:
         g = ctypes.c_void_p(g_gamma.data_ptr()) if g_gamma is not None else None
         self._check(self.lib.gh_step_vjp(self.h, self._dev(u_n, 50, "u_n"), self._dev(lam_np1, 50, "lam_np1"),
                                          self._dev(out, 50, "lam_n"), g))
+        return out
+
+    def filter(self, u, out=None):
+        """The domain's angular filter applied once: out = F u (a new field if out is None)."""
+        self._sync_stream()
+        if out is None:
+            out = self.new_field()
+        self._check(self.lib.gh_filter(self.h, self._dev(u, 50, "u"), self._dev(out, 50, "out")))
         return out
 
     def set_angular(self, method):

@@ -84,3 +84,63 @@ def test_host_calls_reject_bad_arguments(lib):
         ghmi.host_operator(0, 1)
     with pytest.raises(ValueError):
         ghmi.host_operator(9, 3)
+
+
+def _oracle_coupling(L, kind, params):
+    """The oracle's coupling matrix, column by column (unit coefficient vectors)."""
+    from oracle import tensor_filter as tf
+    key = tf.sigma_function(kind, L, params)
+    ns = (L + 1) ** 2
+    n = 50 * ns
+    M = np.zeros((n, n))
+    for col in range(n):
+        c = np.zeros((50, ns))
+        c[col // ns, col % ns] = 1.0
+        M[:, col] = tf.filter_coefficients(c, L, key).ravel()
+    return M
+
+
+def _dense(row_ptr, col, val):
+    n = len(row_ptr) - 1
+    M = np.zeros((n, n))
+    for r in range(n):
+        M[r, col[row_ptr[r]:row_ptr[r + 1]]] = val[row_ptr[r]:row_ptr[r + 1]]
+    return M
+
+
+@pytest.mark.parametrize("L,kind,params", [(3, 2, (0.0, 3.0, 2.0)), (5, 2, (2.0 / 3.0, 36.0, 8.0)),
+                                           (6, 3, (0.5,))])
+def test_tensor_filter_matrix_matches_oracle(lib, L, kind, params):
+    """The library's coupling matrix (ladder-operator generators, Newton form
+    of sigma(J^2), sparse) equals the oracle's (generators from the grid,
+    Lagrange projectors, dense) entry by entry, and so does its transpose."""
+    O = _oracle_coupling(L, "expcheb" if kind == 2 else "heaviside", params)
+    H = _dense(*ghmi.tensor_filter_matrix(L, kind, params))
+    HT = _dense(*ghmi.tensor_filter_matrix(L, kind, params, transpose=True))
+    assert np.max(np.abs(H - O)) < 1e-14
+    assert np.max(np.abs(HT - O.T)) < 1e-14
+    # sparse: at most a few percent of the entries
+    assert np.count_nonzero(H) < 0.05 * H.size
+
+
+def test_tensor_filter_matrix_is_block_diagonal_in_degree_and_tensor(lib):
+    L = 7
+    row_ptr, col, val = ghmi.tensor_filter_matrix(L, 2, (2.0 / 3.0, 36.0, 8.0))
+    ns = (L + 1) ** 2
+    deg = np.concatenate([np.full(2 * l + 1, l) for l in range(L + 1)])
+    group = np.array([0] * 10 + [1] * 10 + [2] * 30)
+    rows = np.repeat(np.arange(len(row_ptr) - 1), np.diff(row_ptr))
+    assert np.array_equal(deg[rows % ns], deg[col % ns])
+    assert np.array_equal(group[rows // ns], group[col // ns])
+    # psi_00 and Pi_00 (time-time components) are the plain degree filter: diagonal
+    for f in (0, 10):
+        sel = rows // ns == f
+        assert np.array_equal(rows[sel], col[sel])
+
+
+def test_tensor_filter_matrix_rejects_bad_arguments(lib):
+    for L, kind, params in ((0, 2, (0.5, 1.0, 2.0)), (64, 2, (0.5, 1.0, 2.0)), (5, 1, (0.5, 1.0, 2.0)),
+                            (5, 2, (1.0, 1.0, 2.0)), (5, 2, (0.5, 1.0, 0.0)), (5, 3, (-0.1,))):
+        with pytest.raises(ghmi.GHError) as ei:
+            ghmi.tensor_filter_matrix(L, kind, params)
+        assert ei.value.code == -1
