@@ -98,9 +98,10 @@ struct gh_ctx {
   TfCol* d_tf_cols = nullptr;
   long long *d_tf_soff = nullptr, *d_tfT_soff = nullptr;   // sliced-ELL of F and of F^T
   int *d_tf_swid = nullptr, *d_tfT_swid = nullptr;
+  int *d_tf_perm = nullptr, *d_tfT_perm = nullptr;
   int *d_tf_lidx = nullptr, *d_tfT_lidx = nullptr;
   double *d_tf_val = nullptr, *d_tfT_val = nullptr;
-  int n_tf_wide = 0, n_tf_narrow = 0;
+  int n_tf_items[3] = {0, 0, 0};
   long long tf_nnz = 0;
 
   bool have_dp5 = false;
@@ -234,9 +235,10 @@ void free_domain(gh_ctx* c) {
   c->d_tf_cols = nullptr;
   c->d_tf_soff = c->d_tfT_soff = nullptr;
   c->d_tf_swid = c->d_tfT_swid = nullptr;
+  c->d_tf_perm = c->d_tfT_perm = nullptr;
   c->d_tf_lidx = c->d_tfT_lidx = nullptr;
   c->d_tf_val = c->d_tfT_val = nullptr;
-  c->n_tf_wide = c->n_tf_narrow = 0;
+  c->n_tf_items[0] = c->n_tf_items[1] = c->n_tf_items[2] = 0;
   c->tf_nnz = 0;
   c->have_dp5 = false;
   c->d_dpk = c->d_dpy = c->d_dpu5 = c->d_dpf = c->d_dpnval = nullptr;
@@ -397,10 +399,10 @@ int queue_tensor_filter(gh_ctx* c, const double* src, double* dst, bool transpos
   HIPCHK(c, ghk::gemm(p2s.shape, p2s.d_tiles, p2s.n_tiles, p2s.d_groups, src, X, c->stream, 6));
   {
     Timed t(c, 9);
-    HIPCHK(c, ghk::tensor_couple(c->d_tf_items, c->n_tf_wide, c->n_tf_narrow, c->d_tf_segs, c->d_tf_cols,
+    HIPCHK(c, ghk::tensor_couple(c->d_tf_items, c->n_tf_items, c->d_tf_segs, c->d_tf_cols,
                                  transpose ? c->d_tfT_soff : c->d_tf_soff, transpose ? c->d_tfT_swid : c->d_tf_swid,
-                                 transpose ? c->d_tfT_lidx : c->d_tf_lidx, transpose ? c->d_tfT_val : c->d_tf_val, X,
-                                 Y, c->stream));
+                                 transpose ? c->d_tfT_perm : c->d_tf_perm, transpose ? c->d_tfT_lidx : c->d_tf_lidx,
+                                 transpose ? c->d_tfT_val : c->d_tf_val, X, Y, c->stream));
   }
   HIPCHK(c, ghk::gemm(s2p.shape, s2p.d_tiles, s2p.n_tiles, s2p.d_groups, Y, dst, c->stream, 7));
   return GH_OK;
@@ -595,11 +597,11 @@ int build_tensor_filter(gh_ctx* c) {
   std::vector<TfSeg> segs;
   std::vector<TfCol> colv;
   std::vector<long long> soff[2];
-  std::vector<int> swid[2], lidx[2];
+  std::vector<int> swid[2], perm[2], lidx[2];
   std::vector<double> val[2];
   struct Work {
-    int seg, col_begin, ncols;
-    double cost;
+    int seg, col_begin, ncols, nc;
+    std::vector<double> slice_cost;
   };
   std::vector<Work> work;
   std::map<int, bool> done;
@@ -642,36 +644,48 @@ int build_tensor_filter(gh_ctx* c) {
         for (int r = 0; r < c->shells[k].n_r; ++r)
           colv.push_back(TfCol{xoff[k] + (long long)r * nsp, (long long)c->shells[k].n_r * nsp});
     const int ncols = int(colv.size()) - col_begin;
-    // segments: per tensor, consecutive degrees while the rows fit one wide item
+    // segments: per tensor, consecutive degrees while the rows fit the
+    // 8-column items (a single degree may be larger: fewer columns per item)
     for (auto& tz : tens) {
       const int e0 = tz[0], ne = tz[1];
       for (int l0 = 0; l0 <= L;) {
         int l1 = l0 + 1;
-        while (l1 <= L && ne * ((l1 + 1) * (l1 + 1) - l0 * l0) <= TF_WIDE_ROWS) ++l1;
+        while (l1 <= L && ne * ((l1 + 1) * (l1 + 1) - l0 * l0) <= 1024) ++l1;
         const int s0 = l0 * l0, nsg = l1 * l1 - s0, n = ne * nsg;
         if (n > TF_MAX_ROWS) return fail(c, GH_ERR_ARG, "tensor filter: L too large for the coupling kernel");
-        const int seg_id = int(segs.size());
+        const int seg_id = int(segs.size()), nslice = (n + 63) / 64;
         segs.push_back(TfSeg{e0, ne, s0, nsg, int(soff[0].size()), 0});
-        double cost = 0.0;
+        std::vector<double> cost(nslice, 0.0);
         for (int pass = 0; pass < 2; ++pass) {
           const ghtf::Csr& M = pass ? FT : F;
-          for (int q0 = 0; q0 < n; q0 += 64) {
-            // one slice: rows q0 .. q0 + 63 of the segment
+          auto row_of = [&](int i) { return (long long)(e0 + i / nsg) * ns + s0 + i % nsg; };
+          // rows sorted by their number of couplings (longest first)
+          std::vector<int> order(n);
+          for (int i = 0; i < n; ++i) order[i] = i;
+          std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return M.row_ptr[row_of(a) + 1] - M.row_ptr[row_of(a)] > M.row_ptr[row_of(b) + 1] - M.row_ptr[row_of(b)];
+          });
+          for (int q = 0; q < nslice; ++q) {
             int w = 0;
-            for (int lane = 0; lane < 64 && q0 + lane < n; ++lane) {
-              const int i = q0 + lane, e = e0 + i / nsg, sl = s0 + i % nsg;
-              const long long row = (long long)e * ns + sl;
+            for (int lane = 0; lane < 64 && 64 * q + lane < n; ++lane) {
+              const long long row = row_of(order[64 * q + lane]);
               w = std::max<int>(w, int(M.row_ptr[row + 1] - M.row_ptr[row]));
             }
             const long long off = (long long)val[pass].size();
             soff[pass].push_back(off);
             swid[pass].push_back(w);
-            if (!pass) cost += w;
+            cost[q] = std::max(cost[q], double(w));
             val[pass].resize(size_t(off) + size_t(64) * w, 0.0);
             lidx[pass].resize(size_t(off) + size_t(64) * w, 0);
-            for (int lane = 0; lane < 64 && q0 + lane < n; ++lane) {
-              const int i = q0 + lane, e = e0 + i / nsg, sl = s0 + i % nsg;
-              const long long row = (long long)e * ns + sl;
+            for (int lane = 0; lane < 64; ++lane) {
+              const int pos = 64 * q + lane;
+              if (pos >= n) {
+                perm[pass].push_back(-1);
+                continue;
+              }
+              const int i = order[pos];
+              perm[pass].push_back(i);
+              const long long row = row_of(i);
               int k = 0;
               for (long long p = M.row_ptr[row]; p < M.row_ptr[row + 1]; ++p, ++k) {
                 const int e2 = M.col[p] / ns, s2 = M.col[p] % ns;
@@ -683,31 +697,39 @@ int build_tensor_filter(gh_ctx* c) {
             }
           }
         }
-        work.push_back(Work{seg_id, col_begin, ncols, cost});
+        work.push_back(Work{seg_id, col_begin, ncols, tf_cols_for_rows(n), cost});
         l0 = l1;
       }
     }
   }
-  // work items: wide (TF_WIDE columns) for segments of at most TF_WIDE_ROWS
-  // rows, narrow otherwise; the items of one segment go to one XCD (its part
-  // of the matrix stays in that XCD's L2), segments balanced over the 8 XCDs
-  // by their slice widths times the columns; list position p runs on XCD p % 8.
+  // work items per column class: (segment, nc columns, all its slices); the
+  // items of one segment go to one XCD (its part of the matrix stays in that
+  // XCD's L2), segments balanced over the 8 XCDs; list position p of a launch
+  // runs on XCD p % 8.
   std::vector<TfItem> items;
-  for (int cls = 0; cls < 2; ++cls) {
-    const int per = cls ? TF_NARROW : TF_WIDE;
-    std::vector<Work> ws;
-    for (auto& w : work) {
-      const bool wide = segs[w.seg].ne * segs[w.seg].nsg <= TF_WIDE_ROWS;
-      if (wide == (cls == 0)) ws.push_back(w);
-    }
-    std::sort(ws.begin(), ws.end(), [](const Work& a, const Work& b) { return a.cost * a.ncols > b.cost * b.ncols; });
+  const int cls_nc[3] = {8, 4, 2};
+  for (int cls = 0; cls < 3; ++cls) {
+    std::vector<const Work*> ws;
+    for (auto& w : work)
+      if (w.nc == cls_nc[cls]) ws.push_back(&w);
     std::vector<std::vector<TfItem>> px(8);
+    std::vector<std::pair<double, int>> order;
+    for (size_t q = 0; q < ws.size(); ++q) {
+      double tot = 0.0;
+      for (double x : ws[q]->slice_cost) tot += x;
+      order.push_back({tot * ws[q]->ncols, int(q)});
+    }
+    std::sort(order.begin(), order.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+      return a.first > b.first;
+    });
     double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (auto& w : ws) {
+    for (auto& o : order) {
+      const Work& w = *ws[o.second];
       const int x = int(std::min_element(load, load + 8) - load);
-      load[x] += w.cost * w.ncols;
-      for (int c0 = 0; c0 < w.ncols; c0 += per)
-        px[x].push_back(TfItem{w.seg, w.col_begin + c0, std::min(per, w.ncols - c0), 0});
+      load[x] += o.first;
+      const int nsl = int(w.slice_cost.size());
+      for (int c0 = 0; c0 < w.ncols; c0 += w.nc)
+        px[x].push_back(TfItem{w.seg, w.col_begin + c0, std::min(w.nc, w.ncols - c0), 0, nsl, 0, 0, 0});
     }
     size_t longest = 0;
     for (auto& v : px) longest = std::max(longest, v.size());
@@ -715,13 +737,15 @@ int build_tensor_filter(gh_ctx* c) {
     for (size_t q = 0; q < longest; ++q)
       for (int x = 0; x < 8; ++x)
         if (q < px[x].size()) items.push_back(px[x][q]);
-    (cls ? c->n_tf_narrow : c->n_tf_wide) = int(items.size() - before);
+    c->n_tf_items[cls] = int(items.size() - before);
   }
   if ((rc = upload(c, &c->d_tf_segs, segs))) return rc;
   if ((rc = upload(c, &c->d_tf_cols, colv))) return rc;
   if ((rc = upload(c, &c->d_tf_items, items))) return rc;
   if ((rc = upload(c, &c->d_tf_soff, soff[0]))) return rc;
   if ((rc = upload(c, &c->d_tf_swid, swid[0]))) return rc;
+  if ((rc = upload(c, &c->d_tf_perm, perm[0]))) return rc;
+  if ((rc = upload(c, &c->d_tfT_perm, perm[1]))) return rc;
   if ((rc = upload(c, &c->d_tf_lidx, lidx[0]))) return rc;
   if ((rc = upload(c, &c->d_tf_val, val[0]))) return rc;
   if ((rc = upload(c, &c->d_tfT_soff, soff[1]))) return rc;
@@ -1469,7 +1493,7 @@ int gh_query(const gh_ctx* c, int what, long long* value) {
     case 9: *value = c->deriv_tr ? 1 : 0; break;
     case 10: *value = c->filt_tr ? 1 : 0; break;
     case 11: *value = c->tf_nnz; break;
-    case 12: *value = c->n_tf_wide + c->n_tf_narrow; break;
+    case 12: *value = c->n_tf_items[0] + c->n_tf_items[1] + c->n_tf_items[2]; break;
     default: return GH_ERR_ARG;
   }
   return GH_OK;

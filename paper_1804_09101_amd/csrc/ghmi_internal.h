@@ -30,15 +30,17 @@ struct PtBlock {
 // Tensor-coupled filter, the coupling step on the coefficient array X (per
 // shell [field][radius][nsp]): Y = F X for every column (shell, radius).
 // The rows of F come in segments: rows (e, s) with e0 <= e < e0 + ne and
-// s0 <= s < s0 + nsg, numbered e-major, whose couplings all stay in the
-// segment.  A segment's rows are cut into slices of 64 (one per wave), stored
-// sliced-ELL: slice q holds width[q] couplings per row, the k-th of every row
-// contiguous (val/lidx[off[q] + 64 k + lane], zero-padded); lidx is the
-// input's position inside the segment, (e' - e0) * nsg + (s' - s0).  A work
-// item stages its segment's inputs for up to TF_WIDE (segments of at most
-// TF_WIDE_ROWS rows) or TF_NARROW columns in LDS and writes the segment's
-// outputs for them.
-enum { TF_WIDE = 8, TF_NARROW = 2, TF_WIDE_ROWS = 1024, TF_MAX_ROWS = 4096 };
+// s0 <= s < s0 + nsg (segment row i = (e - e0) * nsg + (s - s0)), whose
+// couplings all stay in the segment.  A segment's rows, sorted by their number
+// of couplings, are cut into slices of 64 (one per wave) stored sliced-ELL:
+// slice q holds width[q] couplings per row, the k-th of every row contiguous
+// (val/lidx[off[q] + 64 k + lane], zero-padded), perm[64 q + lane] is the
+// segment row of the lane (-1: padding); lidx is the input's segment row.  A
+// work item stages its segment's inputs for ncol columns in LDS (64 KB: up to
+// 8 columns for segments of at most 1024 rows, 4 up to 2048, 2 up to 4096) and
+// computes the slices [q0, q1) for them.
+enum { TF_LDS_DOUBLES = 8192, TF_MAX_ROWS = 4096 };
+inline int tf_cols_for_rows(int n) { return n <= 1024 ? 8 : (n <= 2048 ? 4 : 2); }
 struct TfSeg {
   int e0, ne, s0, nsg;
   int slice0, pad;     // first slice of the segment in the slice tables
@@ -48,7 +50,7 @@ struct TfCol {
   long long fstride;  // distance between fields: n_r nsp
 };
 struct TfItem {
-  int seg, col0, ncol, pad;
+  int seg, col0, ncol, q0, q1, pad0, pad1, pad2;
 };
 
 // Kernel launchers (ghmi_kernels.hip).  All are asynchronous on `st`.
@@ -83,10 +85,10 @@ hipError_t ang_theta(int nmax, const ShellDev* sh, const PtBlock* tblk, int n_tb
 
 hipError_t fill_pattern(double* x, long long n, hipStream_t st);
 
-// items[0, n_wide) stage TF_WIDE columns, items[n_wide, n_wide + n_narrow) TF_NARROW.
-hipError_t tensor_couple(const TfItem* items, int n_wide, int n_narrow, const TfSeg* segs, const TfCol* cols,
-                         const long long* soff, const int* swidth, const int* lidx, const double* val,
-                         const double* X, double* Y, hipStream_t st);
+// n_items[3]: the items come grouped by their column class (8, 4, 2 columns).
+hipError_t tensor_couple(const TfItem* items, const int n_items[3], const TfSeg* segs, const TfCol* cols,
+                         const long long* soff, const int* swidth, const int* perm, const int* lidx,
+                         const double* val, const double* X, double* Y, hipStream_t st);
 
 hipError_t radial(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* dtab,
                   const double* u, double* dR, int ncomp_lo, int ncomp_hi, hipStream_t st);

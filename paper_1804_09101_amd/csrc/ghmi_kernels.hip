@@ -1120,25 +1120,36 @@ __global__ __launch_bounds__(256) void k_ang_theta(const ShellDev* __restrict__ 
 
 // ---------------------------------------------------------------------------
 // Tensor-coupled filter: the coupling step Y = F X on the angular
-// coefficients.  One workgroup (4 waves) per (segment, column chunk): the
-// segment's inputs of NC columns (shell, radius) are staged in LDS as
-// [input][column] (runs of nsg consecutive coefficients per field from HBM),
-// then every wave takes 64-row slices: lane = row, the k-th couplings of the
-// 64 rows are one contiguous load of values and one of input positions, and
-// each coupling is applied to the NC staged columns of its input (NC/2
-// 16-byte LDS reads).  Consecutive lanes own consecutive coefficients s, so
-// the stores of Y are contiguous runs per column.
+// coefficients.  One workgroup (16 waves) per work item (segment, NC columns
+// (shell, radius), a range of slices): the segment's inputs are staged in
+// LDS, NC doubles per input row (runs of nsg consecutive coefficients per
+// field from HBM); then every wave takes a 64-row slice: lane = row, the k-th
+// couplings of the 64 rows are one contiguous load of values and one of input
+// rows, and each coupling is applied to the staged columns of its input (NC/2
+// 16-byte LDS reads).  Column pair p of input row r sits at pair slot
+// (p + r/4) mod (NC/2), so the reads of 64 random rows spread over the LDS
+// banks.
 // ---------------------------------------------------------------------------
+constexpr int TF_THREADS = 1024;
+
+template <int NP>
+__device__ __forceinline__ int tf_slot(int row, int pair) {
+  return row * NP + ((pair + (row >> 2)) & (NP - 1));
+}
+
 template <int NC>
-__global__ __launch_bounds__(256) void k_tensor_couple(const TfItem* __restrict__ items,
-                                                       const TfSeg* __restrict__ segs,
-                                                       const TfCol* __restrict__ cols,
-                                                       const long long* __restrict__ soff,
-                                                       const int* __restrict__ swidth,
-                                                       const int* __restrict__ lidx,
-                                                       const double* __restrict__ val,
-                                                       const double* __restrict__ X, double* __restrict__ Y) {
-  extern __shared__ double lds[];
+__global__ __launch_bounds__(TF_THREADS) void k_tensor_couple(const TfItem* __restrict__ items,
+                                                              const TfSeg* __restrict__ segs,
+                                                              const TfCol* __restrict__ cols,
+                                                              const long long* __restrict__ soff,
+                                                              const int* __restrict__ swidth,
+                                                              const int* __restrict__ perm,
+                                                              const int* __restrict__ lidx,
+                                                              const double* __restrict__ val,
+                                                              const double* __restrict__ X, double* __restrict__ Y) {
+  constexpr int NP = NC / 2;
+  static_assert(NP == 1 || NP == 2 || NP == 4, "column pairs must be a power of two");
+  __shared__ double2 lds[TF_LDS_DOUBLES / 2];
   const TfItem it = items[blockIdx.x];
   const TfSeg sg = segs[it.seg];
   const int n = sg.ne * sg.nsg;
@@ -1150,37 +1161,58 @@ __global__ __launch_bounds__(256) void k_tensor_couple(const TfItem* __restrict_
     cbase[c] = cc.base;
     cstr[c] = cc.fstride;
   }
-  for (int i = threadIdx.x; i < n; i += 256) {
+  for (int i = threadIdx.x; i < n; i += TF_THREADS) {
     const int e = i / sg.nsg, s = i - e * sg.nsg;
+    double x[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c)
-      lds[i * NC + c] = (c < nc) ? X[cbase[c] + (long long)(sg.e0 + e) * cstr[c] + sg.s0 + s] : 0.0;
+      x[c] = (c < nc) ? X[cbase[c] + (long long)(sg.e0 + e) * cstr[c] + sg.s0 + s] : 0.0;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) lds[tf_slot<NP>(i, p)] = double2{x[2 * p], x[2 * p + 1]};
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nsl = (n + 63) >> 6;
-  for (int q = wave; q < nsl; q += 4) {
+  for (int q = it.q0 + wave; q < it.q1; q += TF_THREADS / 64) {
     const long long off = soff[sg.slice0 + q];
     const int w = swidth[sg.slice0 + q];
+    const int row = perm[(long long)(sg.slice0 + q) * 64 + lane];
     double acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = 0.0;
     const double* __restrict__ vq = val + off + lane;
     const int* __restrict__ iq = lidx + off + lane;
-#pragma unroll 4
-    for (int k = 0; k < w; ++k) {
-      const double v = vq[64 * k];
-      const double2* xp = reinterpret_cast<const double2*>(lds + iq[64 * k] * NC);
+    // groups of 16 couplings: all 32 loads issued before the first is used
+    constexpr int U = 16;
+    int k = 0;
+    for (; k + U <= w; k += U) {
+      double v[U];
+      int li[U];
 #pragma unroll
-      for (int c2 = 0; c2 < NC / 2; ++c2) {
-        const double2 x = xp[c2];
-        acc[2 * c2] += v * x.x;
-        acc[2 * c2 + 1] += v * x.y;
+      for (int u = 0; u < U; ++u) {
+        v[u] = vq[64 * (k + u)];
+        li[u] = iq[64 * (k + u)];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          const double2 x = lds[tf_slot<NP>(li[u], p)];
+          acc[2 * p] += v[u] * x.x;
+          acc[2 * p + 1] += v[u] * x.y;
+        }
+    }
+    for (; k < w; ++k) {
+      const double v = vq[64 * k];
+      const int li = iq[64 * k];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const double2 x = lds[tf_slot<NP>(li, p)];
+        acc[2 * p] += v * x.x;
+        acc[2 * p + 1] += v * x.y;
       }
     }
-    const int i = q * 64 + lane;
-    if (i < n) {
-      const int e = i / sg.nsg, s = i - e * sg.nsg;
+    if (row >= 0) {
+      const int e = row / sg.nsg, s = row - e * sg.nsg;
 #pragma unroll
       for (int c = 0; c < NC; ++c)
         if (c < nc) Y[cbase[c] + (long long)(sg.e0 + e) * cstr[c] + sg.s0 + s] = acc[c];
@@ -1210,15 +1242,21 @@ hipError_t fill_pattern(double* x, long long n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t tensor_couple(const TfItem* items, int n_wide, int n_narrow, const TfSeg* segs, const TfCol* cols,
-                         const long long* soff, const int* swidth, const int* lidx, const double* val,
-                         const double* X, double* Y, hipStream_t st) {
-  if (n_wide > 0)
-    hipLaunchKernelGGL(k_tensor_couple<TF_WIDE>, dim3(n_wide), dim3(256), size_t(8) * TF_WIDE * TF_WIDE_ROWS, st,
-                       items, segs, cols, soff, swidth, lidx, val, X, Y);
-  if (n_narrow > 0)
-    hipLaunchKernelGGL(k_tensor_couple<TF_NARROW>, dim3(n_narrow), dim3(256), size_t(8) * TF_NARROW * TF_MAX_ROWS,
-                       st, items + n_wide, segs, cols, soff, swidth, lidx, val, X, Y);
+hipError_t tensor_couple(const TfItem* items, const int n_items[3], const TfSeg* segs, const TfCol* cols,
+                         const long long* soff, const int* swidth, const int* perm, const int* lidx,
+                         const double* val, const double* X, double* Y, hipStream_t st) {
+  const TfItem* it = items;
+  if (n_items[0] > 0)
+    hipLaunchKernelGGL(k_tensor_couple<8>, dim3(n_items[0]), dim3(TF_THREADS), 0, st, it, segs, cols, soff, swidth,
+                       perm, lidx, val, X, Y);
+  it += n_items[0];
+  if (n_items[1] > 0)
+    hipLaunchKernelGGL(k_tensor_couple<4>, dim3(n_items[1]), dim3(TF_THREADS), 0, st, it, segs, cols, soff, swidth,
+                       perm, lidx, val, X, Y);
+  it += n_items[1];
+  if (n_items[2] > 0)
+    hipLaunchKernelGGL(k_tensor_couple<2>, dim3(n_items[2]), dim3(TF_THREADS), 0, st, it, segs, cols, soff, swidth,
+                       perm, lidx, val, X, Y);
   return hipGetLastError();
 }
 
