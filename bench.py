@@ -182,6 +182,23 @@ def batched_comparison(steps):
     return out
 
 
+def interface_state_measurement(solver, u0_dev, steps):
+    """The same RK3 steps with the interface projection recomputed from the
+    state before every boundary treatment (gh_set_interface 1)."""
+    import torch
+    solver.set_interface(1)
+    u = u0_dev.clone()
+    solver.step(u, 5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.step(u, steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    solver.set_interface(0)
+    return {"mode": "interface projection from the state (gh_set_interface 1)", "ms_per_step": t / steps * 1e3,
+            "value": solver.P * 3 * steps / t, "unit": "grid-point RHS evals/s"}
+
+
 def tensor_filter_measurement(wl, steps, applications=50):
     """The tensor-coupled ExpCheb filter (filter_kind 2, the exponential
     factors of the default filter in total angular momentum j) on the same
@@ -500,6 +517,8 @@ def main():
         out["transform"] = transform_measurement(solver, dev(u0), args.steps)
         log(f"transform: {out['transform']['ms_per_step']:.3f} ms/step, graph "
             f"{P * 3 * args.steps / out['transform']['graph_value'] / args.steps * 1e3:.3f} ms/step")
+    out["interface_state"] = interface_state_measurement(solver, dev(u0), args.steps)
+    log(f"interface from state: {out['interface_state']['ms_per_step']:.3f} ms/step")
     if not args.no_tensor_filter:
         out["tensor_filter"] = tensor_filter_measurement(wl, min(args.steps, 50))
         tfm = out["tensor_filter"]

@@ -253,7 +253,21 @@ int gh_kernel_stats(gh_ctx* ctx, int kind, long long* launches, double* total_ms
 int gh_query(const gh_ctx* ctx, int what, long long* value);
 /* (continued) 11: number of stored couplings of the tensor-coupled filter
  * (kinds 2, 3; summed over the distinct L of the domain, else 0); 12: work
- * items of one launch of its coupling kernel. */
+ * items of one launch of its coupling kernel; 13: the interface mode
+ * (gh_set_interface). */
+
+/* Where the characteristic projection at shell interfaces comes from.
+ * mode 0 (default): the unit normal's metric normalisation and the upwind
+ * choice (signs of the characteristic speeds) are taken from u_bg at
+ * gh_set_background and frozen, so the boundary treatment is a fixed linear
+ * map.  mode 1: they are recomputed from the state whose d_t u is being
+ * treated (the paper's internal boundaries compute the characteristic
+ * variables from the evolved fields; section on benchmarks of the overall
+ * code, the ApplyBCs cases), before every boundary treatment of gh_rhs,
+ * gh_step, gh_step_stages and gh_step_dp5.  The reverse-pass entry points
+ * (gh_rhs_vjp, gh_step_vjp, gh_step_vjp_stages) need mode 0 and return
+ * GH_ERR_ARG in mode 1.  Drops a captured step graph when the mode changes. */
+int gh_set_interface(gh_ctx* ctx, int mode);
 
 /* Apply the domain's angular filter (filter_kind 1-3) once: out = F u.
  * Device pointers, [50 P] each, distinct (GH_ERR_ARG if out == u, or if the

@@ -31,10 +31,13 @@ class Shell:
 class Domain:
     """Shells of one or more independent instances (black holes)."""
 
-    def __init__(self, shells, filter_params=None, filter_kind=1):
+    def __init__(self, shells, filter_params=None, filter_kind=1, interface_from_state=False):
         """filter_kind (with filter_params): 1 angular exponential filter of every
         component, (eta_c, alpha, order); 2 tensor-coupled ExpCheb filter,
-        (eta_c, alpha, order); 3 tensor-coupled Heaviside filter, (eta_c,)."""
+        (eta_c, alpha, order); 3 tensor-coupled Heaviside filter, (eta_c,).
+        interface_from_state: the characteristic projection and upwind choice
+        at interfaces come from the state whose d_t u is being computed instead
+        of the background u_bg."""
         self.shells = list(shells)
         self.grids = [_grid.ShellGrid(s.n_r, s.L, s.r_in, s.r_out) for s in self.shells]
         self.spheres = {}
@@ -47,6 +50,7 @@ class Domain:
         self.P = int(self.offsets[-1])
         self.filter_params = filter_params
         self.filter_kind = filter_kind if filter_params is not None else 0
+        self.interface_from_state = bool(interface_from_state)
         # interfaces: consecutive shells of one instance
         self.interfaces = []
         for k in range(len(self.shells) - 1):
@@ -129,11 +133,12 @@ class Domain:
             dHk = dHb[k].reshape((4, 4) + dHb[k].shape[1:])
             out.append(_gh.rhs_pointwise(ub[k], du, Hb[k], dHk, g0, g1, g2))
         if apply_bc:
-            self.apply_bc(out, self.split(u_bg, 50), gammas)
+            self.apply_bc(out, ub if self.interface_from_state else self.split(u_bg, 50), gammas)
         return self.join(out)
 
     def interface_projection(self, k, ubg_blk):
-        """Frozen unit normal s = +r_hat (g-normalised) at the outer face of shell k."""
+        """Unit normal s = +r_hat (g-normalised) at the outer face of shell k,
+        with the metric of the given block (the background, or the state)."""
         g = self.grids[k]
         psi, _, _ = _gh.unpack_fields(ubg_blk[:, -1])
         geo = _gh.Geometry(psi)
@@ -150,7 +155,8 @@ class Domain:
         internal boundaries exchange characteristic fields, the outer boundary
         gets a boundary condition, excision boundaries need none.  Readings:
         * interface (shell A inside, B outside, s = +r_hat normalised with the
-          background metric of u_bg): project both sides' d_t u onto u^psi,
+          metric of ubg_blocks at A's outer face: the background u_bg, or the
+          state itself when interface_from_state): project both sides' d_t u onto u^psi,
           u^0, u^+, u^-; take each of u^0, u^+-  from the upwind side (speed > 0:
           A, < 0: B, = 0: the average) and u^psi as the average of both sides;
           reconstruct and store the same d_t u on both sides;

@@ -59,6 +59,11 @@ struct gh_ctx {
   int n_cblk = 0;
   int maxr = 0;                // register-array size of the column radial kernel (0: point form)
   double *d_dtab = nullptr, *d_angtab = nullptr, *d_radtab = nullptr, *d_bctab = nullptr;
+  // interface projection from the state (gh_set_interface 1): its own table,
+  // rebuilt from the state before every boundary treatment, and scratch for
+  // the excision speeds the table kernel also writes
+  int iface_mode = 0, bc_total = 0;
+  double *d_bctab_s = nullptr, *d_exscr = nullptr;
   std::map<int, double*> d_angop;   // per L: [S][2S], B operand (Theta^T | Phi^T)
   std::map<int, double*> d_filtop;  // per L: [S][S], B operand F^T
   std::map<int, double*> d_angopT;  // per L: [2S][S], B operand (Theta ; Phi) of the transposed derivative
@@ -245,6 +250,8 @@ void free_domain(gh_ctx* c) {
   c->d_dprej = c->d_dpacc = nullptr;
   c->d_sh = nullptr; c->d_blk = nullptr; c->d_cblk = nullptr; c->d_fblk = nullptr;
   c->d_dtab = c->d_angtab = c->d_radtab = c->d_bctab = nullptr;
+  c->iface_mode = c->bc_total = 0;
+  c->d_bctab_s = c->d_exscr = nullptr;
   c->d_inst_range = nullptr; c->d_wsum = c->d_partial = nullptr;
   c->d_dR = c->d_dA = c->d_W = c->d_ua = c->d_ub = nullptr;
   c->d_H = c->d_dH = nullptr;
@@ -426,6 +433,18 @@ int queue_filter(gh_ctx* c, const double* src, double* dst) {
   return GH_OK;
 }
 
+// The interface table the boundary treatment of d_t u(x) uses: the frozen
+// one, or (gh_set_interface 1) one rebuilt from x now.
+int interface_table(gh_ctx* c, const double* x, const double** tab) {
+  if (!c->iface_mode) {
+    *tab = c->d_bctab;
+    return GH_OK;
+  }
+  HIPCHK(c, ghk::bc_setup(c->d_sh, c->n_shells, c->max_S, c->d_angtab, x, c->d_bctab_s, c->d_exscr, c->stream));
+  *tab = c->d_bctab_s;
+  return GH_OK;
+}
+
 int queue_rhs(gh_ctx* c, const double* u, double* out) {
   int rc = queue_derivs(c, u);
   if (rc) return rc;
@@ -436,7 +455,9 @@ int queue_rhs(gh_ctx* c, const double* u, double* out) {
   }
   {
     Timed t(c, 4);
-    HIPCHK(c, ghk::boundary(c->d_sh, c->n_shells, c->max_S, c->d_bctab, c->d_gamma, out, c->stream));
+    const double* tab = nullptr;
+    if ((rc = interface_table(c, u, &tab))) return rc;
+    HIPCHK(c, ghk::boundary(c->d_sh, c->n_shells, c->max_S, tab, c->d_gamma, out, c->stream));
   }
   return GH_OK;
 }
@@ -457,7 +478,9 @@ int queue_stage(gh_ctx* c, double c0, const double* u0, double c1, const double*
   }
   {
     Timed t(c, 4);
-    HIPCHK(c, ghk::stage_bc(c->d_sh, c->d_blk, c->n_blk, c->d_bctab, c->d_gamma, c->d_dt, c0, u0, c1, us, c->d_W,
+    const double* tab = nullptr;
+    if ((rc = interface_table(c, us, &tab))) return rc;
+    HIPCHK(c, ghk::stage_bc(c->d_sh, c->d_blk, c->n_blk, tab, c->d_gamma, c->d_dt, c0, u0, c1, us, c->d_W,
                             out, c->stream));
   }
   return GH_OK;
@@ -918,6 +941,7 @@ int gh_set_domain(gh_ctx* c, int n_inst, int n_shells, const gh_shell* shells, i
   if ((rc = upload(c, &c->d_shell_range, srange))) return rc;
   if ((rc = upload(c, &c->d_wsum, wsum))) return rc;
   if ((rc = dalloc(c, &c->d_bctab, size_t(std::max(bc_total, 1))))) return rc;
+  c->bc_total = bc_total;
   if ((rc = dalloc(c, &c->d_partial, size_t(c->n_blk)))) return rc;
 
   // angular operators (and filters), uploaded once per L
@@ -1305,6 +1329,8 @@ int gh_rhs_vjp(gh_ctx* c, const double* u, const double* lam, double* lam_u, dou
   if (rc) return rc;
   if (!u || !lam || !lam_u || lam_u == u || lam_u == lam)
     return fail(c, GH_ERR_ARG, "u, lam, lam_u must be device pointers and lam_u distinct from u and lam");
+  if (c->iface_mode)
+    return fail(c, GH_ERR_ARG, "the reverse pass needs the frozen interface projection (gh_set_interface 0)");
   HIPCHK(c, hipSetDevice(c->device));
   if ((rc = ensure_adjoint(c))) return rc;
   return queue_rhs_vjp(c, u, lam, lam_u, 1.0, 0, g_gamma);
@@ -1350,6 +1376,8 @@ int gh_step_vjp(gh_ctx* c, const double* u_n, const double* lam_np1, double* lam
   if (rc) return rc;
   if (!u_n || !lam_np1 || !lam_n || lam_n == u_n)
     return fail(c, GH_ERR_ARG, "u_n, lam_np1, lam_n must be device pointers and lam_n distinct from u_n");
+  if (c->iface_mode)
+    return fail(c, GH_ERR_ARG, "the reverse pass needs the frozen interface projection (gh_set_interface 0)");
   HIPCHK(c, hipSetDevice(c->device));
   if ((rc = ensure_adjoint(c))) return rc;
   // recompute the stages: u1 = u + h L(u), u2 = 3/4 u + 1/4 (u1 + h L(u1))
@@ -1384,6 +1412,8 @@ int gh_step_vjp_stages(gh_ctx* c, const double* u_n, const double* u1, const dou
   if (!u_n || !u1 || !u2 || !lam_np1 || !lam_n || lam_n == u_n || lam_n == u1 || lam_n == u2 ||
       (derivs && lam_n == derivs))
     return fail(c, GH_ERR_ARG, "device pointers required; lam_n must not alias u_n, u1, u2 or derivs");
+  if (c->iface_mode)
+    return fail(c, GH_ERR_ARG, "the reverse pass needs the frozen interface projection (gh_set_interface 0)");
   HIPCHK(c, hipSetDevice(c->device));
   if ((rc = ensure_adjoint(c))) return rc;
   return queue_step_vjp(c, u_n, u1, u2, lam_np1, lam_n, g_gamma, derivs);
@@ -1444,6 +1474,21 @@ int gh_constraints_vjp(gh_ctx* c, const double* u, const double* lam_norm, doubl
   return GH_OK;
 }
 
+int gh_set_interface(gh_ctx* c, int mode) {
+  if (!c) return GH_ERR_ARG;
+  if (!c->have_domain) return fail(c, GH_ERR_ORDER, "gh_set_domain has not been called");
+  if (mode != 0 && mode != 1) return fail(c, GH_ERR_ARG, "mode must be 0 (background) or 1 (state)");
+  HIPCHK(c, hipSetDevice(c->device));
+  int rc;
+  if (mode == 1 && !c->d_bctab_s) {
+    if ((rc = dalloc(c, &c->d_bctab_s, size_t(std::max(c->bc_total, 1))))) return rc;
+    if ((rc = dalloc(c, &c->d_exscr, size_t(c->n_shells) * c->max_S))) return rc;
+  }
+  if (mode != c->iface_mode) drop_graph(c);
+  c->iface_mode = mode;
+  return GH_OK;
+}
+
 int gh_filter(gh_ctx* c, const double* u, double* out) {
   if (!c || !u || !out) return GH_ERR_ARG;
   if (!c->have_domain) return fail(c, GH_ERR_ORDER, "gh_set_domain has not been called");
@@ -1494,6 +1539,7 @@ int gh_query(const gh_ctx* c, int what, long long* value) {
     case 10: *value = c->filt_tr ? 1 : 0; break;
     case 11: *value = c->tf_nnz; break;
     case 12: *value = c->n_tf_items[0] + c->n_tf_items[1] + c->n_tf_items[2]; break;
+    case 13: *value = c->iface_mode; break;
     default: return GH_ERR_ARG;
   }
   return GH_OK;

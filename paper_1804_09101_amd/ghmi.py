@@ -26,7 +26,7 @@ EXPORTS = [
     "gh_last_error", "gh_grid_coords", "gh_host_operator", "gh_set_timing", "gh_kernel_stats",
     "gh_query", "gh_rhs_vjp", "gh_step_vjp", "gh_constraints_vjp",
     "gh_set_graph", "gh_step_stages", "gh_step_vjp_stages", "gh_step_dp5", "gh_set_angular",
-    "gh_filter", "gh_tensor_filter_matrix",
+    "gh_filter", "gh_tensor_filter_matrix", "gh_set_interface",
 ]
 
 KERNEL_KINDS = {"deriv_gemm": 0, "filter_gemm": 1, "radial": 2, "pointwise": 3, "boundary": 4,
@@ -87,6 +87,7 @@ def load_library(path=LIB_PATH):
         "gh_set_angular": (i, [vp, i]),
         "gh_step_vjp_stages": (i, [vp, vp, vp, vp, vp, vp, vp, vp]),
         "gh_filter": (i, [vp, vp, vp]),
+        "gh_set_interface": (i, [vp, i]),
         "gh_tensor_filter_matrix": (i, [i, i, pd, i, pll, pll, ctypes.POINTER(ctypes.c_int), pd]),
     }
     for name, (res, args) in sig.items():
@@ -288,6 +289,11 @@ class GHSolver:
         self._check(self.lib.gh_step_vjp(self.h, self._dev(u_n, 50, "u_n"), self._dev(lam_np1, 50, "lam_np1"),
                                          self._dev(out, 50, "lam_n"), g))
         return out
+
+    def set_interface(self, mode):
+        """0: interface projection from the background (frozen, default); 1: from
+        the state at every boundary treatment (no reverse pass in this mode)."""
+        self._check(self.lib.gh_set_interface(self.h, int(mode)))
 
     def filter(self, u, out=None):
         """The domain's angular filter applied once: out = F u (a new field if out is None)."""

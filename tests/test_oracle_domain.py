@@ -129,3 +129,27 @@ def test_pulse_evolution_stays_bounded_and_filter_keeps_interfaces_equal():
     assert np.max(np.abs(b[0][:, -1] - b[1][:, 0])) < 1e-13      # roundoff only
     assert np.max(np.abs(u - ubg)) < 2e-3
     assert d.constraint_norm(u, H)[0] < 1.5 * n0
+
+
+def test_interface_projection_from_the_state():
+    """With the state equal to the background the two readings of the
+    interface projection coincide exactly; for a perturbed state they differ
+    (only at interface points), and the outer and excision treatment is the
+    same in both."""
+    from paper_1804_09101_amd import configs, inputs
+    shells = [(0, 7, 5, 1.8, 2.6), (0, 7, 5, 2.6, 3.6), (0, 6, 5, 3.6, 5.0)]
+    wl = configs.Workload("iface", shells, [(1.0, 0.4, (0.1, 0.2, 1.0))], [(1.0, -1.0, 1.0)], [0.005], None, 1, None)
+    frozen = domain.Domain([domain.Shell(*s) for s in shells])
+    state = domain.Domain([domain.Shell(*s) for s in shells], interface_from_state=True)
+    u0, ubg, H, dH = wl.initial_data(frozen.xyz(), frozen.offsets)
+    assert np.array_equal(frozen.rhs(ubg, H, dH, ubg, wl.gamma), state.rhs(ubg, H, dH, ubg, wl.gamma))
+    u = u0 + frozen.to_layout(inputs.smooth_random_field(frozen.xyz(), 5e-2, 2, 3, 2.0))
+    a = frozen.split(frozen.rhs(u, H, dH, ubg, wl.gamma), 50)
+    b = frozen.split(state.rhs(u, H, dH, ubg, wl.gamma), 50)
+    for k in range(3):
+        # the points away from the two interfaces: shell 0 all but its outer
+        # face, shell 1 its interior, shell 2 all but its inner face
+        inner = [slice(None, -1), slice(1, -1), slice(1, None)][k]
+        assert np.array_equal(a[k][:, inner], b[k][:, inner])
+    assert np.max(np.abs(a[0][:, -1] - b[0][:, -1])) > 1e-6 * np.max(np.abs(a[0][:, -1]))
+    assert np.array_equal(a[2][:, -1], b[2][:, -1])          # outer boundary: Dirichlet in both
