@@ -225,8 +225,11 @@ int gh_step_vjp_stages(gh_ctx* ctx, const double* u_n, const double* u1, const d
  * not aliasing u).  A zero norm contributes nothing. */
 int gh_constraints_vjp(gh_ctx* ctx, const double* u, const double* lam_norm, double* lam_u);
 
-/* Kernel timing.  While enabled, every launch of the kernels named below is
- * bracketed by HIP events on the context's stream (a small overhead).
+/* Kernel timing.  enable 1: every launch of the kernels named below is
+ * bracketed by HIP events on the context's stream (about 4 us per launch on
+ * the 8-shell workload's RK3 step); 2: only the angular derivative GEMM
+ * (kind 0), the least overhead for timing the dominant kernel inside a timed
+ * run; 0: off.  GH_ERR_ARG for other values.
  * gh_kernel_stats waits for the recorded work, returns the number of launches
  * and their summed duration in milliseconds since timing was enabled or last
  * queried, and clears that kind's record.

@@ -131,8 +131,9 @@ struct gh_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
 
-  // kernel timing (gh_set_timing)
+  // kernel timing (gh_set_timing): every kind, or (timing_only >= 0) one kind
   bool timing = false;
+  int timing_only = -1;
   struct Rec { hipEvent_t a, b; int kind; };
   std::vector<Rec> recs;
 };
@@ -157,7 +158,8 @@ struct Timed {
   int kind;
   hipEvent_t a = nullptr, b = nullptr;
   Timed(gh_ctx* c_, int k) : c(c_), kind(k) {
-    if (c->timing && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+    if (c->timing && (c->timing_only < 0 || c->timing_only == k) && hipEventCreate(&a) == hipSuccess &&
+        hipEventCreate(&b) == hipSuccess)
       (void)hipEventRecord(a, c->stream);
   }
   ~Timed() {
@@ -1549,8 +1551,10 @@ int gh_set_timing(gh_ctx* c, int enable) {
   if (!c) return GH_ERR_ARG;
   HIPCHK(c, hipSetDevice(c->device));
   if (c->stream) HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (enable < 0 || enable > 2) return fail(c, GH_ERR_ARG, "enable must be 0, 1 or 2");
   clear_timing(c);
   c->timing = enable != 0;
+  c->timing_only = enable == 2 ? 0 : -1;
   return GH_OK;
 }
 

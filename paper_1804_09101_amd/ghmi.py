@@ -263,7 +263,10 @@ class GHSolver:
         self._check(self.lib.gh_set_graph(self.h, 1 if enable else 0))
 
     def set_timing(self, enable=True):
-        self._check(self.lib.gh_set_timing(self.h, 1 if enable else 0))
+        """True/1: events around every launch; 2: only around the angular
+        derivative GEMM; False/0: off."""
+        level = 2 if enable == 2 else (1 if enable else 0)
+        self._check(self.lib.gh_set_timing(self.h, level))
 
     def kernel_stats(self, kind):
         """(launches, total_ms) of one kernel kind since timing was enabled or last queried."""

@@ -217,3 +217,20 @@ def test_set_background_again_after_steps_mixed_L():
     torch.cuda.synchronize()
     for _ in range(2):
         c.s.set_background(dev(c.H), dev(c.dH), dev(c.ubg))
+
+
+def test_timing_levels():
+    """Level 1 times every kernel kind, level 2 only the angular derivative
+    GEMM; other levels are rejected."""
+    c = Case(configs.single_shell())
+    u = dev(c.u0)
+    c.s.set_timing(True)
+    c.s.step(u, 2)
+    assert c.s.kernel_stats("deriv_gemm")[0] == 6 and c.s.kernel_stats("pointwise")[0] == 6
+    c.s.set_timing(2)
+    c.s.step(u, 2)
+    assert c.s.kernel_stats("deriv_gemm")[0] == 6 and c.s.kernel_stats("pointwise")[0] == 0
+    c.s.set_timing(False)
+    with pytest.raises(ghmi.GHError) as ei:
+        c.s._check(c.s.lib.gh_set_timing(c.s.h, 3))
+    assert ei.value.code == -1
