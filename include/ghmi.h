@@ -259,6 +259,14 @@ int gh_query(const gh_ctx* ctx, int what, long long* value);
  * items of one launch of its coupling kernel; 13: the interface mode
  * (gh_set_interface). */
 
+/* Pin the kernel variant and tile order of a GEMM plan instead of the
+ * autotuner's choice (for reproducible timing, and to check every variant):
+ * plan 0: the angular derivative GEMM, 1: the filter GEMM (filter_kind 1);
+ * shape: variant index 0 .. 12 (tile, wave layout, LDS layout, k-slice depth;
+ * gh_query 6/7 report the current one); order 0: column blocks per XCD, 1:
+ * row blocks.  GH_ERR_ARG otherwise.  Drops a captured step graph. */
+int gh_set_gemm_variant(gh_ctx* ctx, int plan, int shape, int order);
+
 /* Where the characteristic projection at shell interfaces comes from.
  * mode 0 (default): the unit normal's metric normalisation and the upwind
  * choice (signs of the characteristic speeds) are taken from u_bg at

@@ -1476,6 +1476,18 @@ int gh_constraints_vjp(gh_ctx* c, const double* u, const double* lam_norm, doubl
   return GH_OK;
 }
 
+int gh_set_gemm_variant(gh_ctx* c, int plan, int shape, int order) {
+  if (!c) return GH_ERR_ARG;
+  if (!c->have_domain) return fail(c, GH_ERR_ORDER, "gh_set_domain has not been called");
+  if (plan < 0 || plan > 1 || shape < 0 || shape >= ghk::NUM_TILE_SHAPES || order < 0 || order > 1)
+    return fail(c, GH_ERR_ARG, "plan 0 or 1, shape 0 .. NUM_TILE_SHAPES-1, order 0 or 1");
+  if (plan == 1 && c->filter_kind != 1) return fail(c, GH_ERR_ARG, "the domain has no filter GEMM (filter_kind 1)");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  drop_graph(c);
+  return plan_upload(c, plan ? c->filter : c->deriv, shape, order);
+}
+
 int gh_set_interface(gh_ctx* c, int mode) {
   if (!c) return GH_ERR_ARG;
   if (!c->have_domain) return fail(c, GH_ERR_ORDER, "gh_set_domain has not been called");

@@ -16,8 +16,9 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // Grouped FP64 GEMM on the matrix cores: C = A * B for every group of a tile
 // list.  One workgroup of WGM x WGN waves computes a BM x BN tile; each wave
 // owns a (BM/WGM) x (BN/WGN) sub-tile made of 16x16 blocks of
-// v_mfma_f64_16x16x4_f64.  A and B k-slices (BK = 16) are staged through LDS,
-// double buffered.  B is stored k-major ([BK][BN]); A either k-major
+// v_mfma_f64_16x16x4_f64.  A and B k-slices (BK = 16 or 32: fewer barriers
+// per K against twice the LDS) are staged through LDS, double buffered.  B is
+// stored k-major ([BK][BN]); A either k-major
 // ([BK][BM], AROW = false) or row-major with a one-double pad per row
 // ([BM][BK+1], AROW = true: the global-to-LDS store is then a plain row copy
 // and the padded rows keep the fragment reads free of bank conflicts).
@@ -33,13 +34,12 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // PhysToSpec and 7: SpecToPhys of the tensor-coupled filter) so that profiles
 // attribute time to each.  ROLE 2 adds into C
 // (C += A B); the others overwrite C.
-template <int BM, int BN, int WGM, int WGN, bool AROW, int ROLE>
+template <int BM, int BN, int WGM, int WGN, bool AROW, int BK, int ROLE>
 __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(const GemmTile* __restrict__ tiles,
                                                          const GemmGroup* __restrict__ groups,
                                                          const double* __restrict__ Abase,
                                                          double* __restrict__ Cbase) {
   constexpr int NT = 64 * WGM * WGN;
-  constexpr int BK = 16;
   constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int TM = WM / 16, TN = WN / 16;
   static_assert(TM * 16 == WM && TN * 16 == WN, "wave sub-tile must be whole 16x16 blocks");
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(const GemmTile* __restr
     for (int p = 0; p < APASS; ++p) {
       int idx = p * NT + tid;
       if (AGRP % NT != 0 && idx >= AGRP) break;
-      int row = t.m0 + idx / 4, kq = k0 + (idx % 4) * 4;
+      int row = t.m0 + idx / (BK / 4), kq = k0 + (idx % (BK / 4)) * 4;
       const double* src = Ag + (long long)row * G.lda + kq;
       if (row < M && kq + 3 < K) {
         double2 v0 = *reinterpret_cast<const double2*>(src);
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(const GemmTile* __restr
     for (int p = 0; p < APASS; ++p) {
       int idx = p * NT + tid;
       if (AGRP % NT != 0 && idx >= AGRP) break;
-      int row = idx / 4, kq = (idx % 4) * 4;
+      int row = idx / (BK / 4), kq = (idx % (BK / 4)) * 4;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         if (AROW) As[buf][row * ALD + kq + e] = ra[p][e];
@@ -174,11 +174,14 @@ namespace ghk {
 struct TileShape {
   int bm, bn, wgm, wgn;
   bool arow;
+  int bk;
 };
 static const TileShape kTiles[NUM_TILE_SHAPES] = {
-    {64, 64, 2, 2, false},  {64, 128, 2, 2, false}, {128, 64, 2, 2, false}, {128, 128, 2, 2, false},
-    {96, 64, 2, 2, false},  {96, 64, 2, 2, true},   {128, 64, 4, 2, true},  {128, 128, 4, 2, true},
-    {64, 128, 2, 4, true},  {192, 64, 4, 2, true}};
+    {64, 64, 2, 2, false, 16},  {64, 128, 2, 2, false, 16}, {128, 64, 2, 2, false, 16},
+    {128, 128, 2, 2, false, 16}, {96, 64, 2, 2, false, 16},  {96, 64, 2, 2, true, 16},
+    {128, 64, 4, 2, true, 16},  {128, 128, 4, 2, true, 16}, {64, 128, 2, 4, true, 16},
+    {192, 64, 4, 2, true, 16},  {128, 64, 4, 2, true, 32},  {192, 64, 4, 2, true, 32},
+    {128, 128, 4, 2, true, 32}};
 
 void tile_dims(int shape, int* bm, int* bn) {
   *bm = kTiles[shape].bm;
@@ -189,22 +192,25 @@ template <int ROLE>
 static hipError_t gemm_role(int shape, const GemmTile* tiles, int n_tiles, const GemmGroup* groups,
                             const double* Abase, double* Cbase, hipStream_t st) {
   dim3 grid(n_tiles);
-#define GH_GEMM_CASE(i, BM_, BN_, WGM_, WGN_, AROW_)                                                  \
-  case i:                                                                                             \
-    hipLaunchKernelGGL((k_gemm<BM_, BN_, WGM_, WGN_, AROW_, ROLE>), grid, dim3(64 * WGM_ * WGN_), 0, st, \
-                       tiles, groups, Abase, Cbase);                                                  \
+#define GH_GEMM_CASE(i, BM_, BN_, WGM_, WGN_, AROW_, BK_)                                                  \
+  case i:                                                                                                  \
+    hipLaunchKernelGGL((k_gemm<BM_, BN_, WGM_, WGN_, AROW_, BK_, ROLE>), grid, dim3(64 * WGM_ * WGN_), 0, st, \
+                       tiles, groups, Abase, Cbase);                                                       \
     break;
   switch (shape) {
-    GH_GEMM_CASE(0, 64, 64, 2, 2, false)
-    GH_GEMM_CASE(1, 64, 128, 2, 2, false)
-    GH_GEMM_CASE(2, 128, 64, 2, 2, false)
-    GH_GEMM_CASE(3, 128, 128, 2, 2, false)
-    GH_GEMM_CASE(4, 96, 64, 2, 2, false)
-    GH_GEMM_CASE(5, 96, 64, 2, 2, true)
-    GH_GEMM_CASE(6, 128, 64, 4, 2, true)
-    GH_GEMM_CASE(7, 128, 128, 4, 2, true)
-    GH_GEMM_CASE(8, 64, 128, 2, 4, true)
-    GH_GEMM_CASE(9, 192, 64, 4, 2, true)
+    GH_GEMM_CASE(0, 64, 64, 2, 2, false, 16)
+    GH_GEMM_CASE(1, 64, 128, 2, 2, false, 16)
+    GH_GEMM_CASE(2, 128, 64, 2, 2, false, 16)
+    GH_GEMM_CASE(3, 128, 128, 2, 2, false, 16)
+    GH_GEMM_CASE(4, 96, 64, 2, 2, false, 16)
+    GH_GEMM_CASE(5, 96, 64, 2, 2, true, 16)
+    GH_GEMM_CASE(6, 128, 64, 4, 2, true, 16)
+    GH_GEMM_CASE(7, 128, 128, 4, 2, true, 16)
+    GH_GEMM_CASE(8, 64, 128, 2, 4, true, 16)
+    GH_GEMM_CASE(9, 192, 64, 4, 2, true, 16)
+    GH_GEMM_CASE(10, 128, 64, 4, 2, true, 32)
+    GH_GEMM_CASE(11, 192, 64, 4, 2, true, 32)
+    GH_GEMM_CASE(12, 128, 128, 4, 2, true, 32)
     default: return hipErrorInvalidValue;
   }
 #undef GH_GEMM_CASE

@@ -26,8 +26,10 @@ EXPORTS = [
     "gh_last_error", "gh_grid_coords", "gh_host_operator", "gh_set_timing", "gh_kernel_stats",
     "gh_query", "gh_rhs_vjp", "gh_step_vjp", "gh_constraints_vjp",
     "gh_set_graph", "gh_step_stages", "gh_step_vjp_stages", "gh_step_dp5", "gh_set_angular",
-    "gh_filter", "gh_tensor_filter_matrix", "gh_set_interface",
+    "gh_filter", "gh_tensor_filter_matrix", "gh_set_interface", "gh_set_gemm_variant",
 ]
+
+NUM_GEMM_VARIANTS = 13
 
 KERNEL_KINDS = {"deriv_gemm": 0, "filter_gemm": 1, "radial": 2, "pointwise": 3, "boundary": 4,
                 "rk_combine_vjp": 5, "pointwise_vjp": 6, "deriv_gemm_T": 7,
@@ -88,6 +90,7 @@ def load_library(path=LIB_PATH):
         "gh_step_vjp_stages": (i, [vp, vp, vp, vp, vp, vp, vp, vp]),
         "gh_filter": (i, [vp, vp, vp]),
         "gh_set_interface": (i, [vp, i]),
+        "gh_set_gemm_variant": (i, [vp, i, i, i]),
         "gh_tensor_filter_matrix": (i, [i, i, pd, i, pll, pll, ctypes.POINTER(ctypes.c_int), pd]),
     }
     for name, (res, args) in sig.items():
@@ -292,6 +295,11 @@ class GHSolver:
         self._check(self.lib.gh_step_vjp(self.h, self._dev(u_n, 50, "u_n"), self._dev(lam_np1, 50, "lam_np1"),
                                          self._dev(out, 50, "lam_n"), g))
         return out
+
+    def set_gemm_variant(self, plan, shape, order):
+        """Pin the kernel variant and tile order of the derivative (plan 0) or
+        filter (plan 1) GEMM instead of the autotuner's choice."""
+        self._check(self.lib.gh_set_gemm_variant(self.h, int(plan), int(shape), int(order)))
 
     def set_interface(self, mode):
         """0: interface projection from the background (frozen, default); 1: from

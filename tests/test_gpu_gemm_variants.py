@@ -1,0 +1,45 @@
+"""Every kernel variant of the grouped GEMM, in both tile orders, pinned in
+turn (gh_set_gemm_variant) for the derivative and the filter GEMM, on a
+mixed-L domain whose sizes are ragged for every tile: K = S = 72 (L = 5, not a
+multiple of 16 or 32), 128 and 288; row counts 50 n_r not multiples of the tile
+heights.  The RHS must match the oracle to 1e-12 of the term scale and a
+filtered step the autotuned one to 1e-13 of the state."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+from paper_1804_09101_amd import configs, ghmi  # noqa: E402
+from test_gpu_parity import Case, _wl, dev  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def test_every_variant_and_order():
+    shells = [(0, 7, 5, 1.8, 2.7), (0, 9, 5, 2.7, 4.0), (1, 5, 7, 1.7, 2.9), (2, 6, 11, 1.6, 3.1)]
+    holes = [(1.0, 0.0, (0, 0, 1)), (1.0, 0.5, (0.3, -0.2, 0.9)), (0.9, 0.2, (0.1, 0.1, 1.0))]
+    wl = _wl("variants", shells, holes, filt=configs.FILTER_DEFAULT)
+    c = Case(wl, pert_amp=1e-3, seed=9)
+    u = dev(c.u0)
+    ref = c.oracle_rhs(c.u0)
+    scale = max(np.max(np.abs(ref)), c.term_scale(c.u0))
+    tuned = u.clone()
+    c.s.step(tuned, 1)
+    worst_rhs = worst_step = 0.0
+    for shape in range(ghmi.NUM_GEMM_VARIANTS):
+        for order in (0, 1):
+            c.s.set_gemm_variant(0, shape, order)
+            c.s.set_gemm_variant(1, shape, order)
+            assert c.s.query(6) == shape and c.s.query(7) == shape and c.s.query(4) == order
+            got = c.s.rhs(u).cpu().numpy()
+            e = np.max(np.abs(got - ref)) / scale
+            v = u.clone()
+            c.s.step(v, 1)
+            es = float((v - tuned).abs().max() / tuned.abs().max())
+            print(f"  variant {shape} order {order}: rhs {e:.2e}, filtered step vs tuned {es:.2e}", flush=True)
+            worst_rhs, worst_step = max(worst_rhs, e), max(worst_step, es)
+            assert e < 1e-12 and es < 1e-13
+    for bad in ((2, 0, 0), (0, ghmi.NUM_GEMM_VARIANTS, 0), (0, 0, 2), (0, -1, 0)):
+        with pytest.raises(ghmi.GHError) as ei:
+            c.s.set_gemm_variant(*bad)
+        assert ei.value.code == -1
