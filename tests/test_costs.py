@@ -1,51 +1,79 @@
 """The cost model reproduces the figures the paper prints for it.
 
-Pins: the expanded SingleBH and BBH polynomials for M and F (section
-"Spectral Operations: Differentiation and Filtering", I1 x S2 paragraphs), the starting intensities 13.7
-(SingleBH, k = 0) and 7.2 (BBH, k = 0), and the DiffJac intensities
-1.81, 2.17, 2.29, 2.41 for N_e = 4, 10, 16, 40 (section "Jacobian
-multiplication"; the first is printed truncated, 20/11 = 1.818)."""
+The printed values live in tests/golden/paper_printed_values.txt, each with
+the section it comes from: the SingleBH and BBH point prescriptions and the
+expanded polynomials for M and F of the I1 x S2 differentiator (section
+"Spectral Operations: Differentiation and Filtering"), the starting
+intensities 13.7 (SingleBH, k = 0) and 7.2 (BBH, k = 0), the DiffJac
+intensities 1.81, 2.17, 2.29, 2.41 for N_e = 4, 10, 16, 40 (section "Jacobian
+multiplication"; the first is printed truncated, 20/11 = 1.818), and the
+SingleBH production shell of 10 x 19 x 38 = 7220 points."""
+
+import os
 
 import pytest
 
 from paper_1804_09101_amd import costs
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_printed_values.txt")
+
+
+def _printed():
+    out = {}
+    for line in open(GOLDEN):
+        line = line.split("#", 1)[0].strip()
+        if not line:
+            continue
+        key, rest = line.split("=", 1)
+        out[key.strip()] = [float(x) for x in rest.split(";", 1)[0].split()]
+    return out
+
+
+P = _printed()
+
+
+def _poly(key, k):
+    c = P[key]
+    return int(round(sum(a * k ** (len(c) - 1 - i) for i, a in enumerate(c))))
+
 
 def _singlebh_poly(k):
-    M = 128 * k**4 + 1728 * k**3 + 8512 * k**2 + 18216 * k + 14337
-    F = 1024 * k**5 + 14848 * k**4 + 85536 * k**3 + 244728 * k**2 + 347760 * k + 196344
-    return M, F
+    return _poly("singlebh_M", k), _poly("singlebh_F", k)
 
 
 def _bbh_poly(k):
-    M = 128 * k**4 + 1840 * k**3 + 9937 * k**2 + 23892 * k + 21576
-    F = 256 * k**5 + 4624 * k**4 + 33368 * k**3 + 120252 * k**2 + 216426 * k + 155624
-    return M, F
+    return _poly("bbh_M", k), _poly("bbh_F", k)
 
 
 @pytest.mark.parametrize("k", range(0, 11))
 def test_singlebh_polynomials(k):
     n_r, nt, nph = costs.singlebh_grid(k)
-    assert nt * nph == 8 * k * k + 48 * k + 72
+    assert (n_r, nt, nph) == (_poly("singlebh_grid_nr", k), _poly("singlebh_grid_ntheta", k),
+                              _poly("singlebh_grid_nphi", k))
+    assert nt * nph == _poly("singlebh_angular_points", k)
     assert costs.shell_dense_derivative(n_r, nt * nph, n_e=1) == _singlebh_poly(k)
 
 
 @pytest.mark.parametrize("k", range(0, 17))
 def test_bbh_polynomials(k):
     n_r, nt, nph = costs.bbh_grid(k)
-    assert nt * nph == 8 * k * k + 56 * k + 98
+    assert (n_r, nt, nph) == (_poly("bbh_grid_nr", k), _poly("bbh_grid_ntheta", k), _poly("bbh_grid_nphi", k))
+    assert nt * nph == _poly("bbh_angular_points", k)
     assert costs.shell_dense_derivative(n_r, nt * nph, n_e=1) == _bbh_poly(k)
 
 
 def test_starting_intensities():
-    for grid, printed in ((costs.singlebh_grid, 13.7), (costs.bbh_grid, 7.2)):
+    for grid, printed in ((costs.singlebh_grid, P["singlebh_intensity_k0"][0]),
+                          (costs.bbh_grid, P["bbh_intensity_k0"][0])):
         n_r, nt, nph = grid(0)
         M, F = costs.shell_dense_derivative(n_r, nt * nph)
         assert round(F / M, 1) == printed
 
 
 def test_diffjac_intensities():
-    for n_e, printed in ((4, 1.81), (10, 2.17), (16, 2.29), (40, 2.41)):
+    pairs = P["diffjac_intensity"]
+    for n_e, printed in zip(pairs[0::2], pairs[1::2]):
+        n_e = int(n_e)
         M, F = costs.diffjac(n_e)
         assert F / M == pytest.approx(5 * n_e / (2 * n_e + 3))
         assert abs(F / M - printed) < 0.01
@@ -68,3 +96,9 @@ def test_angular_gemm_bytes_of_the_8_shell_domain():
     # field matrix 8400 x 512, operator 512 x 1024 (one L), result 8400 x 1024, doubles
     shells = [(0, 21, 15, 1.0 + i, 2.0 + i) for i in range(8)]
     assert costs.angular_gemm_bytes(shells) == 8 * (8400 * 512 + 512 * 1024 + 8400 * 1024)
+
+
+def test_singlebh_production_shell():
+    n_r, nt, nph, total = (int(x) for x in P["singlebh_production_shell"])
+    assert n_r * nt * nph == total
+    assert nph == 2 * nt                       # the angular grid's N_phi = 2 N_theta
