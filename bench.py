@@ -236,6 +236,17 @@ def tensor_filter_measurement(wl, steps, applications=50):
     alg_bytes = 2 * 8 * coeff + 12 * nnz + 8 * (rows + 1)
     avg_c = ms_c / n_c / 1e3
     gbs = alg_bytes / avg_c / 1e9
+    # the same application by transforms (Fourier GEMMs and per-order Legendre steps)
+    s.set_angular(1)
+    for _ in range(3):
+        s.filter(u, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(applications):
+        s.filter(u, out)
+    torch.cuda.synchronize()
+    t_tr = time.perf_counter() - t0
+    s.set_angular(0)
     # RK3 steps with the tensor filter
     ust = dev(u0)
     s.step(ust, 5)
@@ -247,6 +258,7 @@ def tensor_filter_measurement(wl, steps, applications=50):
     return {"filter": "tensor-coupled ExpCheb (filter_kind 2)", "params": list(params),
             "couplings": nnz, "density": nnz / sum((50 * (L + 1) ** 2) ** 2 for L in {sh[2] for sh in wl.shells}),
             "work_items": s.query(12), "ms_per_application": tf / applications * 1e3,
+            "ms_per_application_by_transforms": t_tr / applications * 1e3,
             "filter_avg_us": ms_all / n_all * 1e3,
             "coupling": {"bound": "hbm", "avg_launch_us": avg_c * 1e6, "algorithmic_bytes": alg_bytes,
                          "achieved": gbs, "peak": MI355X_HBM_PEAK_GBS, "unit": "GB/s",
@@ -539,7 +551,8 @@ def main():
     if not args.no_tensor_filter:
         out["tensor_filter"] = tensor_filter_measurement(wl, min(args.steps, 50))
         tfm = out["tensor_filter"]
-        log(f"tensor filter: {tfm['ms_per_application']:.3f} ms per application, coupling "
+        log(f"tensor filter: {tfm['ms_per_application']:.3f} ms per application "
+            f"({tfm['ms_per_application_by_transforms']:.3f} by transforms), coupling "
             f"{tfm['coupling']['avg_launch_us']:.1f} us ({tfm['coupling']['achieved']:.0f} GB/s), "
             f"RK3 with it {tfm['rk3_ms_per_step']:.3f} ms/step")
     if not args.no_dp5:

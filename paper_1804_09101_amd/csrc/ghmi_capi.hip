@@ -97,6 +97,9 @@ struct gh_ctx {
   // SpecToPhys GEMM; the adjoint uses the transposed matrices
   std::map<int, double*> d_anaT, d_synT, d_syn, d_ana;   // per L: B operands [S][nsp], [ns][S], [S][nsp], [ns][S]
   double *d_tfx = nullptr, *d_tfy = nullptr;
+  double* d_legtab = nullptr;                // per L: Legendre analysis and synthesis tables (transform form)
+  PtBlock *d_lg_ablk = nullptr, *d_lg_sblk = nullptr;
+  int n_lg_ablk = 0, n_lg_sblk = 0;
   GemmPlan tf_p2s, tf_s2p, tf_p2sT, tf_s2pT;
   TfItem* d_tf_items = nullptr;
   TfSeg* d_tf_segs = nullptr;
@@ -237,6 +240,9 @@ void free_domain(gh_ctx* c) {
   c->tf_p2sT = GemmPlan();
   c->tf_s2pT = GemmPlan();
   c->d_tfx = c->d_tfy = nullptr;
+  c->d_legtab = nullptr;
+  c->d_lg_ablk = c->d_lg_sblk = nullptr;
+  c->n_lg_ablk = c->n_lg_sblk = 0;
   c->d_tf_items = nullptr;
   c->d_tf_segs = nullptr;
   c->d_tf_cols = nullptr;
@@ -405,7 +411,14 @@ int queue_tensor_filter(gh_ctx* c, const double* src, double* dst, bool transpos
   double* Y = c->d_tfy;
   const GemmPlan& p2s = transpose ? c->tf_p2sT : c->tf_p2s;
   const GemmPlan& s2p = transpose ? c->tf_s2pT : c->tf_s2p;
-  HIPCHK(c, ghk::gemm(p2s.shape, p2s.d_tiles, p2s.n_tiles, p2s.d_groups, src, X, c->stream, 6));
+  const bool tr = c->filt_tr && !transpose;   // by transforms: Fourier GEMM + per-order Legendre steps
+  if (tr) {
+    HIPCHK(c, ghk::gemm(c->tr_ana.shape, c->tr_ana.d_tiles, c->tr_ana.n_tiles, c->tr_ana.d_groups, src, c->d_W,
+                        c->stream, 4));
+    HIPCHK(c, ghk::leg_analysis(c->d_sh, c->d_lg_ablk, c->n_lg_ablk, c->d_legtab, c->d_W, X, c->stream));
+  } else {
+    HIPCHK(c, ghk::gemm(p2s.shape, p2s.d_tiles, p2s.n_tiles, p2s.d_groups, src, X, c->stream, 6));
+  }
   {
     Timed t(c, 9);
     HIPCHK(c, ghk::tensor_couple(c->d_tf_items, c->n_tf_items, c->d_tf_segs, c->d_tf_cols,
@@ -413,7 +426,13 @@ int queue_tensor_filter(gh_ctx* c, const double* src, double* dst, bool transpos
                                  transpose ? c->d_tfT_perm : c->d_tf_perm, transpose ? c->d_tfT_lidx : c->d_tf_lidx,
                                  transpose ? c->d_tfT_val : c->d_tf_val, X, Y, c->stream));
   }
-  HIPCHK(c, ghk::gemm(s2p.shape, s2p.d_tiles, s2p.n_tiles, s2p.d_groups, Y, dst, c->stream, 7));
+  if (tr) {
+    HIPCHK(c, ghk::leg_synthesis(c->d_sh, c->d_lg_sblk, c->n_lg_sblk, c->d_legtab, Y, c->d_W, c->stream));
+    HIPCHK(c, ghk::gemm(c->tr_fsyn.shape, c->tr_fsyn.d_tiles, c->tr_fsyn.n_tiles, c->tr_fsyn.d_groups, c->d_W, dst,
+                        c->stream, 5));
+  } else {
+    HIPCHK(c, ghk::gemm(s2p.shape, s2p.d_tiles, s2p.n_tiles, s2p.d_groups, Y, dst, c->stream, 7));
+  }
   return GH_OK;
 }
 
@@ -636,6 +655,32 @@ int build_tensor_filter(gh_ctx* c) {
   for (int k = 0; k < c->n_shells; ++k) xoff[k + 1] = xoff[k] + 50LL * c->shells[k].n_r * nsp_of(c->shells[k].L);
   if ((rc = dalloc(c, &c->d_tfx, size_t(xoff[c->n_shells])))) return rc;
   if ((rc = dalloc(c, &c->d_tfy, size_t(xoff[c->n_shells])))) return rc;
+  {
+    // transform form: Legendre tables per L, blocks over (row, s) and (row, i, m'), shell offsets
+    std::map<int, long long> lg_off;
+    std::vector<double> legtab;
+    std::vector<PtBlock> ab, sb;
+    for (int k = 0; k < c->n_shells; ++k) {
+      const int L = c->shells[k].L, n = L + 1, rows = 50 * c->shells[k].n_r;
+      if (!lg_off.count(L)) {
+        lg_off[L] = (long long)legtab.size();
+        const std::vector<double> T = ghtf::legendre_tables(L);
+        legtab.insert(legtab.end(), T.begin(), T.end());
+      }
+      c->h_sh[k].tf_off = xoff[k];
+      c->h_sh[k].lg_off = lg_off[L];
+      c->h_sh[k].nsp = nsp_of(L);
+      // one thread per (group of 10 rows, coefficient) and (group of 10 rows, m', i)
+      for (int q0 = 0; q0 < rows / 10 * n * n; q0 += 256) ab.push_back(PtBlock{k, q0});
+      for (int q0 = 0; q0 < rows / 10 * 2 * n * n; q0 += 256) sb.push_back(PtBlock{k, q0});
+    }
+    if ((rc = upload(c, &c->d_legtab, legtab))) return rc;
+    if ((rc = upload(c, &c->d_lg_ablk, ab))) return rc;
+    if ((rc = upload(c, &c->d_lg_sblk, sb))) return rc;
+    c->n_lg_ablk = int(ab.size());
+    c->n_lg_sblk = int(sb.size());
+    HIPCHK(c, hipMemcpy(c->d_sh, c->h_sh.data(), c->h_sh.size() * sizeof(ShellDev), hipMemcpyHostToDevice));
+  }
   for (int k0 = 0; k0 < c->n_shells; ++k0) {
     const int L = c->shells[k0].L;
     if (done.count(L)) continue;
@@ -1233,7 +1278,7 @@ int ensure_transform(gh_ctx* c) {
   HIPCHK(c, ghk::fill_pattern(c->d_X, (long long)(2 * F50), c->stream));
   if ((rc = autotune(c, c->tr_ana, c->d_ua, c->d_ub, 4))) return rc;
   if ((rc = autotune(c, c->tr_syn, c->d_X, c->d_dA, 5))) return rc;
-  if (c->filter_kind == 1)
+  if (c->filter_kind != 0)
     if ((rc = autotune(c, c->tr_fsyn, c->d_X, c->d_ub, 5))) return rc;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->have_tr = true;
@@ -1271,7 +1316,7 @@ int gh_set_angular(gh_ctx* c, int method) {
   HIPCHK(c, hipSetDevice(c->device));
   int rc;
   if (method >= 1 && (rc = ensure_transform(c))) return rc;
-  bool dtr = method == 1, ftr = method == 1 && c->filter_kind == 1;
+  bool dtr = method == 1, ftr = method == 1 && c->filter_kind != 0;
   if (method == 2) {
     // time both forms of each operation on this domain (non-zero data in the work arrays)
     const bool timing = c->timing;
@@ -1283,7 +1328,7 @@ int gh_set_angular(gh_ctx* c, int method) {
     c->deriv_tr = true;
     if ((rc = time_op(c, [&]() { return queue_derivs(c, c->d_ua); }, &t_tr))) return rc;
     dtr = t_tr < t_dense;
-    if (c->filter_kind == 1) {
+    if (c->filter_kind != 0) {
       c->filt_tr = false;
       if ((rc = time_op(c, [&]() { return queue_filter(c, c->d_ua, c->d_ub); }, &t_dense))) return rc;
       c->filt_tr = true;

@@ -19,6 +19,10 @@ struct ShellDev {
   int inner;          // 1: inner face is an excision boundary
   double dscale;      // d/dr = dscale * d/dxi, dscale = 2/(r_out - r_in)
   long long kt_off;   // offset of this L's per-order theta kernels in the transform table (-1: none)
+  long long tf_off;   // tensor filter: first coefficient of the shell in the coefficient arrays
+  long long lg_off;   // tensor filter: offset of this L's Legendre tables (analysis [ns][n], synthesis [n][ns])
+  int nsp;            // tensor filter: coefficients per (field, radius) row, (L+1)^2 rounded up to even
+  int pad_;
 };
 
 // A block of up to 256 consecutive points inside one shell.
@@ -84,6 +88,18 @@ hipError_t ang_theta(int nmax, const ShellDev* sh, const PtBlock* tblk, int n_tb
                      const double* AB, double* X, int mode, hipStream_t st);
 
 hipError_t fill_pattern(double* x, long long n, hipStream_t st);
+
+// Tensor-coupled filter by transforms.  leg_analysis: Fourier coefficients
+// F (per shell at 50 pt_off, [field, radius][theta node i][m'], m' < n: cos m,
+// m' >= n: sin (m' - n)) -> real Y_lm coefficients X[tf_off + row nsp + s],
+// s = l l + l + m, with the analysis table (weights, sqrt2 folded in);
+// leg_synthesis: coefficients Y -> the same Fourier layout G for the synthesis
+// GEMM.  Blocks: (shell, first (group of 10 rows, s) or (group, m', i) index),
+// 256 threads.
+hipError_t leg_analysis(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* legtab, const double* F,
+                        double* X, hipStream_t st);
+hipError_t leg_synthesis(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* legtab, const double* Y,
+                         double* G, hipStream_t st);
 
 // n_items[3]: the items come grouped by their column class (8, 4, 2 columns).
 hipError_t tensor_couple(const TfItem* items, const int n_items[3], const TfSeg* segs, const TfCol* cols,

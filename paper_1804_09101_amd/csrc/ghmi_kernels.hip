@@ -1220,6 +1220,82 @@ __global__ __launch_bounds__(TF_THREADS) void k_tensor_couple(const TfItem* __re
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Tensor-coupled filter by transforms: the per-order Legendre steps between
+// the Fourier GEMMs and the coupling.  Analysis: one thread per (row, s),
+// s fastest:
+//   X[s] = sum_i TA[i][s] F[i][m'(s)],  TA[i][s] = f_m (2 pi / N_phi) w_i P_l^|m|(x_i)
+// (f_0 = 1, f_m = sqrt2; m'(s) = m for m >= 0, n + |m| for m < 0): the table
+// loads of a wave are contiguous, its F loads fall in one 2n-row of the block.
+// Each thread takes LG_ROWS consecutive rows, so every table value it loads
+// serves LG_ROWS rows.  Synthesis: one thread per (row, m', i), i fastest:
+//   G[i][m'] = sum_{l >= m} TS[s(l, +-m)][i] Y[s],  TS[s][i] = f_m P_l^|m|(x_i)
+// (zero for the sin column of m = 0): the table loads of a wave are
+// contiguous and its coefficient loads take a few values (4 columns m').
+// ---------------------------------------------------------------------------
+constexpr int LG_ROWS = 10;   // rows per thread (divides the 50 n_r rows of every shell)
+
+__global__ __launch_bounds__(256) void k_leg_analysis(const ShellDev* __restrict__ sh,
+                                                      const PtBlock* __restrict__ blk,
+                                                      const double* __restrict__ legtab,
+                                                      const double* __restrict__ F, double* __restrict__ X) {
+  const PtBlock b = blk[blockIdx.x];
+  const ShellDev d = sh[b.shell];
+  const int n = d.L + 1, ns = n * n, S = 2 * n * n;
+  const int q = b.q0 + threadIdx.x;
+  if (q >= 5 * d.n_r * ns) return;
+  const int g = q / ns, sidx = q - g * ns;
+  int l = int(sqrt(double(sidx)));      // degree of s = l l + l + m
+  if (l * l > sidx) --l;
+  if ((l + 1) * (l + 1) <= sidx) ++l;
+  const int m = sidx - l * l - l;
+  const int col = m >= 0 ? m : n - m;
+  const double* __restrict__ TA = legtab + d.lg_off + sidx;
+  const double* __restrict__ f = F + 50LL * d.pt_off + (long long)g * LG_ROWS * S + col;
+  double acc[LG_ROWS];
+#pragma unroll
+  for (int r = 0; r < LG_ROWS; ++r) acc[r] = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double t = TA[(long long)i * ns];
+#pragma unroll
+    for (int r = 0; r < LG_ROWS; ++r) acc[r] += t * f[(long long)r * S + (long long)i * 2 * n];
+  }
+  double* __restrict__ x = X + d.tf_off + (long long)g * LG_ROWS * d.nsp + sidx;
+#pragma unroll
+  for (int r = 0; r < LG_ROWS; ++r) x[(long long)r * d.nsp] = acc[r];
+}
+
+__global__ __launch_bounds__(256) void k_leg_synthesis(const ShellDev* __restrict__ sh,
+                                                       const PtBlock* __restrict__ blk,
+                                                       const double* __restrict__ legtab,
+                                                       const double* __restrict__ Y, double* __restrict__ G) {
+  const PtBlock b = blk[blockIdx.x];
+  const ShellDev d = sh[b.shell];
+  const int n = d.L + 1, ns = n * n, S = 2 * n * n;
+  const int q = b.q0 + threadIdx.x;
+  if (q >= 5 * d.n_r * S) return;
+  const int g = q / S, rem = q - g * S, col = rem / n, i = rem - col * n;
+  const bool sinpart = col >= n;
+  const int m = sinpart ? col - n : col;
+  double acc[LG_ROWS];
+#pragma unroll
+  for (int r = 0; r < LG_ROWS; ++r) acc[r] = 0.0;
+  if (!(sinpart && m == 0)) {
+    const double* __restrict__ TS = legtab + d.lg_off + (long long)ns * n + i;
+    const double* __restrict__ y = Y + d.tf_off + (long long)g * LG_ROWS * d.nsp;
+    for (int l = m; l < n; ++l) {
+      const int sidx = l * l + l + (sinpart ? -m : m);
+      const double t = TS[(long long)sidx * n];
+#pragma unroll
+      for (int r = 0; r < LG_ROWS; ++r) acc[r] += t * y[(long long)r * d.nsp + sidx];
+    }
+  }
+  double* __restrict__ out = G + 50LL * d.pt_off + (long long)g * LG_ROWS * S + (long long)i * 2 * n + col;
+#pragma unroll
+  for (int r = 0; r < LG_ROWS; ++r) out[(long long)r * S] = acc[r];
+}
+
 }  // namespace
 
 namespace ghk {
@@ -1239,6 +1315,20 @@ hipError_t fill_pattern(double* x, long long n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   long long nb = (n + 255) / 256;
   hipLaunchKernelGGL(k_fill_pattern, dim3((unsigned)(nb < 8192 ? nb : 8192)), dim3(256), 0, st, x, n);
+  return hipGetLastError();
+}
+
+hipError_t leg_analysis(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* legtab, const double* F,
+                        double* X, hipStream_t st) {
+  if (n_blk <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_leg_analysis, dim3(n_blk), dim3(256), 0, st, sh, blk, legtab, F, X);
+  return hipGetLastError();
+}
+
+hipError_t leg_synthesis(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* legtab, const double* Y,
+                         double* G, hipStream_t st) {
+  if (n_blk <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_leg_synthesis, dim3(n_blk), dim3(256), 0, st, sh, blk, legtab, Y, G);
   return hipGetLastError();
 }
 

@@ -361,4 +361,22 @@ std::vector<double> sphere_analysis(int L) {
 
 std::vector<double> sphere_synthesis(int L) { return ylm_grid(L, nullptr); }
 
+std::vector<double> legendre_tables(int L) {
+  std::vector<double> x, w, P, dP;
+  ghsetup::gauss_legendre(L, x, w);
+  const int n = L + 1, ns = n * n, nph = 2 * n;
+  std::vector<double> T(size_t(2) * ns * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    ghsetup::legendre_normalised(L, x[i], P, dP);
+    for (int l = 0; l <= L; ++l)
+      for (int m = -l; m <= l; ++m) {
+        const int s = l * l + l + m, am = m < 0 ? -m : m;
+        const double v = (am ? std::sqrt(2.0) : 1.0) * P[size_t(l) * n + am];
+        T[size_t(i) * ns + s] = v * w[i] * 2.0 * kPi / nph;
+        T[size_t(ns) * n + size_t(s) * n + i] = v;
+      }
+  }
+  return T;
+}
+
 }  // namespace ghtf

@@ -38,4 +38,11 @@ Csr transpose(const Csr& m);
 std::vector<double> sphere_analysis(int L);
 std::vector<double> sphere_synthesis(int L);
 
+// The same analysis and synthesis factorised by azimuthal order, for Fourier
+// coefficients F[i][m'] (m' < n: cos m phi, m' >= n: sin (m' - n) phi; n = L+1):
+//   analysis  TA[i][s] = f_m (2 pi / N_phi) w_i P_l^|m|(x_i)   (n x (L+1)^2),
+//   synthesis TS[s][i] = f_m P_l^|m|(x_i)                       ((L+1)^2 x n),
+// f_0 = 1, f_m = sqrt2, s = l*l + l + m.  Returned as TA followed by TS.
+std::vector<double> legendre_tables(int L);
+
 }  // namespace ghtf

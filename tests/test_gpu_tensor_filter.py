@@ -185,3 +185,42 @@ def test_tensor_filter_queries_and_errors():
         with pytest.raises(ghmi.GHError) as ei:
             ghmi.GHSolver(MIXED, 2, params, filter_kind=kind)
         assert ei.value.code == -1
+
+
+def test_transform_form_matches_oracle_and_dense_form():
+    """gh_set_angular 1: PhysToSpec and SpecToPhys by Fourier GEMMs and
+    per-order Legendre steps; the same discrete filter as the dense form (to
+    rounding), in single applications, filtered steps and (the reverse pass
+    keeping the dense transposes) the step transpose."""
+    wl, d, s, u0, ubg, H, dH = _setup(MIXED, HOLES2, 2, STRONG)
+    rng = np.random.default_rng(8)
+    u = u0 + 1e-3 * rng.standard_normal(u0.shape)
+    dense = s.filter(dev(u)).cpu().numpy()
+    s.set_angular(1)
+    assert s.query(10) == 1
+    got = s.filter(dev(u)).cpu().numpy()
+    ref = d.apply_filter(u)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    diff = np.max(np.abs(got - dense)) / np.max(np.abs(ref))
+    print(f"  transform-form tensor filter: rel err {err:.3e}, vs dense {diff:.3e}", flush=True)
+    assert err < 1e-12 and diff < 1e-12
+    a = dev(u0)
+    s.step(a, 3)
+    ref = u0.copy()
+    for _ in range(3):
+        ref = d.rk3_step(ref, H, dH, ubg, wl.gamma, wl.dt)
+    e3 = np.max(np.abs(a.cpu().numpy() - ref)) / np.max(np.abs(ref - u0))
+    print(f"  3 steps, transform form: err/change {e3:.3e}", flush=True)
+    assert e3 < 1e-10
+    lam = rng.standard_normal(u0.shape)
+    v = rng.standard_normal(u0.shape)
+    jv = d.rk3_step(u0 + 1j * H_CS * v, H, dH, ubg, wl.gamma, wl.dt).imag / H_CS
+    ln = s.step_vjp(dev(u0), dev(lam)).cpu().numpy()
+    ed = abs(np.sum(lam * jv) - np.sum(ln * v)) / np.sum(np.abs(lam * jv))
+    print(f"  step vjp (transform forward, dense reverse): rel {ed:.2e}", flush=True)
+    assert ed < 1e-12
+    s.set_angular(2)
+    assert s.query(10) in (0, 1)
+    got2 = s.filter(dev(u)).cpu().numpy()
+    ref2 = d.apply_filter(u)
+    assert np.max(np.abs(got2 - ref2)) / np.max(np.abs(ref2)) < 1e-12
