@@ -431,7 +431,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the path shards by instance or by "
-                                   "shell across GPUs (see DESIGN.md) but no multi-GPU run is provided",
+                                   "shell across GPUs, but no multi-GPU run is provided",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
