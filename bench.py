@@ -430,8 +430,8 @@ def main():
                     help="only run a plain 256 MiB device copy 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the path shards by instance or by "
-                                   "shell across GPUs, but no multi-GPU run is provided",
+        print(json.dumps({"error": "one GPU only: the path would shard by instance or by shell across "
+                                   "GPUs, but no multi-GPU run is provided",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
