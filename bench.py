@@ -7,17 +7,19 @@ is the 8-shell pulse problem: 8 shells r in [1.8, 100], N_r = 21, L = 15
 (16 x 32), Schwarzschild M = 1 with a Gaussian pulse in Pi_ab, FP64.
 
 Metric: grid-point RHS evaluations per second = points * 3 * steps / time.
-The timed region runs with per-kernel HIP-event timing on, which gives the
-angular GEMM's average launch duration for the roofline figure.  Further
-measurements on the same GPU: the same steps replayed from a captured HIP
-graph; the adjoint/forward cost ratio of a 200-step evolution with gradients
-of the final constraint norm (checkpoint every 20 steps); 64 heterogeneous
-Kerr holes in one context against one context per hole; the 20-shell L = 31
-domain (forward rate, and the adjoint/forward ratio on a 4-instance batch);
-adaptive Dormand-Prince 5(4) stepping of the 8-shell workload.
+The timed region records HIP events around the angular derivative GEMM (the
+roofline kernel) only; the per-kernel split comes from a separate run with
+events around every launch.  Further measurements on the same GPU: the same
+steps replayed from a captured HIP graph; the angular operators by transforms
+(gh_set_angular 2); the interface projection taken from the state; the
+tensor-coupled filter (dense and by transforms, its coupling kernel against
+the HBM roofline); adaptive Dormand-Prince 5(4) stepping; the adjoint/forward
+cost ratio of a 200-step evolution with gradients of the final constraint
+norm (checkpoint every 20 steps); 64 heterogeneous Kerr holes in one context
+against one context per hole; the 20-shell L = 31 domain (forward rate, and
+the adjoint/forward ratio on a 4-instance batch).
 
-Prints one JSON line (rank 0).  With --gpus > 1 it exits: this build runs on
-one GPU.
+Prints one JSON line.  With --gpus > 1 it exits: the path runs on one GPU.
 """
 
 import argparse
