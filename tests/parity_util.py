@@ -55,7 +55,8 @@ def rounding_scale_by_shifts(d, j, ublk):
     Ph = _abs_operator_by_shifts(sph.d_dphi, sph.nth, sph.nph)
     Dr = np.abs(_traced(spectral.d_dxi, g.n_r)) * (2.0 / (g.r_out - g.r_in))
     U = np.abs(ublk).reshape(50, g.n_r, sph.S)
+    U2 = U.reshape(-1, sph.S)                             # one product over all (field, radius) rows
     k_r = np.einsum("ij,fjs->fis", Dr, U)
-    k_t = (U @ Th) / g.R.reshape(1, g.n_r, sph.S)
-    k_p = (U @ Ph) / (g.R * np.sin(g.TH)).reshape(1, g.n_r, sph.S)
+    k_t = (U2 @ Th).reshape(U.shape) / g.R.reshape(1, g.n_r, sph.S)
+    k_p = (U2 @ Ph).reshape(U.shape) / (g.R * np.sin(g.TH)).reshape(1, g.n_r, sph.S)
     return float(np.max(k_r + k_t + k_p))

@@ -39,19 +39,53 @@ def _rhs_error(c, label, ref, scale):
     return diff / scale
 
 
-def test_largest_degree():
+@pytest.fixture(scope="module")
+def deg63():
+    """One shell of the largest degree: the library context (host operators of
+    8192 x 16384 built and tuned) and the oracle domain; the oracle's RHS and
+    rounding scale are added by the first test that needs them."""
     wl = _wl("L63", [(0, 3, 63, 1.8, 2.2)], [(1.0, 0.3, (0.2, 0.3, 0.4))], dt=[1e-4], filt=configs.FILTER_DEFAULT)
-    c = Case(wl, pert_amp=1e-3, seed=21)
-    assert c.s.P == 3 * 8192
-    ref = c.oracle_rhs(c.u0)
-    kappa = rounding_scale_by_shifts(c.d, 0, c.d.split(c.u0, 50)[0])
-    print(f"  term scale {max(np.max(np.abs(ref)), c.term_scale(c.u0)):.3e}", flush=True)
+    return {"c": Case(wl, pert_amp=1e-3, seed=21)}
+
+
+def _oracle63(st, what):
+    """The oracle's RHS, rounding scale or filtered state of the L = 63 case,
+    each computed once (about 10 to 20 s of host time each)."""
+    c = st["c"]
+    if what not in st:
+        if what == "ref":
+            st[what] = c.oracle_rhs(c.u0)
+        elif what == "kappa":
+            st[what] = rounding_scale_by_shifts(c.d, 0, c.d.split(c.u0, 50)[0])
+        else:
+            st[what] = c.d.apply_filter(c.u0)
+    return st[what]
+
+
+def test_largest_degree_context(deg63):
+    c = deg63["c"]
+    assert c.s.P == 3 * 8192 and c.s.query(8) == 0
+
+
+@pytest.mark.parametrize("what", ["ref", "kappa", "fref"])
+def test_largest_degree_oracle(deg63, what):
+    v = np.asarray(_oracle63(deg63, what))
+    assert np.all(np.isfinite(v)) and np.max(np.abs(v)) > 0
+
+
+def test_largest_degree_dense(deg63):
+    c = deg63["c"]
+    ref, kappa, fref = (_oracle63(deg63, w) for w in ("ref", "kappa", "fref"))
     assert _rhs_error(c, "L = 63 dense (scale kappa)", ref, kappa) < 1e-14
-    fref = c.d.apply_filter(c.u0)
     got = c.s.filter(dev(c.u0)).cpu().numpy()
     ef = np.max(np.abs(got - fref)) / np.max(np.abs(fref))
     print(f"  L = 63 exponential filter: rel err {ef:.3e}", flush=True)
     assert ef < 1e-12
+
+
+def test_largest_degree_by_transforms(deg63):
+    c = deg63["c"]
+    ref, kappa, fref = (_oracle63(deg63, w) for w in ("ref", "kappa", "fref"))
     c.s.set_angular(1)
     assert c.s.query(9) == 1 and c.s.query(10) == 1
     assert _rhs_error(c, "L = 63 by transforms (scale kappa)", ref, kappa) < 1e-14
@@ -59,6 +93,7 @@ def test_largest_degree():
     ef = np.max(np.abs(got - fref)) / np.max(np.abs(fref))
     print(f"  L = 63 filter by transforms: rel err {ef:.3e}", flush=True)
     assert ef < 1e-12
+    c.s.set_angular(0)
 
 
 def test_most_radial_points():
