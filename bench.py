@@ -11,8 +11,8 @@ The timed region records HIP events around the angular derivative GEMM (the
 roofline kernel) only; the per-kernel split comes from a separate run with
 events around every launch.  Further measurements on the same GPU: the same
 steps replayed from a captured HIP graph; the angular operators by transforms
-(gh_set_angular 2); the interface projection taken from the state; the
-tensor-coupled filter (dense and by transforms, its coupling kernel against
+(gh_set_angular 2); the constraints and their norm (gh_constraints); the
+interface projection taken from the state; the tensor-coupled filter (dense and by transforms, its coupling kernel against
 the HBM roofline); adaptive Dormand-Prince 5(4) stepping; the adjoint/forward
 cost ratio of a 200-step evolution with gradients of the final constraint
 norm (checkpoint every 20 steps); 64 heterogeneous Kerr holes in one context
@@ -294,6 +294,25 @@ def dp5_measurement(solver, u0_dev, wl, attempts=40, atol=1e-8, rtol=1e-8):
             "physical_time_per_s": adv / w, "rk3_dt": float(wl.dt[0])}
 
 
+def constraints_measurement(solver, u0_dev, n=50):
+    """gh_constraints on the state (derivatives of the 50 fields, the 64
+    constraints per point and the volume norm per instance), wall clock over
+    n evaluations, with and without the per-point array."""
+    import torch
+    res = {}
+    for want_C in (False, True):
+        solver.constraints(u0_dev, want_C=want_C)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            solver.constraints(u0_dev, want_C=want_C)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / n
+        res["with_C" if want_C else "norm_only"] = {"ms_per_evaluation": t * 1e3, "value": solver.P / t,
+                                                    "unit": "grid points/s"}
+    return res
+
+
 def transform_measurement(solver, u0_dev, steps):
     """The same RK3 steps with the angular derivatives and filter each applied
     in the faster of the dense and the transform form on this domain
@@ -548,6 +567,9 @@ def main():
         out["transform"] = transform_measurement(solver, dev(u0), args.steps)
         log(f"transform: {out['transform']['ms_per_step']:.3f} ms/step, graph "
             f"{P * 3 * args.steps / out['transform']['graph_value'] / args.steps * 1e3:.3f} ms/step")
+    out["constraints"] = constraints_measurement(solver, dev(u0))
+    log(f"constraints: {out['constraints']['norm_only']['ms_per_evaluation']:.3f} ms per evaluation (norm only), "
+        f"{out['constraints']['with_C']['ms_per_evaluation']:.3f} ms with the per-point array")
     out["interface_state"] = interface_state_measurement(solver, dev(u0), args.steps)
     log(f"interface from state: {out['interface_state']['ms_per_step']:.3f} ms/step")
     if not args.no_tensor_filter:
