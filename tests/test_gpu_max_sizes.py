@@ -41,11 +41,12 @@ def _rhs_error(c, label, ref, scale):
     return diff / scale
 
 
-# The L = 63 context builds its 8192-point operators on one host thread
-# (about 17 s on an idle core, minutes on a loaded host), so those stages run
-# when GHMI_TEST_MAX_DEGREE=1 is set.
+# Alone these stages take about 70 s (the L = 63 context builds its 8192-point
+# operators on one host thread); created after the rest of the GPU suite in the
+# same process that context has taken minutes, so they run when
+# GHMI_TEST_MAX_DEGREE=1 is set.
 needs_max_degree = pytest.mark.skipif(os.environ.get("GHMI_TEST_MAX_DEGREE") != "1",
-                                      reason="L = 63 stages run with GHMI_TEST_MAX_DEGREE=1 (minutes of host setup)")
+                                      reason="L = 63 stages run with GHMI_TEST_MAX_DEGREE=1 (slow context setup)")
 
 
 @pytest.fixture(scope="module")
