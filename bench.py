@@ -546,7 +546,7 @@ def main():
         "roofline": {"kernel": "angular derivative GEMM (FP64 MFMA)", "bound": "mfma",
                      "achieved": achieved, "peak": MI355X_FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / MI355X_FP64_PEAK_TFLOPS,
-                     "traffic": gemm_traffic(solver.query(6), solver.query(4)),
+                     "traffic": gemm_traffic(solver.query(6), solver.query(4)) if solver.query(14) < 0 else None,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "algorithmic_bytes": costs.angular_gemm_bytes(wl.shells),
                      "flops_per_launch": flops, "avg_launch_us": avg_s * 1e6},
@@ -558,7 +558,9 @@ def main():
                                 "around the angular derivative GEMM only)"},
         "gemm_tiles": {"deriv": solver.query(0), "filter": solver.query(1), "deriv_tiles": solver.query(2),
                        "deriv_order": solver.query(4), "filter_order": solver.query(5),
-                       "deriv_variant": solver.query(6), "filter_variant": solver.query(7)},
+                       "deriv_variant": solver.query(6), "filter_variant": solver.query(7),
+                       "deriv_tail_variant": solver.query(14), "filter_tail_variant": solver.query(15),
+                       "deriv_tail_k_chunks": solver.query(16)},
         "graph_value": P * 3 * args.steps / t_graph,
     }
     log(f"timed {args.steps} steps: {t * 1e3 / args.steps:.3f} ms/step; graph {t_graph * 1e3 / args.steps:.3f} ms/step")

@@ -257,14 +257,29 @@ int gh_query(const gh_ctx* ctx, int what, long long* value);
 /* (continued) 11: number of stored couplings of the tensor-coupled filter
  * (kinds 2, 3; summed over the distinct L of the domain, else 0); 12: work
  * items of one launch of its coupling kernel; 13: the interface mode
- * (gh_set_interface). */
+ * (gh_set_interface); 14: kernel variant of the tail launch of the
+ * derivative GEMM, -1 when it is one launch; 15: the same for the filter GEMM;
+ * 16: number of K chunks of the derivative GEMM's tail (0 without).
+ *
+ * Split plans.  Workgroups of a GEMM launch finish in rounds of one tile per
+ * compute unit, so a tile count just above a multiple of the CU count costs a
+ * whole extra round.  After timing every variant and order the autotuner also
+ * times the fastest one on the leading rows that fill whole rounds (whole row
+ * tiles peeled from the end of the last group), followed by the peeled rows
+ * in smaller tiles over 2, 4 or 8 chunks of K (partial products in a work
+ * space the plan owns) and a kernel that adds the chunks into C in chunk
+ * order, and keeps the split when it is faster.  The split changes the order
+ * of the K sums of the peeled rows (results differ from one launch by
+ * rounding; every run gives the same values).  Query 2 then counts the main
+ * launch's tiles. */
 
 /* Pin the kernel variant and tile order of a GEMM plan instead of the
  * autotuner's choice (for reproducible timing, and to check every variant):
  * plan 0: the angular derivative GEMM, 1: the filter GEMM (filter_kind 1);
  * shape: variant index 0 .. 12 (tile, wave layout, LDS layout, k-slice depth;
  * gh_query 6/7 report the current one); order 0: column blocks per XCD, 1:
- * row blocks.  GH_ERR_ARG otherwise.  Drops a captured step graph. */
+ * row blocks.  A pinned plan is one launch (no tail).  GH_ERR_ARG otherwise.
+ * Drops a captured step graph. */
 int gh_set_gemm_variant(gh_ctx* ctx, int plan, int shape, int order);
 
 /* Where the characteristic projection at shell interfaces comes from.

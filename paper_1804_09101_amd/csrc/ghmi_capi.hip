@@ -25,15 +25,27 @@ struct GemmPlan {
   int shape = 0;
   int order = 0;                          // tile order, see build_tiles
   std::vector<GemmGroup> groups;          // host copy (operator pointers resolved)
-  GemmGroup* d_groups = nullptr;
+  GemmGroup* d_full = nullptr;            // device copy of groups
+  GemmGroup* d_groups = nullptr;          // groups of the main launch (d_full, or their leading rows)
   GemmTile* d_tiles = nullptr;
   int n_tiles = 0;
+  // split plan: the trailing rows that would start one more round of tiles
+  // on a few CUs go to a second launch of smaller tiles over K chunks
+  // (partial products into d_work), then a chunk-ordered sum into C
+  int tail_shape = -1, tail_order = 0, tail_chunks = 0;
+  GemmGroup* d_tgroups = nullptr;
+  GemmTile* d_ttiles = nullptr;
+  int n_ttiles = 0;
+  int tail_rows = 0, tail_cols = 0, tail_ldc = 0;
+  long long tail_c_off = 0;
+  double* d_work = nullptr;
 };
 
 }  // namespace
 
 struct gh_ctx {
   int device = 0;
+  int n_cu = 256;                // compute units of the device (tile rounds of the GEMM plans)
   hipStream_t stream = nullptr;
   std::string err = "";
 
@@ -295,11 +307,111 @@ int plan_upload(gh_ctx* c, GemmPlan& pl, int shape, int order) {
   pl.shape = shape;
   pl.order = order;
   pl.n_tiles = int(tiles.size());
+  pl.tail_shape = -1;
+  pl.n_ttiles = 0;
   int rc;
-  if (!pl.d_groups) {
-    if ((rc = upload(c, &pl.d_groups, pl.groups))) return rc;
+  if (!pl.d_full) {
+    if ((rc = upload(c, &pl.d_full, pl.groups))) return rc;
   }
+  pl.d_groups = pl.d_full;
   if ((rc = upload(c, &pl.d_tiles, tiles))) return rc;
+  return GH_OK;
+}
+
+// Rows of a plan's groups split for whole rounds of tiles: with `shape`, the
+// main launch keeps n_cu * floor(tiles / n_cu) tiles (whole row tiles, peeled
+// from the end of the last groups) and the peeled rows form the tail groups.
+// False when the tile count is already a multiple of n_cu or below it.
+bool split_rows(const std::vector<GemmGroup>& gs, int shape, int n_cu, std::vector<GemmGroup>& mainv,
+                std::vector<GemmGroup>& tailv) {
+  int bm, bn;
+  ghk::tile_dims(shape, &bm, &bn);
+  long long total = 0;
+  for (const auto& g : gs) total += (long long)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);
+  const long long target = (long long)n_cu * (total / n_cu);
+  if (target == 0 || target == total) return false;
+  mainv = gs;
+  tailv.clear();
+  long long cur = total;
+  for (int gi = int(gs.size()) - 1; gi >= 0 && cur > target; --gi) {
+    GemmGroup& g = mainv[gi];
+    const int nt = (g.N + bn - 1) / bn;
+    int mt = (g.M + bm - 1) / bm;
+    while (mt > 0 && cur > target) {
+      --mt;
+      cur -= nt;
+    }
+    const int keep = std::min(g.M, mt * bm);
+    if (keep == g.M) continue;
+    GemmGroup t = gs[gi];
+    t.a_off += (long long)keep * t.lda;
+    t.c_off += (long long)keep * t.ldc;
+    t.M = g.M - keep;
+    tailv.insert(tailv.begin(), t);
+    g.M = keep;
+  }
+  return !tailv.empty();
+}
+
+// Upload a split plan: the main rows with (shape, order); the tail rows (one
+// group) cut into `chunks` K ranges, each a group writing its partial product
+// into the plan's work space, with (tail_shape, order 1).
+int plan_upload_split(gh_ctx* c, GemmPlan& pl, const std::vector<GemmGroup>& mainv, const GemmGroup& tail,
+                      int shape, int order, int tail_shape, int chunks) {
+  const int kc = ((tail.K + chunks - 1) / chunks + 15) / 16 * 16;
+  std::vector<GemmGroup> kv;
+  for (int k0 = 0; k0 < tail.K; k0 += kc) {
+    GemmGroup g = tail;
+    g.a_off = tail.a_off + k0;
+    g.B = tail.B + (long long)k0 * tail.ldb;
+    g.K = std::min(kc, tail.K - k0);
+    g.c_off = (long long)kv.size() * tail.M * tail.N;
+    g.ldc = tail.N;
+    kv.push_back(g);
+  }
+  std::vector<GemmTile> tiles = ghk::build_tiles(mainv, shape, order);
+  std::vector<GemmTile> ttiles = ghk::build_tiles(kv, tail_shape, 1);
+  int rc;
+  if ((rc = upload(c, &pl.d_groups, mainv))) return rc;
+  if ((rc = upload(c, &pl.d_tiles, tiles))) return rc;
+  if ((rc = upload(c, &pl.d_tgroups, kv))) return rc;
+  if ((rc = upload(c, &pl.d_ttiles, ttiles))) return rc;
+  if ((rc = dalloc(c, &pl.d_work, kv.size() * size_t(tail.M) * tail.N))) return rc;
+  pl.shape = shape;
+  pl.order = order;
+  pl.n_tiles = int(tiles.size());
+  pl.tail_shape = tail_shape;
+  pl.tail_order = 1;
+  pl.tail_chunks = int(kv.size());
+  pl.n_ttiles = int(ttiles.size());
+  pl.tail_rows = tail.M;
+  pl.tail_cols = tail.N;
+  pl.tail_ldc = tail.ldc;
+  pl.tail_c_off = tail.c_off;
+  return GH_OK;
+}
+
+// One grouped GEMM of a plan: the main tile list; for a split plan then the
+// tail's partial products (a role that overwrites) and their sum into C
+// (added to C for role 2, C += A B).
+hipError_t launch_plan(const GemmPlan& pl, const double* src, double* dst, hipStream_t st, int role) {
+  hipError_t e = ghk::gemm(pl.shape, pl.d_tiles, pl.n_tiles, pl.d_groups, src, dst, st, role);
+  if (e != hipSuccess || pl.n_ttiles == 0) return e;
+  e = ghk::gemm(pl.tail_shape, pl.d_ttiles, pl.n_ttiles, pl.d_tgroups, src, pl.d_work, st, role == 2 ? 0 : role);
+  if (e != hipSuccess) return e;
+  return ghk::sum_chunks(pl.d_work, pl.tail_chunks, pl.tail_rows, pl.tail_cols, dst + pl.tail_c_off, pl.tail_ldc,
+                         role == 2, st);
+}
+
+// Five launches of a plan after one untimed, in ms.
+int time_plan(gh_ctx* c, const GemmPlan& pl, const double* src, double* dst, int role, hipEvent_t e0,
+              hipEvent_t e1, float* ms) {
+  HIPCHK(c, launch_plan(pl, src, dst, c->stream, role));
+  HIPCHK(c, hipEventRecord(e0, c->stream));
+  for (int it = 0; it < 5; ++it) HIPCHK(c, launch_plan(pl, src, dst, c->stream, role));
+  HIPCHK(c, hipEventRecord(e1, c->stream));
+  HIPCHK(c, hipEventSynchronize(e1));
+  HIPCHK(c, hipEventElapsedTime(ms, e0, e1));
   return GH_OK;
 }
 
@@ -315,14 +427,8 @@ int autotune(gh_ctx* c, GemmPlan& pl, const double* src, double* dst, int role) 
     for (int order = 0; order < 2; ++order) {
       int rc = plan_upload(c, pl, sh, order);
       if (rc) return rc;
-      HIPCHK(c, ghk::gemm(sh, pl.d_tiles, pl.n_tiles, pl.d_groups, src, dst, c->stream, role));
-      HIPCHK(c, hipEventRecord(e0, c->stream));
-      for (int it = 0; it < 5; ++it)
-        HIPCHK(c, ghk::gemm(sh, pl.d_tiles, pl.n_tiles, pl.d_groups, src, dst, c->stream, role));
-      HIPCHK(c, hipEventRecord(e1, c->stream));
-      HIPCHK(c, hipEventSynchronize(e1));
       float ms = 0;
-      HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+      if ((rc = time_plan(c, pl, src, dst, role, e0, e1, &ms))) return rc;
       if (ms < best) {
         best = ms;
         best_shape = sh;
@@ -330,8 +436,35 @@ int autotune(gh_ctx* c, GemmPlan& pl, const double* src, double* dst, int role) 
       }
     }
   }
+  // the fastest variant split for whole rounds of tiles, its tail rows in
+  // smaller tiles of another variant
+  int best_tail = -1, best_chunks = 0;
+  std::vector<GemmGroup> mainv, tailv;
+  if (split_rows(pl.groups, best_shape, c->n_cu, mainv, tailv) && tailv.size() == 1) {
+    int bm, bn;
+    ghk::tile_dims(best_shape, &bm, &bn);
+    for (int ts = 0; ts < ghk::NUM_TILE_SHAPES; ++ts) {
+      int tbm, tbn;
+      ghk::tile_dims(ts, &tbm, &tbn);
+      if (ts == best_shape || tbm * tbn >= bm * bn) continue;
+      for (int chunks = 2; chunks <= 8; chunks *= 2) {
+        if (tailv[0].K < 16 * chunks) continue;
+        int rc = plan_upload_split(c, pl, mainv, tailv[0], best_shape, best_order, ts, chunks);
+        if (rc) return rc;
+        float ms = 0;
+        if ((rc = time_plan(c, pl, src, dst, role, e0, e1, &ms))) return rc;
+        if (ms < best) {
+          best = ms;
+          best_tail = ts;
+          best_chunks = chunks;
+        }
+      }
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (best_tail >= 0)
+    return plan_upload_split(c, pl, mainv, tailv[0], best_shape, best_order, best_tail, best_chunks);
   return plan_upload(c, pl, best_shape, best_order);
 }
 
@@ -383,14 +516,14 @@ int queue_derivs(gh_ctx* c, const double* u, double* dR = nullptr, double* dA = 
     // Fourier analysis into the RHS work space (free until the pointwise
     // kernel), theta kernels, synthesis into dA
     Timed t(c, 8);
-    HIPCHK(c, ghk::gemm(c->tr_ana.shape, c->tr_ana.d_tiles, c->tr_ana.n_tiles, c->tr_ana.d_groups, u, c->d_W,
+    HIPCHK(c, launch_plan(c->tr_ana, u, c->d_W,
                         c->stream, 4));
     HIPCHK(c, ghk::ang_theta(c->tr_nmax, c->d_sh, c->d_tblk, c->n_tblk, c->d_ktab, c->d_W, c->d_X, 0, c->stream));
-    HIPCHK(c, ghk::gemm(c->tr_syn.shape, c->tr_syn.d_tiles, c->tr_syn.n_tiles, c->tr_syn.d_groups, c->d_X, dA,
+    HIPCHK(c, launch_plan(c->tr_syn, c->d_X, dA,
                         c->stream, 5));
   } else {
     Timed t(c, 0);
-    HIPCHK(c, ghk::gemm(c->deriv.shape, c->deriv.d_tiles, c->deriv.n_tiles, c->deriv.d_groups, u, dA, c->stream,
+    HIPCHK(c, launch_plan(c->deriv, u, dA, c->stream,
                         0));
   }
   {
@@ -413,11 +546,11 @@ int queue_tensor_filter(gh_ctx* c, const double* src, double* dst, bool transpos
   const GemmPlan& s2p = transpose ? c->tf_s2pT : c->tf_s2p;
   const bool tr = c->filt_tr && !transpose;   // by transforms: Fourier GEMM + per-order Legendre steps
   if (tr) {
-    HIPCHK(c, ghk::gemm(c->tr_ana.shape, c->tr_ana.d_tiles, c->tr_ana.n_tiles, c->tr_ana.d_groups, src, c->d_W,
+    HIPCHK(c, launch_plan(c->tr_ana, src, c->d_W,
                         c->stream, 4));
     HIPCHK(c, ghk::leg_analysis(c->d_sh, c->d_lg_ablk, c->n_lg_ablk, c->d_legtab, c->d_W, X, c->stream));
   } else {
-    HIPCHK(c, ghk::gemm(p2s.shape, p2s.d_tiles, p2s.n_tiles, p2s.d_groups, src, X, c->stream, 6));
+    HIPCHK(c, launch_plan(p2s, src, X, c->stream, 6));
   }
   {
     Timed t(c, 9);
@@ -428,10 +561,10 @@ int queue_tensor_filter(gh_ctx* c, const double* src, double* dst, bool transpos
   }
   if (tr) {
     HIPCHK(c, ghk::leg_synthesis(c->d_sh, c->d_lg_sblk, c->n_lg_sblk, c->d_legtab, Y, c->d_W, c->stream));
-    HIPCHK(c, ghk::gemm(c->tr_fsyn.shape, c->tr_fsyn.d_tiles, c->tr_fsyn.n_tiles, c->tr_fsyn.d_groups, c->d_W, dst,
+    HIPCHK(c, launch_plan(c->tr_fsyn, c->d_W, dst,
                         c->stream, 5));
   } else {
-    HIPCHK(c, ghk::gemm(s2p.shape, s2p.d_tiles, s2p.n_tiles, s2p.d_groups, Y, dst, c->stream, 7));
+    HIPCHK(c, launch_plan(s2p, Y, dst, c->stream, 7));
   }
   return GH_OK;
 }
@@ -442,13 +575,13 @@ int queue_filter(gh_ctx* c, const double* src, double* dst) {
   Timed t(c, 1);
   if (c->filter_kind >= 2) return queue_tensor_filter(c, src, dst, false);
   if (c->filt_tr) {
-    HIPCHK(c, ghk::gemm(c->tr_ana.shape, c->tr_ana.d_tiles, c->tr_ana.n_tiles, c->tr_ana.d_groups, src, c->d_W,
+    HIPCHK(c, launch_plan(c->tr_ana, src, c->d_W,
                         c->stream, 4));
     HIPCHK(c, ghk::ang_theta(c->tr_nmax, c->d_sh, c->d_tblk, c->n_tblk, c->d_ktab, c->d_W, c->d_X, 1, c->stream));
-    HIPCHK(c, ghk::gemm(c->tr_fsyn.shape, c->tr_fsyn.d_tiles, c->tr_fsyn.n_tiles, c->tr_fsyn.d_groups, c->d_X, dst,
+    HIPCHK(c, launch_plan(c->tr_fsyn, c->d_X, dst,
                         c->stream, 5));
   } else {
-    HIPCHK(c, ghk::gemm(c->filter.shape, c->filter.d_tiles, c->filter.n_tiles, c->filter.d_groups, src, dst,
+    HIPCHK(c, launch_plan(c->filter, src, dst,
                         c->stream, 1));
   }
   return GH_OK;
@@ -579,7 +712,7 @@ int queue_rhs_vjp(gh_ctx* c, const double* x, const double* mu, double* out, dou
   }
   {
     Timed t(c, 7);
-    HIPCHK(c, ghk::gemm(c->derivT.shape, c->derivT.d_tiles, c->derivT.n_tiles, c->derivT.d_groups, c->d_dAb, out,
+    HIPCHK(c, launch_plan(c->derivT, c->d_dAb, out,
                         c->stream, 2));
   }
   if (c->maxr)
@@ -605,6 +738,9 @@ int gh_create(gh_ctx** out, int device, void* hip_stream) {
   if (hipSetDevice(device) != hipSuccess) return GH_ERR_DEVICE;
   gh_ctx* c = new gh_ctx();
   c->device = device;
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+    c->n_cu = ncu;
   c->stream = static_cast<hipStream_t>(hip_stream);
   *out = c;
   return GH_OK;
@@ -1394,7 +1530,7 @@ int queue_step_vjp(gh_ctx* c, const double* u_n, const double* u1, const double*
   // filter: u_{n+1} = F u3, so lam3 = F^T lam_{n+1}
   const double* lam3 = lam_np1;
   if (c->filter_kind == 1) {
-    HIPCHK(c, ghk::gemm(c->filterT.shape, c->filterT.d_tiles, c->filterT.n_tiles, c->filterT.d_groups, lam_np1,
+    HIPCHK(c, launch_plan(c->filterT, lam_np1,
                         c->d_lam3, c->stream, 3));
     lam3 = c->d_lam3;
   } else if (c->filter_kind >= 2) {
@@ -1513,7 +1649,7 @@ int gh_constraints_vjp(gh_ctx* c, const double* u, const double* lam_norm, doubl
   HIPCHK(c, ghk::reduce_norm(c->d_inst_range, c->n_inst, c->d_partial, c->d_wsum, c->d_norm, c->stream));
   HIPCHK(c, ghk::constraints_vjp(c->d_sh, c->d_blk, c->n_blk, c->d_angtab, c->d_radtab, u, c->d_H, c->d_C, c->d_norm,
                                  c->d_wsum, lam_norm, lam_u, c->d_dRb, c->d_dAb, c->stream));
-  HIPCHK(c, ghk::gemm(c->derivT.shape, c->derivT.d_tiles, c->derivT.n_tiles, c->derivT.d_groups, c->d_dAb, lam_u,
+  HIPCHK(c, launch_plan(c->derivT, c->d_dAb, lam_u,
                       c->stream, 2));
   if (!c->maxr) return fail(c, GH_ERR_ARG, "adjoint needs n_r <= 64");
   HIPCHK(c, ghk::radial_col(c->maxr, c->d_sh, c->d_cblk, c->n_cblk, c->d_dtab, c->d_dRb, lam_u, 0, 50, true, true,
@@ -1599,6 +1735,9 @@ int gh_query(const gh_ctx* c, int what, long long* value) {
     case 11: *value = c->tf_nnz; break;
     case 12: *value = c->n_tf_items[0] + c->n_tf_items[1] + c->n_tf_items[2]; break;
     case 13: *value = c->iface_mode; break;
+    case 14: *value = c->deriv.n_ttiles ? c->deriv.tail_shape : -1; break;
+    case 15: *value = c->filter.n_ttiles ? c->filter.tail_shape : -1; break;
+    case 16: *value = c->deriv.n_ttiles ? c->deriv.tail_chunks : 0; break;
     default: return GH_ERR_ARG;
   }
   return GH_OK;

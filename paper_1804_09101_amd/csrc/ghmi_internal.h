@@ -156,6 +156,10 @@ hipError_t boundary_vjp(const ShellDev* sh, int n_shells, int max_S, const doubl
 hipError_t gamma_reduce(const int* blk_range, const int* shell_range, int n_inst, int max_S,
                         const double* gpart, const double* bcg, const double* dt, double coef, int use_dt,
                         double* g, hipStream_t st);
+// C (rows x cols, leading dimension ldc) = (accumulate: +=) the chunk-ordered
+// sum of the nchunk row-major partial blocks in W (split-K tail of a GEMM plan).
+hipError_t sum_chunks(const double* W, int nchunk, int rows, int cols, double* C, int ldc, bool accumulate,
+                      hipStream_t st);
 hipError_t lincomb(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* dt, int use_dt, double ca,
                    const double* x, double cb, const double* y, double cc, const double* z, double* out,
                    hipStream_t st);

@@ -1051,6 +1051,23 @@ __global__ __launch_bounds__(256) void k_dp_accept(const ShellDev* __restrict__ 
   if (dst2) dst2[e] = src2[e];
 }
 
+// Split-K tail of a GEMM plan: C[r][c] = (or +=) the sum over chunks q of
+// W[q][r][c], added in chunk order (so the result is the same on every run).
+// W holds nchunk row-major blocks of rows x cols.
+template <bool ACC>
+__global__ __launch_bounds__(256) void k_sum_chunks(const double* __restrict__ W, int nchunk, int rows, int cols,
+                                                   double* __restrict__ C, int ldc) {
+  const long long n = (long long)rows * cols;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double s = W[i];
+  for (int q = 1; q < nchunk; ++q) s += W[(long long)q * n + i];
+  const long long r = i / cols, col = i - r * cols;
+  double* o = C + r * ldc + col;
+  if (ACC) *o += s;
+  else *o = s;
+}
+
 __global__ __launch_bounds__(256) void k_fill_int(int* __restrict__ x, int n, int v) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < n) x[i] = v;
@@ -1354,6 +1371,16 @@ hipError_t radial(const ShellDev* sh, const PtBlock* blk, int n_blk, const doubl
                   const double* u, double* dR, int ncomp_lo, int ncomp_hi, hipStream_t st) {
   dim3 grid(n_blk, ncomp_hi - ncomp_lo), block(256);
   hipLaunchKernelGGL(k_radial, grid, block, 0, st, sh, blk, dtab, u, dR, ncomp_lo);
+  return hipGetLastError();
+}
+
+hipError_t sum_chunks(const double* W, int nchunk, int rows, int cols, double* C, int ldc, bool accumulate,
+                      hipStream_t st) {
+  const long long n = (long long)rows * cols;
+  if (n <= 0) return hipSuccess;
+  dim3 grid(unsigned((n + 255) / 256));
+  if (accumulate) hipLaunchKernelGGL(k_sum_chunks<true>, grid, dim3(256), 0, st, W, nchunk, rows, cols, C, ldc);
+  else hipLaunchKernelGGL(k_sum_chunks<false>, grid, dim3(256), 0, st, W, nchunk, rows, cols, C, ldc);
   return hipGetLastError();
 }
 

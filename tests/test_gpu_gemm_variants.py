@@ -43,3 +43,34 @@ def test_every_variant_and_order():
         with pytest.raises(ghmi.GHError) as ei:
             c.s.set_gemm_variant(*bad)
         assert ei.value.code == -1
+
+
+def test_split_plan_matches_one_launch():
+    """pulse_8shell's derivative GEMM has 1 056 tiles of 128 x 64, 4.125 per
+    CU of the MI355X: the tuner may split it into whole rounds plus a tail over
+    K chunks.  Whatever it keeps, the RHS matches the oracle, and the RHS and a
+    filtered step match the same variants pinned as one launch up to the
+    rounding of the reordered K sums (1e-13 of the term scale and of the
+    state); two runs of the split plan are bitwise equal."""
+    wl = configs.pulse_8shell()
+    c = Case(wl)
+    u = dev(c.u0)
+    tuned_rhs = c.s.rhs(u)
+    assert torch.equal(c.s.rhs(u), tuned_rhs)
+    tuned_step = u.clone()
+    c.s.step(tuned_step, 1)
+    print(f"  tuned: derivative variant {c.s.query(6)} tail {c.s.query(14)} over {c.s.query(16)} K chunks, "
+          f"filter variant {c.s.query(7)} tail {c.s.query(15)}", flush=True)
+    ref = c.oracle_rhs(c.u0)
+    scale = max(np.max(np.abs(ref)), c.term_scale(c.u0))
+    err = np.max(np.abs(tuned_rhs.cpu().numpy() - ref)) / scale
+    assert err < 1e-12
+    c.s.set_gemm_variant(0, c.s.query(6), c.s.query(4))
+    c.s.set_gemm_variant(1, c.s.query(7), c.s.query(5))
+    assert c.s.query(14) == -1 and c.s.query(15) == -1 and c.s.query(16) == 0
+    one = u.clone()
+    c.s.step(one, 1)
+    d_rhs = float((c.s.rhs(u) - tuned_rhs).abs().max()) / scale
+    d_step = float((one - tuned_step).abs().max() / one.abs().max())
+    print(f"  split vs one launch: rhs {d_rhs:.2e} of the term scale, step {d_step:.2e} of the state", flush=True)
+    assert d_rhs < 1e-13 and d_step < 1e-13
