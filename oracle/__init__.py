@@ -22,9 +22,11 @@ Modules:
             SSP-RK3 step, filter, constraint norm
   tensor_filter  the tensor-coupled angular filter (total angular momentum)
   dp5       Dormand-Prince 5(4) tableau and step control
+  kerr_schild  the oracle's own exact Kerr-Schild spacetimes (hyper-dual
+            derivatives), used by its pins instead of the input generator
 
 All functions accept complex128 inputs so that complex-step differentiation
 gives exact directional derivatives (used as the reference gradient).
 """
 
-from . import grid, spectral, gh, domain, tensor_filter  # noqa: F401
+from . import grid, spectral, gh, domain, tensor_filter, kerr_schild  # noqa: F401

@@ -153,3 +153,47 @@ def test_interface_projection_from_the_state():
         assert np.array_equal(a[k][:, inner], b[k][:, inner])
     assert np.max(np.abs(a[0][:, -1] - b[0][:, -1])) > 1e-6 * np.max(np.abs(a[0][:, -1]))
     assert np.array_equal(a[2][:, -1], b[2][:, -1])          # outer boundary: Dirichlet in both
+
+
+def test_constraint_norm_closed_form():
+    """Flat metric psi = eta, Pi = 0, with H_a chosen so that C_a = 0.
+
+    Instance 0 (two shells of different widths, [2, 3] and [3, 5.5]):
+    Phi_iab = c x_i for every pair, so C_iab = -c x_i, C_ijab = d_i(c x_j) -
+    d_j(c x_i) = 0 and sum_c C_c^2 = 10 c^2 r^2; the volume average over the
+    ball shell [a, b] is 10 c^2 (3/5)(b^5 - a^5)/(b^3 - a^3).
+    Instance 1 (one shell): Phi_iab = c' constant, C_iab = -c', so the norm is
+    |c'| sqrt(30).
+    The gauge source: g^ij Phi_ija = c sum_i x_i, psi^bc Phi_ibc = 2 c x_i, so
+    C_0 = H_0 + c s and C_j = H_j + c s - c x_j (s = x + y + z).
+    A missing square root, a missing division by the weight sum, a missing r^2
+    or shell-width factor, or a mix of the instances changes one of the two
+    values."""
+    c, c1 = 0.37, -0.21
+    shells = [domain.Shell(0, 7, 3, 2.0, 3.0), domain.Shell(0, 9, 3, 3.0, 5.5),
+              domain.Shell(1, 6, 2, 1.5, 4.0)]
+    d = domain.Domain(shells)
+    xyz = d.xyz()
+    P = xyz.shape[1]
+    inst = np.concatenate([np.full(n, shells[k].instance) for k, n in enumerate(d.npts)])
+    u = np.zeros((50, P))
+    for n, (a, b) in enumerate(gh.PAIRS):
+        if a == b:
+            u[n] = -1.0 if a == 0 else 1.0
+    H = np.zeros((4, P))
+    s = xyz.sum(axis=0)
+    for i in range(3):
+        phi = np.where(inst == 0, c * xyz[i], c1)
+        u[20 + 10 * i:30 + 10 * i] = phi
+    H[0] = np.where(inst == 0, -c * s, -3.0 * c1)
+    for j in range(3):
+        H[j + 1] = np.where(inst == 0, -c * s + c * xyz[j], -2.0 * c1)
+    uL, HL = d.to_layout(u), d.to_layout(H)
+    C = d.split(d.constraints(uL, HL), 64)
+    for blk in C:
+        assert np.max(np.abs(blk[0:4])) < 1e-14            # C_a = 0 as constructed
+    norm = d.constraint_norm(uL, HL)
+    a_, b_ = 2.0, 5.5
+    want0 = math.sqrt(10 * c * c * 0.6 * (b_ ** 5 - a_ ** 5) / (b_ ** 3 - a_ ** 3))
+    assert abs(norm[0] - want0) < 1e-13 * want0
+    assert abs(norm[1] - abs(c1) * math.sqrt(30.0)) < 1e-14

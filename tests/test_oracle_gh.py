@@ -12,7 +12,12 @@ break:
       eigenvectors with the published speeds;
   gamma0: a homogeneous constraint violation on flat space decays
       (d_t C_0 = -2 gamma0 C_0, d_t C_i = -gamma0 C_i at linear order);
-  the gauge constraint written two ways agrees and vanishes on Kerr-Schild.
+  the gauge constraint written two ways agrees and vanishes on Kerr-Schild;
+  the characteristic projection used at boundaries (char_fields) is, row by
+  row, a left eigenvector of that principal symbol with the published speed
+  (so its gamma2 term is fixed by the RHS, not only by its own inverse).
+The exact spacetimes come from the oracle's own generator
+(oracle/kerr_schild.py), not from the seeded input generator.
 """
 
 import math
@@ -21,7 +26,7 @@ import numpy as np
 import pytest
 
 from oracle import gh, grid
-from paper_1804_09101_amd import inputs
+from oracle import kerr_schild as ks
 
 GAMMAS = [(1.0, -1.0, 1.0), (0.3, 0.7, -0.2), (2.5, 0.0, 0.4)]
 
@@ -33,7 +38,7 @@ def _points(n=5, L=4, r_in=1.9, r_out=6.0):
 @pytest.fixture(scope="module")
 def kerr():
     xyz = _points()
-    return inputs.kerr_schild(xyz, M=1.0, chi=0.7, axis=(0.2, 0.3, 0.4), with_derivs=True)
+    return ks.exact_fields(xyz, M=1.0, chi=0.7, axis=(0.2, 0.3, 0.4))
 
 
 @pytest.mark.parametrize("gam", GAMMAS)
@@ -47,8 +52,7 @@ def test_p1_kerr_schild_rhs_vanishes(kerr, gam):
 @pytest.mark.parametrize("gam", GAMMAS)
 def test_p1_boosted_hole_rhs_is_time_derivative(gam):
     xyz = _points(5, 4, 2.6, 7.0)
-    gf = inputs.kerr_schild_metric(1.0, 0.4, (0.1, 0.5, 0.3), boost=(0.25, -0.1, 0.15))
-    ex = inputs.exact_spacetime(xyz, gf, with_derivs=True)
+    ex = ks.exact_fields(xyz, M=1.0, chi=0.4, axis=(0.1, 0.5, 0.3), boost=(0.25, -0.1, 0.15))
     assert np.max(np.abs(ex["dtu"])) > 1e-2           # genuinely time dependent
     assert np.max(np.abs(ex["dH"].reshape(4, 4, -1)[0])) > 1e-3   # d_t H_a != 0
     r = gh.rhs_pointwise(ex["u"], ex["du"], ex["H"], ex["dH"].reshape(4, 4, -1), *gam)
@@ -174,6 +178,40 @@ def test_p3_principal_symbol_characteristic_structure(kerr, gam):
             assert np.max(np.abs(e @ A[p] + v * e)) < 1e-12
 
 
+@pytest.mark.parametrize("gam", GAMMAS)
+def test_char_fields_are_left_eigenvectors_of_principal_symbol(kerr, gam):
+    """Every row of the projection char_fields (the map the boundary treatment
+    uses) is a left eigenvector of the RHS's principal symbol A(s) with the
+    speed char_speeds gives it: e A = -v e.  The rows are read off by applying
+    char_fields to the 50 unit vectors; a sign or a missing gamma2 term in any
+    projection breaks the relation for that row."""
+    g0, g1, g2 = gam
+    npt = 5
+    u = kerr["u"][:, 3:3 + npt] + 1e-2 * np.random.default_rng(8).standard_normal((50, npt))
+    psi, _, _ = gh.unpack_fields(u)
+    geo = gh.Geometry(psi)
+    s_lo, s_up = gh.unit_normal(geo, np.random.default_rng(9).standard_normal((3, npt)))
+    A = _principal_matrix(u, s_lo, gam)
+    v_psi, v_0, v_p, v_m = gh.char_speeds(geo, s_lo, g1)
+    eye = np.eye(50)
+    for p in range(npt):
+        sl = np.repeat(s_lo[:, p:p + 1], 50, axis=1)
+        su = np.repeat(s_up[:, p:p + 1], 50, axis=1)
+        upsi, u0, up, um = gh.char_fields(eye, sl, su, g2)      # [.., 50]: rows of the map
+        groups = [(upsi, v_psi[p]), (up, v_p[p]), (um, v_m[p])] + [(u0[i], v_0[p]) for i in range(3)]
+        for rows, v in groups:
+            assert np.linalg.matrix_rank(rows, tol=1e-10) >= 3       # not vacuous
+            for e in rows:
+                assert np.max(np.abs(e @ A[p] + v * e)) < 1e-12
+        # the rows span the whole field space (the boundary map can be inverted)
+        R = np.concatenate([upsi, u0.reshape(30, 50), up, um])
+        assert np.linalg.matrix_rank(R, tol=1e-10) == 50
+        # and the reconstruction inverts them on every field vector
+        v = np.random.default_rng(p).standard_normal((50, 50))
+        back = gh.char_reconstruct(*gh.char_fields(v, sl, su, g2), sl, g2)
+        assert np.max(np.abs(back - v)) < 1e-13
+
+
 def test_characteristic_roundtrip(kerr):
     rng = np.random.default_rng(7)
     v = rng.standard_normal((50, 9))
@@ -193,7 +231,7 @@ def test_excision_speeds_closed_form():
     """
     M, r = 1.0, 1.8
     xyz = np.array([[r], [0.0], [0.0]])
-    ex = inputs.kerr_schild(xyz, M=M, chi=0.0)
+    ex = ks.exact_fields(xyz, M=M, chi=0.0)
     psi, _, _ = gh.unpack_fields(ex["u"])
     geo = gh.Geometry(psi)
     s_lo, _ = gh.unit_normal(geo, np.array([[-1.0], [0.0], [0.0]]))
