@@ -31,8 +31,10 @@
  *    allocated in gh_set_domain and freed by gh_destroy / the next
  *    gh_set_domain.
  *  - Setup calls (gh_set_domain, gh_set_background, gh_set_params) are
- *    synchronous.  Compute calls (gh_rhs, gh_step, gh_constraints) are queued
- *    on the context's HIP stream and return before the work completes.
+ *    synchronous: they return when the new values are in place, after the
+ *    work already queued on the context has used the old ones.  Compute
+ *    calls (gh_rhs, gh_step, gh_constraints, ...) are queued on the
+ *    context's HIP stream and return before the work completes.
  *  - Calls on one context must not overlap (one host thread at a time).
  *
  * Layout: shells are concatenated in the order given to gh_set_domain
@@ -102,7 +104,14 @@ int gh_set_domain(gh_ctx* ctx, int n_inst, int n_shells, const gh_shell* shells,
 int gh_num_points(const gh_ctx* ctx, long long* total_points, long long* shell_offsets);
 
 /* Background data, DEVICE pointers in the shell layout (copied; the caller
- * may free them afterwards):
+ * may free them afterwards).  The paper's test problem is an isolated
+ * Kerr-Schild black hole (port overview, eq. dimensionlessspin); the gauge
+ * source of the GH system is an input here, frozen in time (for a stationary
+ * hole H_a = -psi^bc Gamma_abc of the exact metric, which makes the hole an
+ * exact solution).  Of the paper's three ApplyBCs cases (Conclusions) this
+ * call prepares the internal-boundary exchange (through u_bg) and checks the
+ * excision case, which needs no condition when all characteristics leave the
+ * domain:
  *   H    [4 components]  gauge source H_a;
  *   dH   [16 components] d_a H_b at component a*4+b (a = 0: time derivative);
  *   u_bg [50 components] background state.  At shell interfaces it fixes the
@@ -113,8 +122,14 @@ int gh_num_points(const gh_ctx* ctx, long long* total_points, long long* shell_o
 int gh_set_background(gh_ctx* ctx, const double* H, const double* dH, const double* u_bg);
 
 /* Constraint-damping parameters gamma [n_inst][3] = (gamma0, gamma1, gamma2)
- * and time steps dt [n_inst] (HOST pointers; dt may be NULL if only gh_rhs
- * and gh_constraints are used). */
+ * of the first-order GH system (Lindblom et al. 2006, eqs. 35-37; the paper
+ * names the system in its port overview but prints neither the equations nor
+ * the parameter values) and time steps dt [n_inst] of the method-of-lines
+ * evolution (section "The Spectral Einstein Code") (HOST pointers; dt may be
+ * NULL if only gh_rhs and gh_constraints are used).  Waits for the work
+ * already queued on the context's stream (and for graph replays) before the
+ * new values replace the old ones, since that work reads them from device
+ * memory. */
 int gh_set_params(gh_ctx* ctx, const double* gamma, const double* dt);
 
 /* dudt = d_t u including boundary treatment.  u, dudt: device [50] layout;
@@ -175,7 +190,12 @@ int gh_set_angular(gh_ctx* ctx, int method);
  * Bypassed while kernel timing is on. */
 int gh_set_graph(gh_ctx* ctx, int enable);
 
-/* Constraints of u.  C (device [64] layout, may be NULL) receives per point
+/* Constraints of u.  The paper evolves the GH system without printing its
+ * constraints; these are the constraints of the first-order system
+ * (Lindblom et al. 2006: the gauge constraint, their eq. 40, and the three-
+ * and four-index constraints of the first-order reduction), and the norm is
+ * this library's monitor, a volume average with the grid's own quadrature.
+ * C (device [64] layout, may be NULL) receives per point
  * C_a (4), C_iab = d_i psi_ab - Phi_iab (30, i = x,y,z) and
  * C_ijab = d_i Phi_jab - d_j Phi_iab (30, ij = xy, xz, yz).
  * norm (device [n_inst], may be NULL) receives per instance
@@ -187,7 +207,9 @@ int gh_constraints(gh_ctx* ctx, const double* u, double* C, double* norm);
  * The paper has no adjoint; these are the transposes of the linearised
  * operations above, for gradients of a loss of the final state with respect
  * to the initial state and the damping parameters.  The background (H, dH,
- * frozen boundary projections) and dt are constants.  The first call of
+ * frozen boundary projections) and dt are constants.  Every domain that
+ * gh_set_domain accepts (n_r up to 256, L up to 63) has a reverse pass.  The
+ * first call of
  * either function allocates ~9 further [50] work arrays and tunes the
  * transposed GEMMs (synchronous); later calls are queued on the stream. */
 

@@ -532,7 +532,7 @@ int queue_derivs(gh_ctx* c, const double* u, double* dR = nullptr, double* dA = 
       HIPCHK(c, ghk::radial_col(c->maxr, c->d_sh, c->d_cblk, c->n_cblk, c->d_dtab, u, dR, 0, 50, false, false,
                                 c->stream));
     else
-      HIPCHK(c, ghk::radial(c->d_sh, c->d_blk, c->n_blk, c->d_dtab, u, dR, 0, 50, c->stream));
+      HIPCHK(c, ghk::radial(c->d_sh, c->d_blk, c->n_blk, c->d_dtab, u, dR, 0, 50, false, false, c->stream));
   }
   return GH_OK;
 }
@@ -719,7 +719,7 @@ int queue_rhs_vjp(gh_ctx* c, const double* x, const double* mu, double* out, dou
     HIPCHK(c, ghk::radial_col(c->maxr, c->d_sh, c->d_cblk, c->n_cblk, c->d_dtab, c->d_dRb, out, 0, 50, true, true,
                               c->stream));
   else
-    return fail(c, GH_ERR_ARG, "adjoint needs n_r <= 64");
+    HIPCHK(c, ghk::radial(c->d_sh, c->d_blk, c->n_blk, c->d_dtab, c->d_dRb, out, 0, 50, true, true, c->stream));
   if (g)
     HIPCHK(c, ghk::gamma_reduce(c->d_inst_range, c->d_shell_range, c->n_inst, c->max_S, c->d_gpart, c->d_bcg,
                                 c->d_dt, coef, use_dt, g, c->stream));
@@ -1280,6 +1280,12 @@ int gh_set_params(gh_ctx* c, const double* gamma, const double* dt) {
     for (int i = 0; i < c->n_inst; ++i)
       if (!std::isfinite(dt[i]) || !(dt[i] > 0.0)) return fail(c, GH_ERR_ARG, "dt must be finite and > 0");
   HIPCHK(c, hipSetDevice(c->device));
+  // Work already queued (on the context's stream, or graph replays on the
+  // capture stream) reads gamma and dt from device memory: let it finish
+  // before they change.  A plain hipMemcpy would only be ordered against the
+  // null stream, not against a non-blocking caller stream.
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->cap_stream) HIPCHK(c, hipStreamSynchronize(c->cap_stream));
   HIPCHK(c, hipMemcpy(c->d_gamma, gamma, 3 * c->n_inst * sizeof(double), hipMemcpyHostToDevice));
   c->have_gamma = true;
   if (dt) {
@@ -1651,9 +1657,11 @@ int gh_constraints_vjp(gh_ctx* c, const double* u, const double* lam_norm, doubl
                                  c->d_wsum, lam_norm, lam_u, c->d_dRb, c->d_dAb, c->stream));
   HIPCHK(c, launch_plan(c->derivT, c->d_dAb, lam_u,
                       c->stream, 2));
-  if (!c->maxr) return fail(c, GH_ERR_ARG, "adjoint needs n_r <= 64");
-  HIPCHK(c, ghk::radial_col(c->maxr, c->d_sh, c->d_cblk, c->n_cblk, c->d_dtab, c->d_dRb, lam_u, 0, 50, true, true,
-                            c->stream));
+  if (c->maxr)
+    HIPCHK(c, ghk::radial_col(c->maxr, c->d_sh, c->d_cblk, c->n_cblk, c->d_dtab, c->d_dRb, lam_u, 0, 50, true, true,
+                              c->stream));
+  else
+    HIPCHK(c, ghk::radial(c->d_sh, c->d_blk, c->n_blk, c->d_dtab, c->d_dRb, lam_u, 0, 50, true, true, c->stream));
   return GH_OK;
 }
 

@@ -107,7 +107,8 @@ hipError_t tensor_couple(const TfItem* items, const int n_items[3], const TfSeg*
                          const double* val, const double* X, double* Y, hipStream_t st);
 
 hipError_t radial(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* dtab,
-                  const double* u, double* dR, int ncomp_lo, int ncomp_hi, hipStream_t st);
+                  const double* u, double* dR, int ncomp_lo, int ncomp_hi, bool transpose, bool accumulate,
+                  hipStream_t st);
 
 // Column form of the radial derivative (one thread per field x angular point);
 // maxr = radial_col_maxr(largest n_r) selects the register-array size (0: unsupported).

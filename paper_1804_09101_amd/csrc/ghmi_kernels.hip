@@ -20,8 +20,11 @@ __host__ __device__ constexpr int SYM3(int i, int j) {
 }
 
 // ---------------------------------------------------------------------------
-// Radial derivative: dR[f][r][a] = dscale * sum_r' D[r][r'] u[f][r'][a].
+// Radial derivative: dR[f][r][a] = dscale * sum_r' D[r][r'] u[f][r'][a], one
+// thread per point, any n_r (the column form below keeps a column in
+// registers and covers n_r <= 64).  TRANS applies D^T; ACC adds into dR.
 // ---------------------------------------------------------------------------
+template <bool TRANS, bool ACC>
 __global__ __launch_bounds__(256) void k_radial(const ShellDev* __restrict__ sh,
                                                 const PtBlock* __restrict__ blk,
                                                 const double* __restrict__ dtab,
@@ -35,11 +38,14 @@ __global__ __launch_bounds__(256) void k_radial(const ShellDev* __restrict__ sh,
   const int f = f0 + blockIdx.y;
   const int r = q / s.S, a = q - r * s.S;
   const long long base = 50LL * s.pt_off + (long long)f * P;
-  const double* D = dtab + s.d_off + r * s.n_r;
+  // row r of D (stride 1) or of D^T (column r of D, stride n_r)
+  const double* D = dtab + s.d_off + (TRANS ? r : r * s.n_r);
+  const int dstride = TRANS ? s.n_r : 1;
   const double* col = u + base + a;
   double acc = 0.0;
-  for (int rp = 0; rp < s.n_r; ++rp) acc += D[rp] * col[(long long)rp * s.S];
-  dR[base + q] = s.dscale * acc;
+  for (int rp = 0; rp < s.n_r; ++rp) acc += D[rp * dstride] * col[(long long)rp * s.S];
+  if (ACC) dR[base + q] += s.dscale * acc;
+  else dR[base + q] = s.dscale * acc;
 }
 
 // Radial derivative, one thread per (field, angular point) column: the n_r
@@ -1368,9 +1374,17 @@ hipError_t tensor_couple(const TfItem* items, const int n_items[3], const TfSeg*
 }
 
 hipError_t radial(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* dtab,
-                  const double* u, double* dR, int ncomp_lo, int ncomp_hi, hipStream_t st) {
+                  const double* u, double* dR, int ncomp_lo, int ncomp_hi, bool transpose, bool accumulate,
+                  hipStream_t st) {
   dim3 grid(n_blk, ncomp_hi - ncomp_lo), block(256);
-  hipLaunchKernelGGL(k_radial, grid, block, 0, st, sh, blk, dtab, u, dR, ncomp_lo);
+  if (!transpose && !accumulate)
+    hipLaunchKernelGGL((k_radial<false, false>), grid, block, 0, st, sh, blk, dtab, u, dR, ncomp_lo);
+  else if (!transpose)
+    hipLaunchKernelGGL((k_radial<false, true>), grid, block, 0, st, sh, blk, dtab, u, dR, ncomp_lo);
+  else if (!accumulate)
+    hipLaunchKernelGGL((k_radial<true, false>), grid, block, 0, st, sh, blk, dtab, u, dR, ncomp_lo);
+  else
+    hipLaunchKernelGGL((k_radial<true, true>), grid, block, 0, st, sh, blk, dtab, u, dR, ncomp_lo);
   return hipGetLastError();
 }
 

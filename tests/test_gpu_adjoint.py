@@ -60,6 +60,33 @@ def test_rhs_vjp_dot_product():
     assert abs(lg - rg) < 1e-11 * np.sum(np.abs(lam * jg))
 
 
+def test_vjp_dot_products_beyond_column_radial_form():
+    """n_r = 70 is above what the register-column radial kernel holds (64), so
+    the reverse pass takes the point form of the transposed radial derivative;
+    the RHS and constraint-norm transposes must still pass the dot test."""
+    shells = [(0, 70, 3, 1.8, 4.0), (0, 9, 3, 4.0, 5.0)]
+    wl, d, s, u0, ubg, H, dH = _setup(shells, [(1.0, 0.2, (0, 1, 1))], [(0.8, -0.4, 1.2)], [0.001], None,
+                                      pert=1e-2)
+    rng = np.random.default_rng(5)
+    lam = rng.standard_normal(u0.shape)
+    v = rng.standard_normal(u0.shape)
+    vg = rng.standard_normal((1, 3))
+    jv = d.rhs(u0 + 1j * H_CS * v, H, dH, ubg, wl.gamma + 1j * H_CS * vg).imag / H_CS
+    lhs = np.sum(lam * jv)
+    g = torch.zeros(3, dtype=torch.float64, device="cuda:0")
+    lu = s.rhs_vjp(dev(u0), dev(lam), g_gamma=g).cpu().numpy()
+    rhs = np.sum(lu * v) + np.sum(g.cpu().numpy() * vg.ravel())
+    err = abs(lhs - rhs) / np.sum(np.abs(lam * jv))
+    print(f"  rhs vjp at n_r = 70: rel {err:.2e}", flush=True)
+    assert err < 1e-12
+    lam_n = np.array([0.9])
+    jn = d.constraint_norm(u0 + 1j * H_CS * v, H).imag / H_CS
+    ln = s.constraints_vjp(dev(u0), dev(lam_n)).cpu().numpy()
+    err = abs(np.sum(lam_n * jn) - np.sum(ln * v)) / np.sum(np.abs(lam_n * jn))
+    print(f"  constraints vjp at n_r = 70: rel {err:.2e}", flush=True)
+    assert err < 1e-12
+
+
 def test_step_vjp_dot_product_with_filter():
     rs = configs.geometric_radii(1.8, 9.0, 2)
     shells = [(0, 9, 7, rs[0], rs[1]), (0, 9, 7, rs[1], rs[2])]
