@@ -2,22 +2,25 @@
 
 A step is one SSP-RK3 step of the whole domain: three right-hand-side
 evaluations (angular derivative GEMM, radial derivative, pointwise GH algebra,
-boundary treatment), three stage updates and the angular filter.  The workload
-is the 8-shell pulse problem: 8 shells r in [1.8, 100], N_r = 21, L = 15
-(16 x 32), Schwarzschild M = 1 with a Gaussian pulse in Pi_ab, FP64.
+boundary treatment) and three stage updates.  The headline workload is the
+largest single-GPU configuration, the 20-shell domain: 20 shells r in
+[1.4, 400], N_r = 33, L = 31 (32 x 64), Kerr chi = 0.9, M = 1, with a seeded
+smooth perturbation of 1e-6 in all 50 fields, FP64 (1 351 680 points), the
+angular derivatives as one grouped FP64-MFMA GEMM of the dense operators.
 
 Metric: grid-point RHS evaluations per second = points * 3 * steps / time.
 The timed region records HIP events around the angular derivative GEMM (the
 roofline kernel) only; the per-kernel split comes from a separate run with
-events around every launch.  Further measurements on the same GPU: the same
-steps replayed from a captured HIP graph; the angular operators by transforms
-(gh_set_angular 2); the constraints and their norm (gh_constraints); the
-interface projection taken from the state; the tensor-coupled filter (dense and by transforms, its coupling kernel against
-the HBM roofline); adaptive Dormand-Prince 5(4) stepping; the adjoint/forward
-cost ratio of a 200-step evolution with gradients of the final constraint
-norm (checkpoint every 20 steps); 64 heterogeneous Kerr holes in one context
-against one context per hole; the 20-shell L = 31 domain (forward rate, and
-the adjoint/forward ratio on a 4-instance batch).
+events around every launch.  Further measurements on the same GPU: the
+20-shell steps replayed from a captured HIP graph and with the angular
+operators by transforms (gh_set_angular 2); its 4-instance batch (forward,
+and the adjoint/forward cost ratio of a checkpointed gradient of the final
+constraint norm); the 8-shell pulse workload (its own GEMM roofline, graph,
+transforms, constraints, the interface projection taken from the state, the
+tensor-coupled filter, adaptive Dormand-Prince 5(4) stepping, the 200-step
+adjoint/forward ratio); 64 heterogeneous Kerr holes in one context against
+one context per hole.  cpu_baseline: the CPU oracle on one shell of the
+20-shell domain on one thread (and on every thread of the pool).
 
 Prints one JSON line.  With --gpus > 1 it exits: the path runs on one GPU.
 """
@@ -42,11 +45,12 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-PROFILE = os.path.join(ROOT, "profiles", "pulse_8shell_step_kernels.md")
+PROFILE_LARGE = os.path.join(ROOT, "profiles", "large_20shell_step_kernels.md")
+PROFILE_PULSE = os.path.join(ROOT, "profiles", "pulse_8shell_step_kernels.md")
 KERNEL_SOURCES = ["ghmi_gemm.hip", "ghmi_gemm.h"]
 
 
-def gemm_traffic(variant, order):
+def gemm_traffic(profile, variant, order):
     """HBM bytes per launch of the derivative GEMM from the committed PMC records.
 
     The profile summary lists, for every kernel variant and tile order,
@@ -57,7 +61,7 @@ def gemm_traffic(variant, order):
     """
     import hashlib
     try:
-        lines = open(PROFILE).read().splitlines()
+        lines = open(profile).read().splitlines()
     except OSError:
         return None
     h = hashlib.sha256()
@@ -74,25 +78,41 @@ def gemm_traffic(variant, order):
     return None
 
 
-def cpu_baseline(wl, n_rhs):
-    """Time the CPU oracle on n_rhs RHS evaluations of the same workload."""
+def cpu_baseline(wl, n_shells=1, n_rhs=1):
+    """The CPU oracle on a bounded sample of the workload: the RHS of its first
+    n_shells shells (boundary treatment included), n_rhs evaluations, once on
+    one thread (threadpoolctl limits NumPy's pools in-process) and once on
+    every thread of the pool.  Rates in grid-point RHS evaluations/s."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import domain
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        threads = os.cpu_count() or 1
-    d = domain.Domain([domain.Shell(*s) for s in wl.shells], filter_params=wl.filter_params)
-    u0, ubg, H, dH = wl.initial_data(d.xyz(), d.offsets)
-    d.rhs(u0, H, dH, ubg, wl.gamma)       # warm the transform tables
-    t0 = time.perf_counter()
-    for _ in range(n_rhs):
-        d.rhs(u0, H, dH, ubg, wl.gamma)
-    t = time.perf_counter() - t0
-    return {"value": d.P * n_rhs / t, "unit": "grid-point RHS evals/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"{n_rhs} RHS evaluations of the full 8-shell workload ({d.P} points), "
-                      f"NumPy oracle, {t:.1f} s"}
+    from paper_1804_09101_amd import configs
+    shells = [tuple(sh) for sh in wl.shells[:n_shells]]
+    sub = configs.Workload(wl.name, shells, wl.holes[:1], wl.gamma[:1], wl.dt[:1], wl.filter_params, wl.n_steps,
+                           wl.perturb)
+    d = domain.Domain([domain.Shell(*sh) for sh in shells], filter_params=wl.filter_params)
+    u0, ubg, H, dH = sub.initial_data(d.xyz(), d.offsets)
+    pool = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    gam = wl.gamma[:1]
+    d.rhs(u0, H, dH, ubg, gam)           # transform tables built before the first timing
+    runs = {}
+    for name, lim in (("one_thread", 1), ("all_threads", None)):
+        with threadpool_limits(limits=lim):
+            c0, t0 = time.process_time(), time.perf_counter()
+            for _ in range(n_rhs):
+                d.rhs(u0, H, dH, ubg, gam)
+            t, c = time.perf_counter() - t0, time.process_time() - c0
+        runs[name] = (d.P * n_rhs / t, t, c / t)
+    v1, t1, _ = runs["one_thread"]
+    va, ta, eff = runs["all_threads"]
+    where = f"shell{'s' if n_shells > 1 else ''} 1{'-%d' % n_shells if n_shells > 1 else ''} of {len(wl.shells)}"
+    return {"value": v1, "unit": "grid-point RHS evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_rhs} RHS evaluation{'s' if n_rhs > 1 else ''} of {where} of the {wl.name} workload "
+                      f"({d.P} points, N_r = {shells[0][1]}, L = {shells[0][2]}, boundary treatment included), "
+                      f"NumPy oracle on one thread, {t1:.1f} s",
+            "all_threads": {"value": va, "thread_pool": int(pool), "effective_cores": round(eff, 2),
+                            "seconds": round(ta, 2),
+                            "note": "same sample with NumPy's full thread pool; effective_cores = CPU time / wall "
+                                    "time (the oracle's transforms are mostly single-threaded einsum loops)"}}
 
 
 def adjoint_ratio(solver, u0_dev, wl, n_steps=200, k=20):
@@ -359,94 +379,214 @@ def warm_adjoint(solver, u):
     torch.cuda.synchronize()
 
 
-def large_measurement(steps, adj_steps, k):
-    """The 20-shell L = 31 domain: forward rate of one instance, and the
-    adjoint/forward ratio of a checkpointed gradient on a 4-instance batch."""
+def upload_workload(wl):
+    """Seeded inputs of a workload generated on the GPU, a solver with its
+    background and parameters set, and the initial state on the device."""
+    import torch
+    from paper_1804_09101_amd import ghmi
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    xyz = ghmi.grid_coords(wl.shells)
+    offs = np.concatenate([[0], np.cumsum([s[1] * 2 * (s[2] + 1) ** 2 for s in wl.shells])])
+    u0, ubg, H, dH = wl.initial_data(xyz, offs, device="cuda:0")
+    del xyz
+    s = ghmi.GHSolver(wl.shells, wl.n_inst, wl.filter_params)
+    s.set_background(dev(H), dev(dH), dev(ubg))
+    s.set_params(wl.gamma, wl.dt)
+    return s, dev(u0)
+
+
+def timed_steps(wl, solver, u0_dev, steps, warmup, profile):
+    """The measured run: warmup steps, then `steps` RK3 steps bracketed by
+    synchronisations with HIP events around the angular derivative GEMM only;
+    a separate run with events around every launch for the per-kernel split;
+    the same steps replayed from a captured graph."""
+    import torch
+    from paper_1804_09101_amd import costs, ghmi
+    u = u0_dev.clone()
+    solver.step(u, warmup)
+    torch.cuda.synchronize()
+    solver.set_timing(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.step(u, steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    stats = {k: solver.kernel_stats(k) for k in ghmi.KERNEL_KINDS}
+    solver.set_timing(False)
+    if not bool(torch.isfinite(u).all()):
+        raise RuntimeError("non-finite state after the timed steps")
+    n_split = max(1, min(steps, 10 if solver.P > 1e6 else 50))
+    ukern = u.clone()
+    solver.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.step(ukern, n_split)
+    torch.cuda.synchronize()
+    t_split = time.perf_counter() - t0
+    split = {k: solver.kernel_stats(k) for k in ghmi.KERNEL_KINDS}
+    solver.set_timing(False)
+    del ukern
+    solver.set_graph(True)
+    ug = u0_dev.clone()
+    solver.step(ug, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.step(ug, steps)
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
+    solver.set_graph(False)
+    del ug
+    P = solver.P
+    n_g, ms_g = stats["deriv_gemm"]
+    avg_s = ms_g / n_g / 1e3
+    flops = costs.angular_gemm_flops(wl.shells)
+    achieved = flops / avg_s / 1e12
+    one_launch = solver.query(14) < 0
+    return {
+        "value": P * 3 * steps / t,
+        "ms_per_step": t / steps * 1e3,
+        "roofline": {"kernel": "angular derivative GEMM (FP64 MFMA)", "bound": "mfma",
+                     "achieved": achieved, "peak": MI355X_FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / MI355X_FP64_PEAK_TFLOPS,
+                     "traffic": gemm_traffic(profile, solver.query(6), solver.query(4)) if one_launch else None,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_bytes": costs.angular_gemm_bytes(wl.shells),
+                     "flops_per_launch": flops, "avg_launch_us": avg_s * 1e6, "launches_timed": n_g},
+        "paper_model": dict(costs.domain_model(wl.shells), note="the paper's dense shell differentiator "
+                            "count for one derivative pass of 50 fields (unfused, minimum M and F)"),
+        "kernels": {k: {"launches": n, "avg_us": (ms / n * 1e3 if n else None),
+                        "share": ms / (t_split * 1e3)} for k, (n, ms) in split.items()},
+        "kernels_run": {"steps": n_split, "ms_per_step": t_split / n_split * 1e3,
+                        "note": "separate run with HIP events around every launch (the timed run records them "
+                                "around the angular derivative GEMM only)"},
+        "gemm_tiles": {"deriv": solver.query(0), "filter": solver.query(1), "deriv_tiles": solver.query(2),
+                       "deriv_order": solver.query(4), "filter_order": solver.query(5),
+                       "deriv_variant": solver.query(6), "filter_variant": solver.query(7),
+                       "deriv_tail_variant": solver.query(14), "filter_tail_variant": solver.query(15),
+                       "deriv_tail_k_chunks": solver.query(16)},
+        "graph_value": P * 3 * steps / t_graph,
+        "graph_ms_per_step": t_graph / steps * 1e3,
+    }
+
+
+def large_batch_measurement(steps, adj_steps, k):
+    """The 4-instance batch of the 20-shell domain: forward rate (dense and by
+    transforms) and the adjoint/forward ratio of a checkpointed gradient of the
+    final constraint norm."""
     import torch
     from paper_1804_09101_amd import autograd as gha
-    from paper_1804_09101_amd import configs, costs, ghmi
-    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
-    out = {}
-    for name, wl in (("single", configs.large_20shell()), ("batch4", configs.large_20shell_batch(4))):
-        log(f"large {name}: building inputs")
-        xyz = ghmi.grid_coords(wl.shells)
-        offs = np.concatenate([[0], np.cumsum([s[1] * 2 * (s[2] + 1) ** 2 for s in wl.shells])])
-        u0, ubg, H, dH = wl.initial_data(xyz, offs, device="cuda:0")
-        del xyz
-        s = ghmi.GHSolver(wl.shells, wl.n_inst, wl.filter_params)
-        s.set_background(dev(H), dev(dH), dev(ubg))
-        s.set_params(wl.gamma, wl.dt)
-        del H, dH, ubg
-        u = dev(u0)
-        s.step(u, 2)
-        torch.cuda.synchronize()
-        s.set_timing(True)
-        t0 = time.perf_counter()
-        s.step(u, steps)
-        torch.cuda.synchronize()
-        t = time.perf_counter() - t0
-        n_g, ms_g = s.kernel_stats("deriv_gemm")
-        s.set_timing(False)
-        flops = costs.angular_gemm_flops(wl.shells)
-        rec = {"points": s.P, "instances": wl.n_inst, "steps": steps, "ms_per_step": t / steps * 1e3,
-               "value": s.P * 3 * steps / t, "unit": "grid-point RHS evals/s",
-               "deriv_gemm_avg_us": ms_g / n_g * 1e3, "deriv_gemm_tflops": flops / (ms_g / n_g / 1e3) / 1e12,
-               "deriv_variant": s.query(6), "deriv_order": s.query(4)}
-        log(f"large {name}: {steps} steps in {t:.2f} s")
-        s.set_angular(2)
-        ut = dev(u0)
-        s.step(ut, 2)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s.step(ut, steps)
-        torch.cuda.synchronize()
-        tt = time.perf_counter() - t0
-        by_transform = bool(s.query(9))
-        s.set_angular(0)
-        del ut
-        rec["transform"] = {"ms_per_step": tt / steps * 1e3, "value": s.P * 3 * steps / tt,
-                            "method": "gh_set_angular 2", "derivatives_by_transform": by_transform}
-        log(f"large {name}: transform {steps} steps in {tt:.2f} s")
-        if name == "batch4":
-            warm_adjoint(s, u)
-            gamma = torch.tensor(wl.gamma, dtype=torch.float64, requires_grad=True)
-            ua = dev(u0).requires_grad_(True)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            un = gha.evolve(ua, gamma, s, wl.dt, adj_steps, checkpoint_every=k)
-            L = gha.constraint_norm(un, s).sum()
-            torch.cuda.synchronize()
-            t_f = time.perf_counter() - t0
-            t0 = time.perf_counter()
-            L.backward()
-            torch.cuda.synchronize()
-            t_b = time.perf_counter() - t0
-            log(f"large {name}: adjoint forward {t_f:.2f} s, backward {t_b:.2f} s")
-            rec["adjoint"] = {"steps": adj_steps, "checkpoint_every": k, "forward_ms": t_f * 1e3,
-                              "backward_ms": t_b * 1e3, "ratio": t_b / t_f,
-                              "grad_gamma_norm": float(gamma.grad.norm()), "grad_u0_norm": float(ua.grad.norm())}
-            del ua, un, L, gamma
-        out[name] = rec
-        del s, u, u0
-        torch.cuda.empty_cache()
+    from paper_1804_09101_amd import configs, costs
+    wl = configs.large_20shell_batch(4)
+    log("large batch4: building inputs")
+    s, u0 = upload_workload(wl)
+    u = u0.clone()
+    s.step(u, 2)
+    torch.cuda.synchronize()
+    s.set_timing(2)
+    t0 = time.perf_counter()
+    s.step(u, steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    n_g, ms_g = s.kernel_stats("deriv_gemm")
+    s.set_timing(False)
+    flops = costs.angular_gemm_flops(wl.shells)
+    rec = {"workload": "large_20shell_batch (4 instances)", "points": s.P, "instances": wl.n_inst, "steps": steps,
+           "ms_per_step": t / steps * 1e3, "value": s.P * 3 * steps / t, "unit": "grid-point RHS evals/s",
+           "deriv_gemm_avg_us": ms_g / n_g * 1e3, "deriv_gemm_tflops": flops / (ms_g / n_g / 1e3) / 1e12,
+           "deriv_variant": s.query(6), "deriv_order": s.query(4)}
+    log(f"large batch4: {steps} steps in {t:.2f} s")
+    s.set_angular(2)
+    ut = u0.clone()
+    s.step(ut, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(ut, steps)
+    torch.cuda.synchronize()
+    tt = time.perf_counter() - t0
+    rec["transform"] = {"ms_per_step": tt / steps * 1e3, "value": s.P * 3 * steps / tt,
+                        "method": "gh_set_angular 2", "derivatives_by_transform": bool(s.query(9))}
+    s.set_angular(0)
+    del ut, u
+    log(f"large batch4: transform {steps} steps in {tt:.2f} s")
+    warm_adjoint(s, u0)
+    gamma = torch.tensor(wl.gamma, dtype=torch.float64, requires_grad=True)
+    ua = u0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    un = gha.evolve(ua, gamma, s, wl.dt, adj_steps, checkpoint_every=k)
+    L = gha.constraint_norm(un, s).sum()
+    torch.cuda.synchronize()
+    t_f = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    L.backward()
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    log(f"large batch4: adjoint forward {t_f:.2f} s, backward {t_b:.2f} s")
+    rec["adjoint"] = {"steps": adj_steps, "checkpoint_every": k, "forward_ms": t_f * 1e3,
+                      "backward_ms": t_b * 1e3, "ratio": t_b / t_f,
+                      "grad_gamma_norm": float(gamma.grad.norm()), "grad_u0_norm": float(ua.grad.norm())}
+    del ua, un, L, gamma, s, u0
+    torch.cuda.empty_cache()
+    return rec
+
+
+def pulse_8shell_measurement(args):
+    """The 8-shell pulse workload and the measurements made on it."""
+    import torch
+    from paper_1804_09101_amd import configs
+    wl = configs.pulse_8shell()
+    solver, u0 = upload_workload(wl)
+    out = {"workload": "pulse_8shell", "shells": len(wl.shells), "n_r": 21, "L": 15, "angular_grid": "16x32",
+           "points": solver.P, "filter": "exp angular", "dt": float(wl.dt[0]), "steps": args.steps,
+           "unit": "grid-point RHS evals/s"}
+    out.update(timed_steps(wl, solver, u0, args.steps, args.warmup, PROFILE_PULSE))
+    log(f"pulse_8shell: {out['ms_per_step']:.3f} ms/step; graph {out['graph_ms_per_step']:.3f} ms/step")
+    out["rk3_physical_time_per_s"] = float(wl.dt[0]) * 1e3 / out["ms_per_step"]
+    if not args.no_transform:
+        out["transform"] = transform_measurement(solver, u0, args.steps)
+        log(f"pulse_8shell transform: {out['transform']['ms_per_step']:.3f} ms/step")
+    out["constraints"] = constraints_measurement(solver, u0)
+    log(f"constraints: {out['constraints']['norm_only']['ms_per_evaluation']:.3f} ms per evaluation (norm only), "
+        f"{out['constraints']['with_C']['ms_per_evaluation']:.3f} ms with the per-point array")
+    out["interface_state"] = interface_state_measurement(solver, u0, args.steps)
+    log(f"interface from state: {out['interface_state']['ms_per_step']:.3f} ms/step")
+    if not args.no_tensor_filter:
+        out["tensor_filter"] = tensor_filter_measurement(wl, min(args.steps, 50))
+        tfm = out["tensor_filter"]
+        log(f"tensor filter: {tfm['ms_per_application']:.3f} ms per application "
+            f"({tfm['ms_per_application_by_transforms']:.3f} by transforms), coupling "
+            f"{tfm['coupling']['avg_launch_us']:.1f} us ({tfm['coupling']['achieved']:.0f} GB/s), "
+            f"RK3 with it {tfm['rk3_ms_per_step']:.3f} ms/step")
+    if not args.no_dp5:
+        out["dp5"] = dp5_measurement(solver, u0, wl)
+        log(f"dp5: {out['dp5']['ms_per_attempt']:.3f} ms/attempt, {out['dp5']['accepted']} of "
+            f"{out['dp5']['attempts']} accepted, mean dt {out['dp5']['mean_accepted_dt']:.3e}")
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_ratio(solver, u0, wl)
+        log(f"adjoint ratio {out['adjoint']['ratio']:.2f}")
+    solver.close()
+    del u0
+    torch.cuda.empty_cache()
     return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-rhs", type=int, default=3, help="oracle RHS evaluations for cpu_baseline (0: skip)")
-    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward measurement")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-shells", type=int, default=1,
+                    help="shells of the 20-shell domain in the oracle's cpu_baseline sample (0: skip)")
+    ap.add_argument("--no-pulse", action="store_true", help="skip the 8-shell pulse workload and its measurements")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward measurements")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-hole batched comparison")
     ap.add_argument("--no-dp5", action="store_true", help="skip the adaptive Dormand-Prince measurement")
     ap.add_argument("--no-transform", action="store_true",
-                    help="skip the angular transform method (gh_set_angular 2) measurement")
+                    help="skip the angular transform method (gh_set_angular 2) measurements")
     ap.add_argument("--no-tensor-filter", action="store_true",
                     help="skip the tensor-coupled filter measurement")
-    ap.add_argument("--no-large", action="store_true",
-                    help="skip the 20-shell L = 31 domain (forward, and the adjoint of a 4-instance batch)")
+    ap.add_argument("--no-large-batch", action="store_true",
+                    help="skip the 4-instance batch of the 20-shell domain (forward and adjoint)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -457,7 +597,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1804_09101_amd import configs, costs, ghmi
+    from paper_1804_09101_amd import configs
 
     if args.calibrate_copy:
         n = 256 * 1024 * 1024 // 8
@@ -471,132 +611,56 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
-    wl = configs.pulse_8shell()
-    xyz = ghmi.grid_coords(wl.shells)
-    offs = np.concatenate([[0], np.cumsum([s[1] * 2 * (s[2] + 1) ** 2 for s in wl.shells])])
-    u0, ubg, H, dH = wl.initial_data(xyz, offs, device="cuda:0")
-    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
-    solver = ghmi.GHSolver(wl.shells, wl.n_inst, wl.filter_params)
-    solver.set_background(dev(H), dev(dH), dev(ubg))
-    solver.set_params(wl.gamma, wl.dt)
-    u = dev(u0)
 
-    solver.step(u, args.warmup)
-    torch.cuda.synchronize()
-    # timed region: HIP events around the angular derivative GEMM only (the
-    # roofline kernel); the per-kernel split comes from a separate run below
-    solver.set_timing(2)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    solver.step(u, args.steps)
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
-    stats = {k: solver.kernel_stats(k) for k in ghmi.KERNEL_KINDS}
-    solver.set_timing(False)
-    # per-kernel split: the same steps with events around every launch
-    n_split = max(1, min(args.steps, 50))
-    ukern = u.clone()
-    solver.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    solver.step(ukern, n_split)
-    torch.cuda.synchronize()
-    t_split = time.perf_counter() - t0
-    split = {k: solver.kernel_stats(k) for k in ghmi.KERNEL_KINDS}
-    solver.set_timing(False)
-    del ukern
-    if not bool(torch.isfinite(u).all()):
-        print(json.dumps({"error": "non-finite state after the timed steps"}))
+    wl = configs.large_20shell()
+    log("large_20shell: building inputs")
+    solver, u0 = upload_workload(wl)
+    try:
+        head = timed_steps(wl, solver, u0, args.steps, args.warmup, PROFILE_LARGE)
+    except RuntimeError as e:
+        print(json.dumps({"error": str(e)}))
         sys.exit(3)
-
+    log(f"large_20shell: timed {args.steps} steps: {head['ms_per_step']:.3f} ms/step; "
+        f"graph {head['graph_ms_per_step']:.3f} ms/step; derivative GEMM "
+        f"{head['roofline']['achieved']:.1f} TFLOP/s ({head['roofline']['frac']:.3f} of peak)")
     P = solver.P
-    value = P * 3 * args.steps / t
-    # the same steps from a captured HIP graph (timing off)
-    solver.set_graph(True)
-    ug = dev(u0)
-    solver.step(ug, 2)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    solver.step(ug, args.steps)
-    torch.cuda.synchronize()
-    t_graph = time.perf_counter() - t0
-    solver.set_graph(False)
-    n_g, ms_g = stats["deriv_gemm"]
-    avg_s = ms_g / n_g / 1e3
-    flops = costs.angular_gemm_flops(wl.shells)
-    achieved = flops / avg_s / 1e12
-    kernels = {k: {"launches": n, "avg_us": (ms / n * 1e3 if n else None),
-                   "share": ms / (t_split * 1e3)} for k, (n, ms) in split.items()}
     out = {
         "metric": "grid-point GH RHS evals/s (FP64, 1 GPU)",
-        "value": value,
+        "value": head.pop("value"),
         "unit": "grid-point RHS evals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": t / args.steps * 1e3,
+        "ms_per_step": head.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic (seeded Kerr-Schild hole + Gaussian pulse)",
-        "config": {"workload": "pulse_8shell", "shells": len(wl.shells), "n_r": 21, "L": 15,
-                   "angular_grid": "16x32", "points": P, "rhs_per_step": 3, "filter": "exp angular",
-                   "dt": float(wl.dt[0]), "parallelism": "single GPU"},
-        "roofline": {"kernel": "angular derivative GEMM (FP64 MFMA)", "bound": "mfma",
-                     "achieved": achieved, "peak": MI355X_FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / MI355X_FP64_PEAK_TFLOPS,
-                     "traffic": gemm_traffic(solver.query(6), solver.query(4)) if solver.query(14) < 0 else None,
-                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "algorithmic_bytes": costs.angular_gemm_bytes(wl.shells),
-                     "flops_per_launch": flops, "avg_launch_us": avg_s * 1e6},
-        "paper_model": dict(costs.domain_model(wl.shells), note="the paper's dense shell differentiator "
-                            "count for one derivative pass of 50 fields (unfused, minimum M and F)"),
-        "kernels": kernels,
-        "kernels_run": {"steps": n_split, "ms_per_step": t_split / n_split * 1e3,
-                        "note": "separate run with HIP events around every launch (the timed run records them "
-                                "around the angular derivative GEMM only)"},
-        "gemm_tiles": {"deriv": solver.query(0), "filter": solver.query(1), "deriv_tiles": solver.query(2),
-                       "deriv_order": solver.query(4), "filter_order": solver.query(5),
-                       "deriv_variant": solver.query(6), "filter_variant": solver.query(7),
-                       "deriv_tail_variant": solver.query(14), "filter_tail_variant": solver.query(15),
-                       "deriv_tail_k_chunks": solver.query(16)},
-        "graph_value": P * 3 * args.steps / t_graph,
+        "data": "synthetic (seeded Kerr-Schild hole, chi = 0.9, with a smooth 1e-6 perturbation of all fields)",
+        "config": {"workload": "large_20shell", "shells": len(wl.shells), "n_r": 33, "L": 31,
+                   "angular_grid": "32x64", "points": P, "rhs_per_step": 3, "filter": "none",
+                   "angular_method": "dense operators, grouped FP64-MFMA GEMM", "dt": float(wl.dt[0]),
+                   "parallelism": "single GPU"},
+        "roofline": head.pop("roofline"),
     }
-    log(f"timed {args.steps} steps: {t * 1e3 / args.steps:.3f} ms/step; graph {t_graph * 1e3 / args.steps:.3f} ms/step")
-    out["rk3_physical_time_per_s"] = float(wl.dt[0]) * args.steps / t
+    out.update(head)
     if not args.no_transform:
-        out["transform"] = transform_measurement(solver, dev(u0), args.steps)
-        log(f"transform: {out['transform']['ms_per_step']:.3f} ms/step, graph "
-            f"{P * 3 * args.steps / out['transform']['graph_value'] / args.steps * 1e3:.3f} ms/step")
-    out["constraints"] = constraints_measurement(solver, dev(u0))
-    log(f"constraints: {out['constraints']['norm_only']['ms_per_evaluation']:.3f} ms per evaluation (norm only), "
-        f"{out['constraints']['with_C']['ms_per_evaluation']:.3f} ms with the per-point array")
-    out["interface_state"] = interface_state_measurement(solver, dev(u0), args.steps)
-    log(f"interface from state: {out['interface_state']['ms_per_step']:.3f} ms/step")
-    if not args.no_tensor_filter:
-        out["tensor_filter"] = tensor_filter_measurement(wl, min(args.steps, 50))
-        tfm = out["tensor_filter"]
-        log(f"tensor filter: {tfm['ms_per_application']:.3f} ms per application "
-            f"({tfm['ms_per_application_by_transforms']:.3f} by transforms), coupling "
-            f"{tfm['coupling']['avg_launch_us']:.1f} us ({tfm['coupling']['achieved']:.0f} GB/s), "
-            f"RK3 with it {tfm['rk3_ms_per_step']:.3f} ms/step")
-    if not args.no_dp5:
-        out["dp5"] = dp5_measurement(solver, dev(u0), wl)
-        log(f"dp5: {out['dp5']['ms_per_attempt']:.3f} ms/attempt, {out['dp5']['accepted']} of "
-            f"{out['dp5']['attempts']} accepted, mean dt {out['dp5']['mean_accepted_dt']:.3e}")
-    if not args.no_adjoint:
-        out["adjoint"] = adjoint_ratio(solver, dev(u0), wl)
-        log(f"adjoint ratio {out['adjoint']['ratio']:.2f}")
+        out["transform"] = transform_measurement(solver, u0, args.steps)
+        log(f"large_20shell transform: {out['transform']['ms_per_step']:.3f} ms/step")
+    solver.close()
+    del solver, u0
+    torch.cuda.empty_cache()
+    if not args.no_large_batch:
+        out["large_batch4"] = large_batch_measurement(steps=10, adj_steps=10 if args.no_adjoint else 20, k=5)
+    if not args.no_pulse:
+        out["pulse_8shell"] = pulse_8shell_measurement(args)
     if not args.no_batched:
-        out["batched"] = batched_comparison(max(5, args.steps // 10))
+        out["batched"] = batched_comparison(max(5, args.steps // 2))
         log(f"batched speedup eager {out['batched']['eager']['speedup']:.2f}, "
             f"graph {out['batched']['graph']['speedup']:.2f}")
-    if not args.no_large:
-        out["large"] = large_measurement(steps=10, adj_steps=10, k=5)
-    if args.cpu_rhs > 0:
+    if args.cpu_shells > 0:
         log("oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_rhs)
+        out["cpu_baseline"] = cpu_baseline(wl, n_shells=args.cpu_shells, n_rhs=1)
     print(json.dumps(out))
 
 

@@ -356,7 +356,11 @@ int gh_grid_coords(int n_shells, const gh_shell* shells, double* xyz);
  *  kind 2: d/dphi on the sphere, S x S (n = L);
  *  kind 3: angular filter, S x S (n = L, params = {eta_c, alpha, order});
  *  kind 4: Clenshaw-Curtis weights on [-1,1], n (n = n_r);
- *  kind 5: Gauss-Legendre nodes then weights, 2(L+1) (n = L). */
+ *  kind 5: Gauss-Legendre nodes then weights, 2(L+1) (n = L);
+ *  kind 6: the derivative GEMM's B operand (Theta^T | Phi^T), S x 2S (n = L);
+ *  kind 7: the filter GEMM's B operand F^T, S x S (n = L, params as kind 3).
+ * GH_ERR_ARG for an unknown kind, n out of range (L above 63) or missing
+ * params. */
 int gh_host_operator(int kind, int n, const double* params, double* out);
 
 #ifdef __cplusplus

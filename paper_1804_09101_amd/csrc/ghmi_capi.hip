@@ -1131,32 +1131,28 @@ int gh_set_domain(gh_ctx* c, int n_inst, int n_shells, const gh_shell* shells, i
   for (auto& kv : ang_off) {
     int L = kv.first, S = 2 * (L + 1) * (L + 1);
     std::vector<double> none;
-    auto Th = ghsetup::sphere_operator(L, 0, none);
-    auto Ph = ghsetup::sphere_operator(L, 1, none);
+    // B operand (Theta^T | Phi^T) of the derivative GEMM, written transposed in place
     std::vector<double> Bop(size_t(S) * 2 * S);
-    for (int a = 0; a < S; ++a)
-      for (int j = 0; j < S; ++j) {
-        Bop[size_t(a) * 2 * S + j] = Th[size_t(j) * S + a];
-        Bop[size_t(a) * 2 * S + S + j] = Ph[size_t(j) * S + a];
-      }
+    ghsetup::sphere_operator_into(L, 0, none, true, Bop.data(), size_t(2) * S);
+    ghsetup::sphere_operator_into(L, 1, none, true, Bop.data() + S, size_t(2) * S);
     double* d = nullptr;
     if ((rc = upload(c, &d, Bop))) return rc;
     c->d_angop[L] = d;
-    std::vector<double> BopT(size_t(2) * S * S);
-    std::copy(Th.begin(), Th.end(), BopT.begin());
-    std::copy(Ph.begin(), Ph.end(), BopT.begin() + size_t(S) * S);
+    // (Theta ; Phi), the B operand of the transposed derivative
+    std::vector<double>& BopT = Bop;
+    ghsetup::sphere_operator_into(L, 0, none, false, BopT.data(), size_t(S));
+    ghsetup::sphere_operator_into(L, 1, none, false, BopT.data() + size_t(S) * S, size_t(S));
     double* dT = nullptr;
     if ((rc = upload(c, &dT, BopT))) return rc;
     c->d_angopT[L] = dT;
     if (filter_kind == 1) {
       auto sig = ghsetup::exp_filter_sigma(L, c->filt[0], c->filt[1], c->filt[2]);
-      auto F = ghsetup::sphere_operator(L, 2, sig);
-      std::vector<double> FT(size_t(S) * S);
-      for (int a = 0; a < S; ++a)
-        for (int j = 0; j < S; ++j) FT[size_t(a) * S + j] = F[size_t(j) * S + a];
+      std::vector<double> F(size_t(S) * S);
+      ghsetup::sphere_operator_into(L, 2, sig, true, F.data(), size_t(S));
       double* f = nullptr;
-      if ((rc = upload(c, &f, FT))) return rc;
+      if ((rc = upload(c, &f, F))) return rc;
       c->d_filtop[L] = f;
+      ghsetup::sphere_operator_into(L, 2, sig, false, F.data(), size_t(S));
       double* fT = nullptr;
       if ((rc = upload(c, &fT, F))) return rc;
       c->d_filtopT[L] = fT;
@@ -1812,6 +1808,7 @@ int gh_grid_coords(int n_shells, const gh_shell* shells, double* xyz) {
 
 int gh_host_operator(int kind, int n, const double* params, double* out) {
   if (!out) return GH_ERR_ARG;
+  if (kind >= 1 && kind <= 7 && kind != 4 && kind != 5 && n > 63) return GH_ERR_ARG;
   std::vector<double> v;
   switch (kind) {
     case 0: if (n < 2) return GH_ERR_ARG; v = ghsetup::cgl_diff_matrix(n); break;
@@ -1822,6 +1819,24 @@ int gh_host_operator(int kind, int n, const double* params, double* out) {
       v = ghsetup::sphere_operator(n, 2, ghsetup::exp_filter_sigma(n, params[0], params[1], params[2]));
       break;
     case 4: if (n < 2) return GH_ERR_ARG; v = ghsetup::clenshaw_curtis(n); break;
+    case 6: {
+      // the derivative GEMM's B operand (Theta^T | Phi^T), S x 2S, as uploaded
+      if (n < 1) return GH_ERR_ARG;
+      const size_t S = size_t(2) * (n + 1) * (n + 1);
+      v.assign(S * 2 * S, 0.0);
+      ghsetup::sphere_operator_into(n, 0, {}, true, v.data(), 2 * S);
+      ghsetup::sphere_operator_into(n, 1, {}, true, v.data() + S, 2 * S);
+      break;
+    }
+    case 7: {
+      // the filter GEMM's B operand F^T, S x S, as uploaded
+      if (n < 1 || !params) return GH_ERR_ARG;
+      const size_t S = size_t(2) * (n + 1) * (n + 1);
+      v.assign(S * S, 0.0);
+      ghsetup::sphere_operator_into(n, 2, ghsetup::exp_filter_sigma(n, params[0], params[1], params[2]), true,
+                                    v.data(), S);
+      break;
+    }
     case 5: {
       if (n < 0) return GH_ERR_ARG;
       std::vector<double> x, w;

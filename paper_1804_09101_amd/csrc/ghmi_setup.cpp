@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <thread>
 
 namespace ghsetup {
 
@@ -209,8 +210,12 @@ std::vector<double> fourier_table(int L) {
   return T;
 }
 
-std::vector<double> sphere_operator(int L, int which, const std::vector<double>& sigma) {
-  // assembled from the per-order factors: cost S^2 (L+1) instead of S^2 (L+1)^2
+void sphere_operator_into(int L, int which, const std::vector<double>& sigma, bool transposed, double* out,
+                          size_t ld) {
+  // assembled from the per-order factors.  An entry depends on the azimuths
+  // only through d = k - k' (mod nph), so the order sum is formed once per
+  // (theta row, theta column, d), nth^2 nph (L+1) multiply-adds, and the S^2
+  // entries are then copies; rows are filled by several host threads.
   const int nth = L + 1, nph = 2 * (L + 1), S = nth * nph, n = L + 1;
   const std::vector<double> K = sphere_factors(L, which, sigma);
   // azimuthal factors for every difference d = k - k' (mod nph)
@@ -220,18 +225,40 @@ std::vector<double> sphere_operator(int L, int which, const std::vector<double>&
       const double ang = 2.0 * kPi * double((m * d) % nph) / nph;
       trig[size_t(m) * nph + d] = (which == 1) ? std::sin(ang) : std::cos(ang);
     }
-  std::vector<double> M(size_t(S) * S, 0.0);
+  // V[ij][ia][d]: the entry of output row (ij, k) and input column (ia, k - d)
+  std::vector<double> V(size_t(nth) * nth * nph);
   for (int ij = 0; ij < nth; ++ij)
-    for (int kj = 0; kj < nph; ++kj) {
-      double* row = &M[size_t(ij * nph + kj) * S];
-      for (int ia = 0; ia < nth; ++ia)
-        for (int ka = 0; ka < nph; ++ka) {
-          const int d = ((kj - ka) % nph + nph) % nph;
-          double acc = 0.0;
-          for (int m = 0; m <= L; ++m) acc += K[(size_t(m) * nth + ij) * nth + ia] * trig[size_t(m) * nph + d];
-          row[ia * nph + ka] = acc;
+    for (int ia = 0; ia < nth; ++ia)
+      for (int d = 0; d < nph; ++d) {
+        double acc = 0.0;
+        for (int m = 0; m <= L; ++m) acc += K[(size_t(m) * nth + ij) * nth + ia] * trig[size_t(m) * nph + d];
+        V[(size_t(ij) * nth + ia) * nph + d] = acc;
+      }
+  auto fill = [&](int r0, int r1) {
+    for (int r = r0; r < r1; ++r) {
+      const int ir = r / nph, kr = r - ir * nph;
+      double* row = out + size_t(r) * ld;
+      for (int ic = 0; ic < nth; ++ic) {
+        if (!transposed) {          // row (ir, kr) = output, column (ic, kc) = input
+          const double* v = &V[(size_t(ir) * nth + ic) * nph];
+          for (int kc = 0; kc < nph; ++kc) row[ic * nph + kc] = v[(kr - kc + nph) % nph];
+        } else {                    // row (ir, kr) = input, column (ic, kc) = output
+          const double* v = &V[(size_t(ic) * nth + ir) * nph];
+          for (int kc = 0; kc < nph; ++kc) row[ic * nph + kc] = v[(kc - kr + nph) % nph];
         }
+      }
     }
+  };
+  const int nt = S >= 2048 ? std::max(1, std::min(16, int(std::thread::hardware_concurrency()))) : 1;
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nt; ++t) pool.emplace_back(fill, int(size_t(S) * t / nt), int(size_t(S) * (t + 1) / nt));
+  for (auto& th : pool) th.join();
+}
+
+std::vector<double> sphere_operator(int L, int which, const std::vector<double>& sigma) {
+  const size_t S = size_t(2) * (L + 1) * (L + 1);
+  std::vector<double> M(S * S);
+  sphere_operator_into(L, which, sigma, false, M.data(), S);
   return M;
 }
 

@@ -26,6 +26,10 @@ void legendre_normalised(int L, double x, std::vector<double>& P, std::vector<do
 // Dense S x S operators on one sphere, row-major (out_j = sum_a M[j*S+a] u_a):
 //   which 0: d/dtheta, 1: d/dphi, 2: filter with factors sigma_l (sigma has L+1 entries).
 std::vector<double> sphere_operator(int L, int which, const std::vector<double>& sigma);
+// The same operator (transposed = false) or its transpose written into out,
+// row r at out + r * ld (S rows of S values), without forming it elsewhere.
+void sphere_operator_into(int L, int which, const std::vector<double>& sigma, bool transposed, double* out,
+                          size_t ld);
 
 // The same operators factorised by azimuthal order m (n = L+1):
 //   M u (i, k) = sum_m sum_i' K_m[i][i'] (cos(m phi_k) A_m(i') + sin(m phi_k) B_m(i'))   (which 0, 2)

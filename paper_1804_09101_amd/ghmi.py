@@ -131,9 +131,12 @@ def host_operator(kind, n, params=None):
     lib = load_library()
     if kind == 0:
         shape = (n, n)
-    elif kind in (1, 2, 3):
+    elif kind in (1, 2, 3, 7):
         S = 2 * (n + 1) ** 2
         shape = (S, S)
+    elif kind == 6:
+        S = 2 * (n + 1) ** 2
+        shape = (S, 2 * S)
     elif kind == 4:
         shape = (n,)
     elif kind == 5:

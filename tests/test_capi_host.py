@@ -63,6 +63,18 @@ def test_angular_operators_match_traced_transforms(lib, L):
     assert np.max(np.abs(ghmi.host_operator(3, L, par) - Fo)) < 1e-13 * (L + 1)
 
 
+@pytest.mark.parametrize("L", [1, 4, 15, 31])
+def test_gemm_operands_are_the_transposed_operators(lib, L):
+    """The B operands uploaded for the derivative and filter GEMMs are written
+    transposed in place; they must equal the transposes of the operators
+    (bitwise: the same sums, only stored elsewhere)."""
+    Th, Ph = ghmi.host_operator(1, L), ghmi.host_operator(2, L)
+    B = ghmi.host_operator(6, L)
+    assert np.array_equal(B, np.hstack([Th.T, Ph.T]))
+    par = (2.0 / 3.0, 36.0, 8.0)
+    assert np.array_equal(ghmi.host_operator(7, L, par), ghmi.host_operator(3, L, par).T)
+
+
 @pytest.mark.parametrize("n", [2, 3, 6, 11, 33])
 def test_quadrature_matches_oracle(lib, n):
     assert np.max(np.abs(ghmi.host_operator(4, n) - grid.clenshaw_curtis_weights(n))) < 1e-14
@@ -84,6 +96,8 @@ def test_host_calls_reject_bad_arguments(lib):
         ghmi.host_operator(0, 1)
     with pytest.raises(ValueError):
         ghmi.host_operator(9, 3)
+    with pytest.raises(ghmi.GHError):
+        ghmi.host_operator(1, 64)
 
 
 def _oracle_coupling(L, kind, params):

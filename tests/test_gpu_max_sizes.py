@@ -14,8 +14,6 @@ So the RHS is compared at 1e-14 kappa (about 45 ulps of it), five steps at
 n_r = 256 at the sum of those errors times dt plus the filter's roundoff, and
 the filter, a product with entries of size 1, at 1e-12 of the state."""
 
-import os
-
 import numpy as np
 import pytest
 
@@ -41,21 +39,17 @@ def _rhs_error(c, label, ref, scale):
     return diff / scale
 
 
-# Alone these stages take about 70 s (the L = 63 context builds its 8192-point
-# operators on one host thread); created after the rest of the GPU suite in the
-# same process that context has taken minutes, so they run when
-# GHMI_TEST_MAX_DEGREE=1 is set.
-needs_max_degree = pytest.mark.skipif(os.environ.get("GHMI_TEST_MAX_DEGREE") != "1",
-                                      reason="L = 63 stages run with GHMI_TEST_MAX_DEGREE=1 (slow context setup)")
-
-
 @pytest.fixture(scope="module")
 def deg63():
     """One shell of the largest degree: the library context (host operators of
     8192 x 16384 built and tuned) and the oracle domain; the oracle's RHS and
     rounding scale are added by the first test that needs them."""
+    import time
+    t0 = time.perf_counter()
     wl = _wl("L63", [(0, 3, 63, 1.8, 2.2)], [(1.0, 0.3, (0.2, 0.3, 0.4))], dt=[1e-4], filt=configs.FILTER_DEFAULT)
-    return {"c": Case(wl, pert_amp=1e-3, seed=21)}
+    c = Case(wl, pert_amp=1e-3, seed=21)
+    print(f"  L = 63 context, oracle domain and inputs ready in {time.perf_counter() - t0:.1f} s", flush=True)
+    return {"c": c}
 
 
 def _oracle63(st, what):
@@ -72,20 +66,17 @@ def _oracle63(st, what):
     return st[what]
 
 
-@needs_max_degree
 def test_largest_degree_context(deg63):
     c = deg63["c"]
     assert c.s.P == 3 * 8192 and c.s.query(8) == 0
 
 
-@needs_max_degree
 @pytest.mark.parametrize("what", ["ref", "kappa", "fref"])
 def test_largest_degree_oracle(deg63, what):
     v = np.asarray(_oracle63(deg63, what))
     assert np.all(np.isfinite(v)) and np.max(np.abs(v)) > 0
 
 
-@needs_max_degree
 def test_largest_degree_dense(deg63):
     c = deg63["c"]
     ref, kappa, fref = (_oracle63(deg63, w) for w in ("ref", "kappa", "fref"))
@@ -96,7 +87,6 @@ def test_largest_degree_dense(deg63):
     assert ef < 1e-12
 
 
-@needs_max_degree
 def test_largest_degree_by_transforms(deg63):
     c = deg63["c"]
     ref, kappa, fref = (_oracle63(deg63, w) for w in ("ref", "kappa", "fref"))

@@ -157,7 +157,9 @@ def test_constraints_parity():
     assert abs(norm[0] - nref[0]) < 1e-11 * nref[0]
 
 
-def test_pulse_8shell_full_size_rhs_and_step():
+def test_pulse_8shell_full_size_rhs():
+    """The full-size RHS; the full-size evolution is checked over ten steps in
+    test_gpu_long_parity.py."""
     wl = configs.pulse_8shell()
     c = Case(wl)
     u = dev(c.u0)
@@ -166,16 +168,6 @@ def test_pulse_8shell_full_size_rhs_and_step():
     err = np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), c.term_scale(c.u0))
     print(f"  full-size rhs rel err {err:.3e}", flush=True)
     assert err < 1e-12
-    c.s.step(u, 1)
-    got = u.cpu().numpy()
-    want = c.d.rk3_step(c.u0, c.H, c.dH, c.ubg, wl.gamma, wl.dt)
-    # one step changes the state by ~5e-7 while the filter acts on O(1) data, so
-    # the error is judged against the state (roundoff ~1e-14); the strict
-    # error/change bar is applied to the multi-step runs above
-    e_state = np.max(np.abs(got - want)) / np.max(np.abs(want))
-    e_change = np.max(np.abs(got - want)) / np.max(np.abs(want - c.u0))
-    print(f"  one filtered step: err/state {e_state:.3e}, err/change {e_change:.3e}", flush=True)
-    assert e_state < 1e-12 and e_change < 1e-6
 
 
 def test_error_paths():
