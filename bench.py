@@ -379,6 +379,34 @@ def warm_adjoint(solver, u):
     torch.cuda.synchronize()
 
 
+def calibration():
+    """What this GPU sustains next to its published peaks: back-to-back FP64
+    MFMAs with no memory traffic (gh_probe_mfma_f64), and a 1 GiB device copy
+    (read + write bytes over the copy time, median of 5)."""
+    import torch
+    from paper_1804_09101_amd import ghmi
+    probe = max(ghmi.probe_mfma_f64(0, 20000) for _ in range(3))
+    n = (1 << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    times = []
+    for _ in range(5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b) / 1e3)
+    del src, dst
+    torch.cuda.empty_cache()
+    t = sorted(times)[2]
+    return {"mfma_f64_probe_tflops": probe, "mfma_f64_peak_tflops": MI355X_FP64_PEAK_TFLOPS,
+            "copy_gb_s": 2 * n * 8 / t / 1e9, "hbm_peak_gb_s": MI355X_HBM_PEAK_GBS,
+            "note": "probe: one launch of v_mfma_f64_16x16x4_f64 on 8 independent accumulators per wave, "
+                    "32 waves per CU; copy: torch copy_ of 1 GiB, bytes read + written"}
+
+
 def upload_workload(wl):
     """Seeded inputs of a workload generated on the GPU, a solver with its
     background and parameters set, and the initial state on the device."""
@@ -612,6 +640,9 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
 
+    calib = calibration()
+    log(f"calibration: FP64 MFMA probe {calib['mfma_f64_probe_tflops']:.1f} TFLOP/s, "
+        f"device copy {calib['copy_gb_s']:.0f} GB/s")
     wl = configs.large_20shell()
     log("large_20shell: building inputs")
     solver, u0 = upload_workload(wl)
@@ -643,6 +674,8 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": head.pop("roofline"),
     }
+    out["roofline"]["frac_of_probe"] = out["roofline"]["achieved"] / calib["mfma_f64_probe_tflops"]
+    out["calibration"] = calib
     out.update(head)
     if not args.no_transform:
         out["transform"] = transform_measurement(solver, u0, args.steps)

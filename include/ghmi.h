@@ -203,6 +203,21 @@ int gh_set_graph(gh_ctx* ctx, int enable);
  * weight (Clenshaw-Curtis x r^2 (r_out-r_in)/2 x Gauss-Legendre x 2pi/N_phi). */
 int gh_constraints(gh_ctx* ctx, const double* u, double* C, double* norm);
 
+/* gh_constraints for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and the same results (bitwise), with the per-block partial sums of
+ * the norm kept in a file-scope device array of GH_STATIC_SCRATCH_DOUBLES
+ * doubles (8 MiB) instead of the context's work space.  The call itself
+ * allocates nothing: no hipMalloc, hipFree or event (kernel timing is not
+ * recorded for it); the derivative work space is the context's, allocated by
+ * gh_set_domain.  Limit: at most GH_STATIC_SCRATCH_DOUBLES blocks of 256
+ * points (domains up to 268 435 456 points), else GH_ERR_ARG.  The array is
+ * shared by every context on the same GPU and keeps the last call's partial
+ * sums: calls that overlap on one GPU (two streams, two host threads) race,
+ * so callers must order them. */
+#define GH_STATIC_SCRATCH_DOUBLES (1 << 20)
+int gh_constraints_static(gh_ctx* ctx, const double* u, double* C, double* norm);
+
 /* ---- adjoint (reverse mode) ---------------------------------------------
  * The paper has no adjoint; these are the transposes of the linearised
  * operations above, for gradients of a loss of the final state with respect
@@ -340,6 +355,14 @@ int gh_filter(gh_ctx* ctx, const double* u, double* out);
  * least the count).  GH_ERR_ARG for L outside 1..63 or invalid params. */
 int gh_tensor_filter_matrix(int L, int kind, const double* params, int transpose, long long* nnz,
                             long long* row_ptr, int* col, double* val);
+
+/* Measured ceiling of the FP64 matrix cores of device `device`: one launch
+ * of back-to-back v_mfma_f64_16x16x4_f64 (eight independent accumulators per
+ * wave, 32 waves per compute unit, `iters` iterations, no memory traffic in
+ * the loop) timed with HIP events after a warm-up launch; *tflops receives the
+ * rate.  Allocates and frees its own small output buffer and stream.  A
+ * measurement aid beside the published peak, not part of the evolution. */
+int gh_probe_mfma_f64(int device, int iters, double* tflops);
 
 /* Message of the last error on this context (never NULL). */
 const char* gh_last_error(const gh_ctx* ctx);

@@ -17,7 +17,30 @@
 #include "ghmi_setup.h"
 #include "ghmi_tensor_filter.h"
 
+#include <mutex>
+
+// Device scratch of gh_constraints_static: one array per GPU, held until the
+// process ends.  Host code never uses this name as an address; it uses the
+// per-device pointer that hipGetSymbolAddress returns (scratch_ptr below).
+static __device__ __align__(256) double scratch[GH_STATIC_SCRATCH_DOUBLES];
+
 namespace {
+
+// Device address of `scratch` on each GPU, looked up once per device (with that
+// device current) by gh_create.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+int lookup_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return GH_ERR_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch_ptr[device]) return GH_OK;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GH_ERR_DEVICE;
+  g_scratch_ptr[device] = static_cast<double*>(p);
+  return GH_OK;
+}
 
 // The GEMM work of one operation over the whole domain: groups of consecutive
 // shells sharing an angular operator, cut into tiles of one tile shape.
@@ -736,6 +759,7 @@ int gh_create(gh_ctx** out, int device, void* hip_stream) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return GH_ERR_DEVICE;
   if (hipSetDevice(device) != hipSuccess) return GH_ERR_DEVICE;
+  if (lookup_scratch(device) != GH_OK) return GH_ERR_DEVICE;
   gh_ctx* c = new gh_ctx();
   c->device = device;
   int ncu = 0;
@@ -1506,6 +1530,30 @@ int gh_constraints(gh_ctx* c, const double* u, double* C, double* norm) {
   HIPCHK(c, ghk::constraints(c->d_sh, c->d_blk, c->n_blk, c->d_angtab, c->d_radtab, u, c->d_dR, c->d_dA, c->d_H,
                              C, c->d_partial, c->stream));
   if (norm) HIPCHK(c, ghk::reduce_norm(c->d_inst_range, c->n_inst, c->d_partial, c->d_wsum, norm, c->stream));
+  return GH_OK;
+}
+
+int gh_constraints_static(gh_ctx* c, const double* u, double* C, double* norm) {
+  if (!c) return GH_ERR_ARG;
+  if (!c->have_domain) return fail(c, GH_ERR_ORDER, "gh_set_domain has not been called");
+  if (!c->have_bg) return fail(c, GH_ERR_ORDER, "gh_set_background has not been called");
+  if (!u) return fail(c, GH_ERR_ARG, "u must be a device pointer");
+  if (c->n_blk > GH_STATIC_SCRATCH_DOUBLES)
+    return fail(c, GH_ERR_ARG, "the domain has " + std::to_string(c->n_blk) + " point blocks of 256; the static "
+                "scratch holds the partial sums of at most " + std::to_string(GH_STATIC_SCRATCH_DOUBLES));
+  double* part = (c->device >= 0 && c->device < kMaxDevices) ? g_scratch_ptr[c->device] : nullptr;
+  if (!part) return fail(c, GH_ERR_DEVICE, "no scratch address for this device");
+  HIPCHK(c, hipSetDevice(c->device));
+  // kernel timing would create events; none are created here
+  const bool timing = c->timing;
+  c->timing = false;
+  int rc = queue_derivs(c, u);
+  c->timing = timing;
+  if (rc) return rc;
+  // every block writes its own partial sum, so nothing needs clearing
+  HIPCHK(c, ghk::constraints(c->d_sh, c->d_blk, c->n_blk, c->d_angtab, c->d_radtab, u, c->d_dR, c->d_dA, c->d_H,
+                             C, part, c->stream));
+  if (norm) HIPCHK(c, ghk::reduce_norm(c->d_inst_range, c->n_inst, part, c->d_wsum, norm, c->stream));
   return GH_OK;
 }
 

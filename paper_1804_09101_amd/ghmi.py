@@ -27,6 +27,7 @@ EXPORTS = [
     "gh_query", "gh_rhs_vjp", "gh_step_vjp", "gh_constraints_vjp",
     "gh_set_graph", "gh_step_stages", "gh_step_vjp_stages", "gh_step_dp5", "gh_set_angular",
     "gh_filter", "gh_tensor_filter_matrix", "gh_set_interface", "gh_set_gemm_variant",
+    "gh_constraints_static", "gh_probe_mfma_f64",
 ]
 
 NUM_GEMM_VARIANTS = 13
@@ -74,6 +75,8 @@ def load_library(path=LIB_PATH):
         "gh_rhs": (i, [vp, vp, vp]),
         "gh_step": (i, [vp, vp, i]),
         "gh_constraints": (i, [vp, vp, vp, vp]),
+        "gh_constraints_static": (i, [vp, vp, vp, vp]),
+        "gh_probe_mfma_f64": (i, [i, i, pd]),
         "gh_last_error": (ctypes.c_char_p, [vp]),
         "gh_grid_coords": (i, [i, psh, pd]),
         "gh_host_operator": (i, [i, i, pd, pd]),
@@ -149,6 +152,16 @@ def host_operator(kind, n, params=None):
     if rc:
         raise GHError(rc, "gh_host_operator")
     return out
+
+
+def probe_mfma_f64(device=0, iters=20000):
+    """Sustained FP64 MFMA rate of the device in TFLOP/s (gh_probe_mfma_f64)."""
+    lib = load_library()
+    out = ctypes.c_double(0.0)
+    rc = lib.gh_probe_mfma_f64(int(device), int(iters), ctypes.byref(out))
+    if rc:
+        raise GHError(rc, "gh_probe_mfma_f64")
+    return out.value
 
 
 def tensor_filter_matrix(L, kind, params, transpose=False):
@@ -263,6 +276,15 @@ class GHSolver:
         self._check(self.lib.gh_constraints(self.h, self._dev(u, 50, "u"),
                                             self._dev(C, 64, "C") if want_C else None,
                                             ctypes.c_void_p(norm.data_ptr())))
+        return C, norm
+
+    def constraints_static(self, u, C=None, norm=None):
+        """gh_constraints_static: the caller supplies the outputs (C [64 P] or
+        None, norm [n_inst] or None); nothing is allocated by the call."""
+        self._sync_stream()
+        self._check(self.lib.gh_constraints_static(
+            self.h, self._dev(u, 50, "u"), self._dev(C, 64, "C") if C is not None else None,
+            ctypes.c_void_p(norm.data_ptr()) if norm is not None else None))
         return C, norm
 
     def set_graph(self, enable=True):
