@@ -31,13 +31,17 @@ class Shell:
 class Domain:
     """Shells of one or more independent instances (black holes)."""
 
-    def __init__(self, shells, filter_params=None, filter_kind=1, interface_from_state=False):
+    def __init__(self, shells, filter_params=None, filter_kind=1, interface_from_state=False,
+                 outer_bc="dirichlet"):
         """filter_kind (with filter_params): 1 angular exponential filter of every
         component, (eta_c, alpha, order); 2 tensor-coupled ExpCheb filter,
         (eta_c, alpha, order); 3 tensor-coupled Heaviside filter, (eta_c,).
         interface_from_state: the characteristic projection and upwind choice
         at interfaces come from the state whose d_t u is being computed instead
-        of the background u_bg."""
+        of the background u_bg.
+        outer_bc: "dirichlet" (d_t u = 0 at the outer boundary) or
+        "constraint_preserving" (gh.outer_constraint_preserving, with the
+        normal and speeds from the state)."""
         self.shells = list(shells)
         self.grids = [_grid.ShellGrid(s.n_r, s.L, s.r_in, s.r_out) for s in self.shells]
         self.spheres = {}
@@ -51,6 +55,9 @@ class Domain:
         self.filter_params = filter_params
         self.filter_kind = filter_kind if filter_params is not None else 0
         self.interface_from_state = bool(interface_from_state)
+        if outer_bc not in ("dirichlet", "constraint_preserving"):
+            raise ValueError("outer_bc must be 'dirichlet' or 'constraint_preserving'")
+        self.outer_bc = outer_bc
         # interfaces: consecutive shells of one instance
         self.interfaces = []
         for k in range(len(self.shells) - 1):
@@ -126,14 +133,18 @@ class Domain:
         Hb = self.split(H, 4)
         dHb = self.split(dH, 16)
         out = []
+        outer_du = {}
         for k, g in enumerate(self.grids):
             inst = self.shells[k].instance
             g0, g1, g2 = gammas[inst]
             du = self.cartesian_derivs(k, ub[k])
             dHk = dHb[k].reshape((4, 4) + dHb[k].shape[1:])
             out.append(_gh.rhs_pointwise(ub[k], du, Hb[k], dHk, g0, g1, g2))
+            if k in self.outer:
+                outer_du[k] = du[:, :, -1]
         if apply_bc:
-            self.apply_bc(out, ub if self.interface_from_state else self.split(u_bg, 50), gammas)
+            self.apply_bc(out, ub if self.interface_from_state else self.split(u_bg, 50), gammas,
+                          state=ub, outer_du=outer_du)
         return self.join(out)
 
     def interface_projection(self, k, ubg_blk):
@@ -148,7 +159,12 @@ class Domain:
         s_lo, s_up = _gh.unit_normal(geo, nhat)
         return geo, s_lo, s_up
 
-    def apply_bc(self, rhs_blocks, ubg_blocks, gammas):
+    def outer_projection(self, k, u_blk):
+        """Unit normal s = +r_hat (normalised with the metric of u_blk) at the
+        outer face of shell k."""
+        return self.interface_projection(k, u_blk)
+
+    def apply_bc(self, rhs_blocks, ubg_blocks, gammas, state=None, outer_du=None):
         """Boundary treatment of the per-shell d_t u blocks, in place.
 
         Paper (section on benchmarks of the overall code, closing remarks):
@@ -160,7 +176,11 @@ class Domain:
           u^0, u^+, u^-; take each of u^0, u^+-  from the upwind side (speed > 0:
           A, < 0: B, = 0: the average) and u^psi as the average of both sides;
           reconstruct and store the same d_t u on both sides;
-        * outer boundary: Dirichlet, d_t u = 0 for all 50 fields;
+        * outer boundary: Dirichlet, d_t u = 0 for all 50 fields, or (outer_bc
+          "constraint_preserving") gh.outer_constraint_preserving with the
+          normal and speeds from the state's metric at the face; that needs the
+          state blocks and the Cartesian derivatives at the outer faces
+          (state, outer_du[k] [3, 50, N_th, N_ph]);
         * inner (excision) boundary: nothing.
         """
         for (ka, kb) in self.interfaces:
@@ -185,7 +205,16 @@ class Domain:
             rhs_blocks[ka][:, -1] = new
             rhs_blocks[kb][:, 0] = new
         for k in self.outer:
-            rhs_blocks[k][:, -1] = 0.0
+            if self.outer_bc == "dirichlet":
+                rhs_blocks[k][:, -1] = 0.0
+                continue
+            if state is None or outer_du is None or k not in outer_du:
+                raise ValueError("the constraint-preserving outer treatment needs the state and its derivatives")
+            inst = self.shells[k].instance
+            g1, g2 = gammas[inst][1], gammas[inst][2]
+            geo, s_lo, s_up = self.outer_projection(k, state[k])
+            rhs_blocks[k][:, -1] = _gh.outer_constraint_preserving(
+                rhs_blocks[k][:, -1], state[k][:, -1], outer_du[k], s_lo, s_up, geo, g1, g2)
 
     def excision_speeds(self, u_bg):
         """Speeds (u^0, u^+, u^-) at every inner boundary, normal s = -r_hat."""

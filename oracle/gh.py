@@ -240,3 +240,55 @@ def char_reconstruct(upsi, u0, up, um, s_lo, gamma2):
     Pi = 0.5 * (up + um) + gamma2 * upsi
     Phi = u0 + 0.5 * np.einsum("i...,n...->in...", s_lo, up - um)
     return np.concatenate([upsi, Pi, Phi.reshape((30,) + Phi.shape[2:])])
+
+
+# ----------------------------------------------------------------------------
+# Constraint-preserving treatment of an outer boundary point
+# ----------------------------------------------------------------------------
+
+def outer_constraint_preserving(dtu, u, du, s_lo, s_up, geo, gamma1, gamma2):
+    """Boundary treatment of d_t u at outer-boundary points (normal s out of the
+    domain), reading the paper's constraint-preserving outer condition
+    (Conclusions, ApplyBCs case (ii)) for the constraints of the first-order
+    system.
+
+    dtu [50, ...] raw time derivatives; u [50, ...] fields; du [3, 50, ...]
+    their Cartesian derivatives; s_lo, s_up the unit normal (unit_normal);
+    geo the Geometry of u.  With N.s = s_k N^k:
+
+    * u^psi (speed -(1+g1) N.s) carries the three-index constraint
+      C_kab = d_k psi_ab - Phi_kab: d_t psi contains (1+g1) N^k C_kab, whose
+      normal part (1+g1)(N.s)(s^k C_kab) is the only piece that needs the
+      normal derivative of psi.  Where u^psi is incoming it is removed.
+    * u^0 (speed -N.s) carries the four-index constraint
+      C_klab = d_k Phi_lab - d_l Phi_kab: the normal advection of Phi_l is
+      (N.s)(s^k d_l Phi_k + s^k C_klab), and under the transverse projector
+      P_i^l = delta_i^l - s_i s^l only the constraint part needs a normal
+      derivative.  Where u^0 is incoming, (N.s) P_i^l s^k C_klab is removed.
+    * u^- (speed -N.s - N) is incoming at an outer boundary; the published
+      condition for it combines physical (Weyl), gauge and two-index
+      constraint parts.  Reading: it is frozen, d_t u^- = 0 (no incoming
+      radiation rate).  The same holds for u^+ if it were incoming.
+    * outgoing fields are left as they are.
+
+    After the treatment the incoming u^psi and u^0 depend on the fields and
+    their tangential derivatives only, and on data that satisfy the
+    constraints the treatment changes nothing but the incoming u^-.
+    """
+    v_psi, v_0, v_p, v_m = char_speeds(geo, s_lo, gamma1)
+    upsi, u0, up, um = char_fields(dtu, s_lo, s_up, gamma2)
+    sN = np.einsum("i...,i...->...", s_lo, geo.shift)
+    # C_kab and s^k C_kab
+    C3 = np.stack([du[k, 0:10] - u[20 + 10 * k:30 + 10 * k] for k in range(3)])          # [k, n]
+    sC3 = np.einsum("k...,kn...->n...", s_up, C3)
+    # C_klab and s^k C_klab  [l, n]
+    dPhi = np.stack([du[:, 20 + 10 * l:30 + 10 * l] for l in range(3)], axis=1)         # [k, l, n]
+    C4 = dPhi - np.swapaxes(dPhi, 0, 1)
+    sC4 = np.einsum("k...,kln...->ln...", s_up, C4)
+    # P_i^l sC4_l = sC4_i - s_i (s^l sC4_l)
+    proj = sC4 - np.einsum("i...,n...->in...", s_lo, np.einsum("l...,ln...->n...", s_up, sC4))
+    upsi = np.where(np.real(v_psi) < 0, upsi - (1.0 + gamma1) * sN * sC3, upsi)
+    u0 = np.where(np.real(v_0) < 0, u0 - sN * proj, u0)
+    up = np.where(np.real(v_p) < 0, 0.0 * up, up)
+    um = np.where(np.real(v_m) < 0, 0.0 * um, um)
+    return char_reconstruct(upsi, u0, up, um, s_lo, gamma2)
