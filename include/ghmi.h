@@ -296,7 +296,8 @@ int gh_query(const gh_ctx* ctx, int what, long long* value);
  * items of one launch of its coupling kernel; 13: the interface mode
  * (gh_set_interface); 14: kernel variant of the tail launch of the
  * derivative GEMM, -1 when it is one launch; 15: the same for the filter GEMM;
- * 16: number of K chunks of the derivative GEMM's tail (0 without).
+ * 16: number of K chunks of the derivative GEMM's tail (0 without); 17: the
+ * outer boundary mode (gh_set_outer_bc).
  *
  * Split plans.  Workgroups of a GEMM launch finish in rounds of one tile per
  * compute unit, so a tile count just above a multiple of the CU count costs a
@@ -331,6 +332,27 @@ int gh_set_gemm_variant(gh_ctx* ctx, int plan, int shape, int order);
  * (gh_rhs_vjp, gh_step_vjp, gh_step_vjp_stages) need mode 0 and return
  * GH_ERR_ARG in mode 1.  Drops a captured step graph when the mode changes. */
 int gh_set_interface(gh_ctx* ctx, int mode);
+
+/* Boundary condition at the outer boundary of every instance.
+ * mode 0 (default): Dirichlet, d_t u = 0 for all 50 fields.  mode 1: the
+ * paper's constraint-preserving outer condition (Conclusions, ApplyBCs case
+ * (ii)), read for the constraints of the first-order GH system: with the unit
+ * normal s (+r_hat normalised with the state's metric at the face) and the
+ * characteristic fields of the state,
+ *   incoming u^psi: minus (1+gamma1)(s.N) s^k C_kab (three-index constraint
+ *     C_kab = d_k psi_ab - Phi_kab, the part that needs d_s psi);
+ *   incoming u^0:  minus (s.N) (delta_i^l - s_i s^l) s^k C_klab (four-index
+ *     constraint C_klab = d_k Phi_lab - d_l Phi_kab, the part that needs
+ *     d_s Phi);
+ *   incoming u^- (and u^+ if incoming): frozen, d_t = 0;
+ *   outgoing fields untouched.
+ * So the incoming fields no longer depend on normal derivatives (which carry
+ * constraint violations into the domain), and on data that satisfy the
+ * constraints nothing changes but the incoming u^-.  Applied in gh_rhs,
+ * gh_step, gh_step_stages, gh_step_dp5 and captured graphs.  The reverse-pass
+ * entry points need mode 0 and return GH_ERR_ARG in mode 1.  Drops a captured
+ * step graph when the mode changes.  gh_query 17 reports the mode. */
+int gh_set_outer_bc(gh_ctx* ctx, int mode);
 
 /* Apply the domain's angular filter (filter_kind 1-3) once: out = F u.
  * Device pointers, [50 P] each, distinct (GH_ERR_ARG if out == u, or if the

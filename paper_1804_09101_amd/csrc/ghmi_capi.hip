@@ -98,6 +98,7 @@ struct gh_ctx {
   // rebuilt from the state before every boundary treatment, and scratch for
   // the excision speeds the table kernel also writes
   int iface_mode = 0, bc_total = 0;
+  int outer_mode = 0;                  // gh_set_outer_bc: 0 Dirichlet, 1 constraint-preserving
   double *d_bctab_s = nullptr, *d_exscr = nullptr;
   std::map<int, double*> d_angop;   // per L: [S][2S], B operand (Theta^T | Phi^T)
   std::map<int, double*> d_filtop;  // per L: [S][S], B operand F^T
@@ -294,6 +295,7 @@ void free_domain(gh_ctx* c) {
   c->d_sh = nullptr; c->d_blk = nullptr; c->d_cblk = nullptr; c->d_fblk = nullptr;
   c->d_dtab = c->d_angtab = c->d_radtab = c->d_bctab = nullptr;
   c->iface_mode = c->bc_total = 0;
+  c->outer_mode = 0;
   c->d_bctab_s = c->d_exscr = nullptr;
   c->d_inst_range = nullptr; c->d_wsum = c->d_partial = nullptr;
   c->d_dR = c->d_dA = c->d_W = c->d_ua = c->d_ub = nullptr;
@@ -634,7 +636,10 @@ int queue_rhs(gh_ctx* c, const double* u, double* out) {
     Timed t(c, 4);
     const double* tab = nullptr;
     if ((rc = interface_table(c, u, &tab))) return rc;
-    HIPCHK(c, ghk::boundary(c->d_sh, c->n_shells, c->max_S, tab, c->d_gamma, out, c->stream));
+    if (c->outer_mode)
+      HIPCHK(c, ghk::outer_cpbc(c->d_sh, c->n_shells, c->max_S, c->d_angtab, c->d_radtab, u, c->d_dR, c->d_dA,
+                                c->d_gamma, out, c->stream));
+    HIPCHK(c, ghk::boundary(c->d_sh, c->n_shells, c->max_S, tab, c->d_gamma, out, c->outer_mode, c->stream));
   }
   return GH_OK;
 }
@@ -657,8 +662,11 @@ int queue_stage(gh_ctx* c, double c0, const double* u0, double c1, const double*
     Timed t(c, 4);
     const double* tab = nullptr;
     if ((rc = interface_table(c, us, &tab))) return rc;
+    if (c->outer_mode)
+      HIPCHK(c, ghk::outer_cpbc(c->d_sh, c->n_shells, c->max_S, c->d_angtab, c->d_radtab, us, dR, dA, c->d_gamma,
+                                c->d_W, c->stream));
     HIPCHK(c, ghk::stage_bc(c->d_sh, c->d_blk, c->n_blk, tab, c->d_gamma, c->d_dt, c0, u0, c1, us, c->d_W,
-                            out, c->stream));
+                            out, c->outer_mode, c->stream));
   }
   return GH_OK;
 }
@@ -1564,6 +1572,8 @@ int gh_rhs_vjp(gh_ctx* c, const double* u, const double* lam, double* lam_u, dou
     return fail(c, GH_ERR_ARG, "u, lam, lam_u must be device pointers and lam_u distinct from u and lam");
   if (c->iface_mode)
     return fail(c, GH_ERR_ARG, "the reverse pass needs the frozen interface projection (gh_set_interface 0)");
+  if (c->outer_mode)
+    return fail(c, GH_ERR_ARG, "the reverse pass needs the Dirichlet outer boundary (gh_set_outer_bc 0)");
   HIPCHK(c, hipSetDevice(c->device));
   if ((rc = ensure_adjoint(c))) return rc;
   return queue_rhs_vjp(c, u, lam, lam_u, 1.0, 0, g_gamma);
@@ -1611,6 +1621,8 @@ int gh_step_vjp(gh_ctx* c, const double* u_n, const double* lam_np1, double* lam
     return fail(c, GH_ERR_ARG, "u_n, lam_np1, lam_n must be device pointers and lam_n distinct from u_n");
   if (c->iface_mode)
     return fail(c, GH_ERR_ARG, "the reverse pass needs the frozen interface projection (gh_set_interface 0)");
+  if (c->outer_mode)
+    return fail(c, GH_ERR_ARG, "the reverse pass needs the Dirichlet outer boundary (gh_set_outer_bc 0)");
   HIPCHK(c, hipSetDevice(c->device));
   if ((rc = ensure_adjoint(c))) return rc;
   // recompute the stages: u1 = u + h L(u), u2 = 3/4 u + 1/4 (u1 + h L(u1))
@@ -1647,6 +1659,8 @@ int gh_step_vjp_stages(gh_ctx* c, const double* u_n, const double* u1, const dou
     return fail(c, GH_ERR_ARG, "device pointers required; lam_n must not alias u_n, u1, u2 or derivs");
   if (c->iface_mode)
     return fail(c, GH_ERR_ARG, "the reverse pass needs the frozen interface projection (gh_set_interface 0)");
+  if (c->outer_mode)
+    return fail(c, GH_ERR_ARG, "the reverse pass needs the Dirichlet outer boundary (gh_set_outer_bc 0)");
   HIPCHK(c, hipSetDevice(c->device));
   if ((rc = ensure_adjoint(c))) return rc;
   return queue_step_vjp(c, u_n, u1, u2, lam_np1, lam_n, g_gamma, derivs);
@@ -1721,6 +1735,15 @@ int gh_set_gemm_variant(gh_ctx* c, int plan, int shape, int order) {
   return plan_upload(c, plan ? c->filter : c->deriv, shape, order);
 }
 
+int gh_set_outer_bc(gh_ctx* c, int mode) {
+  if (!c) return GH_ERR_ARG;
+  if (!c->have_domain) return fail(c, GH_ERR_ORDER, "gh_set_domain has not been called");
+  if (mode != 0 && mode != 1) return fail(c, GH_ERR_ARG, "mode must be 0 (Dirichlet) or 1 (constraint-preserving)");
+  if (mode != c->outer_mode) drop_graph(c);
+  c->outer_mode = mode;
+  return GH_OK;
+}
+
 int gh_set_interface(gh_ctx* c, int mode) {
   if (!c) return GH_ERR_ARG;
   if (!c->have_domain) return fail(c, GH_ERR_ORDER, "gh_set_domain has not been called");
@@ -1787,6 +1810,7 @@ int gh_query(const gh_ctx* c, int what, long long* value) {
     case 11: *value = c->tf_nnz; break;
     case 12: *value = c->n_tf_items[0] + c->n_tf_items[1] + c->n_tf_items[2]; break;
     case 13: *value = c->iface_mode; break;
+    case 17: *value = c->outer_mode; break;
     case 14: *value = c->deriv.n_ttiles ? c->deriv.tail_shape : -1; break;
     case 15: *value = c->filter.n_ttiles ? c->filter.tail_shape : -1; break;
     case 16: *value = c->deriv.n_ttiles ? c->deriv.tail_chunks : 0; break;

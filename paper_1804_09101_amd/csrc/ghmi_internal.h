@@ -122,14 +122,22 @@ hipError_t pointwise_rhs(const ShellDev* sh, const PtBlock* blk, int n_blk, cons
                          const double* H, const double* dH, const double* gamma, double* rhs,
                          hipStream_t st);
 
+// outer_mode 0: Dirichlet d_t u = 0 on outer faces; 1: outer faces left as
+// they are (already treated in place by outer_cpbc).
 hipError_t boundary(const ShellDev* sh, int n_shells, int max_S, const double* bctab,
-                    const double* gamma, double* rhs, hipStream_t st);
+                    const double* gamma, double* rhs, int outer_mode, hipStream_t st);
+
+// Constraint-preserving treatment of the outer faces of rhs in place, from the
+// state u and its radial (dR) and angular (dA) derivatives.
+hipError_t outer_cpbc(const ShellDev* sh, int n_shells, int max_S, const double* angtab, const double* radtab,
+                      const double* u, const double* dR, const double* dA, const double* gamma, double* rhs,
+                      hipStream_t st);
 
 // One SSP-RK3 stage, out = c0 u0 + c1 (us + dt L'), with the boundary
 // treatment of L (raw d_t u, read only) applied on the fly; out may alias u0.
 hipError_t stage_bc(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* bctab,
                     const double* gamma, const double* dt, double c0, const double* u0, double c1,
-                    const double* us, const double* L, double* out, hipStream_t st);
+                    const double* us, const double* L, double* out, int outer_mode, hipStream_t st);
 
 hipError_t constraints(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* angtab,
                        const double* radtab, const double* u, const double* dR, const double* dA,

@@ -435,7 +435,7 @@ __device__ __forceinline__ void interface_pair(const double A[5], const double B
 __global__ __launch_bounds__(256) void k_boundary(const ShellDev* __restrict__ sh,
                                                   const double* __restrict__ bctab,
                                                   const double* __restrict__ gamma,
-                                                  double* __restrict__ rhs) {
+                                                  double* __restrict__ rhs, int outer_mode) {
   const int k = blockIdx.y;
   const ShellDev s = sh[k];
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
@@ -443,8 +443,11 @@ __global__ __launch_bounds__(256) void k_boundary(const ShellDev* __restrict__ s
   const int P = s.n_r * s.S;
   const long long ia = 50LL * s.pt_off + (long long)(s.n_r - 1) * s.S + a;
   if (s.outer) {
+    // outer_mode 1: k_outer_cpbc has already treated the outer face in place
+    if (!outer_mode) {
 #pragma unroll 10
-    for (int f = 0; f < 50; ++f) rhs[ia + (long long)f * P] = 0.0;
+      for (int f = 0; f < 50; ++f) rhs[ia + (long long)f * P] = 0.0;
+    }
     return;
   }
   if (s.bc_off < 0) return;
@@ -474,10 +477,11 @@ __global__ __launch_bounds__(256) void k_boundary(const ShellDev* __restrict__ s
 // SSP-RK3 stage with the boundary treatment folded in:
 //   out = c0 u0 + c1 (us + dt L'),
 // where L' is the raw d_t u in L except on treated faces: zero on the outer
-// boundary, the upwinded interface value on both faces of an interface (each
-// element recomputes its pair's projection from L, which this kernel only
-// reads, so both shells get bitwise the same value).  dt per instance;
-// blockIdx.y = field.  out may alias u0.
+// boundary (outer_mode 0; with outer_mode 1 the outer face of L has already
+// been treated by k_outer_cpbc and is used as it is), the upwinded interface
+// value on both faces of an interface (each element recomputes its pair's
+// projection from L, which this kernel only reads, so both shells get bitwise
+// the same value).  dt per instance; blockIdx.y = field.  out may alias u0.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_stage_bc(const ShellDev* __restrict__ sh,
                                                   const PtBlock* __restrict__ blk,
@@ -486,7 +490,8 @@ __global__ __launch_bounds__(256) void k_stage_bc(const ShellDev* __restrict__ s
                                                   const double* __restrict__ dt, double c0,
                                                   const double* u0, double c1,
                                                   const double* __restrict__ us,
-                                                  const double* __restrict__ L, double* out) {
+                                                  const double* __restrict__ L, double* out,
+                                                  int outer_mode) {
   const PtBlock b = blk[blockIdx.x];
   const ShellDev s = sh[b.shell];
   const int P = s.n_r * s.S;
@@ -497,7 +502,7 @@ __global__ __launch_bounds__(256) void k_stage_bc(const ShellDev* __restrict__ s
   const int r = q / s.S;
   double val;
   if (r == s.n_r - 1 && s.outer) {
-    val = 0.0;
+    val = outer_mode ? L[e] : 0.0;
   } else if ((r == s.n_r - 1 && s.bc_off >= 0) || (r == 0 && !s.inner)) {
     // interface between shell ki (inner side) and ki + 1
     const int ki = (r == 0) ? b.shell - 1 : b.shell;
@@ -928,6 +933,92 @@ __global__ __launch_bounds__(256) void k_bc_setup(const ShellDev* __restrict__ s
     if (mn != mn) mn = -INFINITY;   // NaN speed: report as inflow
   }
   exmin[(long long)k * max_S + a] = mn;
+}
+
+// Constraint-preserving treatment of d_t u at the outer boundary (the
+// paper's ApplyBCs case (ii), Conclusions), in place on the raw RHS at every
+// outer-face point; blockIdx.y = shell, threads over angular points.  With the
+// unit normal s (+r_hat normalised with the state's metric at the face) and
+// N.s = s_k N^k, per symmetric pair:
+//   u^psi incoming (speed -(1+g1) N.s < 0): minus (1+g1)(N.s) s^k C_kab, the
+//     normal part of the three-index constraint C_kab = d_k psi_ab - Phi_kab;
+//   u^0 incoming (speed -N.s < 0): minus (N.s) P_i^l s^k C_klab, the normal
+//     part of the four-index constraint C_klab = d_k Phi_lab - d_l Phi_kab
+//     (P_i^l = delta_i^l - s_i s^l);
+//   u^+, u^- incoming: frozen (zero); outgoing fields untouched.
+// The Cartesian derivatives come from the derivative pass (dR, dA) through the
+// same Jacobian as the pointwise kernel.
+__global__ __launch_bounds__(256) void k_outer_cpbc(const ShellDev* __restrict__ sh,
+                                                    const double* __restrict__ angtab,
+                                                    const double* __restrict__ radtab,
+                                                    const double* __restrict__ u,
+                                                    const double* __restrict__ dR,
+                                                    const double* __restrict__ dA,
+                                                    const double* __restrict__ gamma,
+                                                    double* __restrict__ rhs) {
+  const int k = blockIdx.y;
+  const ShellDev s = sh[k];
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (!s.outer || a >= s.S) return;
+  const int P = s.n_r * s.S;
+  const int r = s.n_r - 1;
+  const long long ib = 50LL * s.pt_off + (long long)r * s.S + a;
+  const long long ab = 100LL * s.pt_off + (long long)r * 2 * s.S + a;
+  const long long astride = (long long)s.n_r * 2 * s.S;
+  const double* ang = angtab + 5LL * (s.ang_off + a);
+  double sl[3], su[3], v0, vp, vm;
+  face_normal(u, ib, P, ang, 1.0, sl, su, &v0, &vp, &vm);
+  const double g1 = gamma[3 * s.instance + 1], g2 = gamma[3 * s.instance + 2];
+  const double sN = -v0;
+  const double vpsi = -(1.0 + g1) * sN;
+  const Jac J = jacobian(ang, radtab[2 * (s.rad_off + r)]);
+  for (int n = 0; n < 10; ++n) {
+    double L[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) L[c] = rhs[ib + (long long)(10 * c + n) * P];
+    const double sPhi = su[0] * L[2] + su[1] * L[3] + su[2] * L[4];
+    double upsi = L[0];
+    double u0[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) u0[i] = L[2 + i] - sl[i] * sPhi;
+    double up = L[1] + sPhi - g2 * L[0];
+    double um = L[1] - sPhi - g2 * L[0];
+    if (vpsi < 0.0) {
+      double dpsi[3];
+      cart(J, dR[ib + (long long)n * P], dA[ab + (long long)n * astride], dA[ab + (long long)n * astride + s.S],
+           dpsi);
+      double sC3 = 0.0;
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) sC3 += su[kk] * (dpsi[kk] - u[ib + (long long)(20 + 10 * kk + n) * P]);
+      upsi -= (1.0 + g1) * sN * sC3;
+    }
+    if (v0 < 0.0) {
+      double dPhi[3][3];   // dPhi[l][k] = d_k Phi_l
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        const int f = 20 + 10 * l + n;
+        cart(J, dR[ib + (long long)f * P], dA[ab + (long long)f * astride], dA[ab + (long long)f * astride + s.S],
+             dPhi[l]);
+      }
+      double sC4[3];
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        double t = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) t += su[kk] * (dPhi[l][kk] - dPhi[kk][l]);
+        sC4[l] = t;
+      }
+      const double ss = su[0] * sC4[0] + su[1] * sC4[1] + su[2] * sC4[2];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) u0[i] -= sN * (sC4[i] - sl[i] * ss);
+    }
+    if (vp < 0.0) up = 0.0;
+    if (vm < 0.0) um = 0.0;
+    rhs[ib + (long long)n * P] = upsi;
+    rhs[ib + (long long)(10 + n) * P] = 0.5 * (up + um) + g2 * upsi;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) rhs[ib + (long long)(20 + 10 * i + n) * P] = u0[i] + 0.5 * sl[i] * (up - um);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_nonfinite(const double* __restrict__ x, long long n,
@@ -1443,17 +1534,26 @@ hipError_t pointwise_rhs(const ShellDev* sh, const PtBlock* blk, int n_blk, cons
 }
 
 hipError_t boundary(const ShellDev* sh, int n_shells, int max_S, const double* bctab,
-                    const double* gamma, double* rhs, hipStream_t st) {
+                    const double* gamma, double* rhs, int outer_mode, hipStream_t st) {
   dim3 grid((max_S + 255) / 256, n_shells), block(256);
-  hipLaunchKernelGGL(k_boundary, grid, block, 0, st, sh, bctab, gamma, rhs);
+  hipLaunchKernelGGL(k_boundary, grid, block, 0, st, sh, bctab, gamma, rhs, outer_mode);
+  return hipGetLastError();
+}
+
+hipError_t outer_cpbc(const ShellDev* sh, int n_shells, int max_S, const double* angtab, const double* radtab,
+                      const double* u, const double* dR, const double* dA, const double* gamma, double* rhs,
+                      hipStream_t st) {
+  dim3 grid((max_S + 255) / 256, n_shells), block(256);
+  hipLaunchKernelGGL(k_outer_cpbc, grid, block, 0, st, sh, angtab, radtab, u, dR, dA, gamma, rhs);
   return hipGetLastError();
 }
 
 hipError_t stage_bc(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* bctab,
                     const double* gamma, const double* dt, double c0, const double* u0, double c1,
-                    const double* us, const double* L, double* out, hipStream_t st) {
+                    const double* us, const double* L, double* out, int outer_mode, hipStream_t st) {
   dim3 grid(n_blk, 50), block(256);
-  hipLaunchKernelGGL(k_stage_bc, grid, block, 0, st, sh, blk, bctab, gamma, dt, c0, u0, c1, us, L, out);
+  hipLaunchKernelGGL(k_stage_bc, grid, block, 0, st, sh, blk, bctab, gamma, dt, c0, u0, c1, us, L, out,
+                     outer_mode);
   return hipGetLastError();
 }
 
