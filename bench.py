@@ -497,10 +497,11 @@ def timed_steps(wl, solver, u0_dev, steps, warmup, profile):
     }
 
 
-def large_batch_measurement(steps, adj_steps, k):
+def large_batch_measurement(steps, adj_steps):
     """The 4-instance batch of the 20-shell domain: forward rate (dense and by
     transforms) and the adjoint/forward ratio of a checkpointed gradient of the
-    final constraint norm."""
+    final constraint norm, with the checkpoint schedule planned for 80% of the
+    free device memory."""
     import torch
     from paper_1804_09101_amd import autograd as gha
     from paper_1804_09101_amd import configs, costs
@@ -539,9 +540,14 @@ def large_batch_measurement(steps, adj_steps, k):
     warm_adjoint(s, u0)
     gamma = torch.tensor(wl.gamma, dtype=torch.float64, requires_grad=True)
     ua = u0.clone().requires_grad_(True)
+    free, _ = torch.cuda.mem_get_info(u0.device)
+    budget = int(0.8 * free)
+    k1, k2 = gha.plan_checkpoints(adj_steps, u0.numel() * 8, budget)
     torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    base_mem = torch.cuda.memory_allocated()
     t0 = time.perf_counter()
-    un = gha.evolve(ua, gamma, s, wl.dt, adj_steps, checkpoint_every=k)
+    un = gha.evolve(ua, gamma, s, wl.dt, adj_steps, checkpoint_every=k1, inner_every=k2)
     L = gha.constraint_norm(un, s).sum()
     torch.cuda.synchronize()
     t_f = time.perf_counter() - t0
@@ -549,9 +555,13 @@ def large_batch_measurement(steps, adj_steps, k):
     L.backward()
     torch.cuda.synchronize()
     t_b = time.perf_counter() - t0
-    log(f"large batch4: adjoint forward {t_f:.2f} s, backward {t_b:.2f} s")
-    rec["adjoint"] = {"steps": adj_steps, "checkpoint_every": k, "forward_ms": t_f * 1e3,
-                      "backward_ms": t_b * 1e3, "ratio": t_b / t_f,
+    peak = torch.cuda.max_memory_allocated() - base_mem
+    log(f"large batch4: adjoint over {adj_steps} steps (checkpoints every {k1}, inner {k2}): forward {t_f:.2f} s, "
+        f"backward {t_b:.2f} s, peak {peak / 1e9:.1f} GB above the solver")
+    rec["adjoint"] = {"steps": adj_steps, "checkpoint_every": k1, "inner_every": k2,
+                      "planned_live_states": gha.live_states(adj_steps, k1, k2),
+                      "state_bytes": u0.numel() * 8, "peak_bytes_above_solver": peak, "budget_bytes": budget,
+                      "forward_ms": t_f * 1e3, "backward_ms": t_b * 1e3, "ratio": t_b / t_f,
                       "grad_gamma_norm": float(gamma.grad.norm()), "grad_u0_norm": float(ua.grad.norm())}
     del ua, un, L, gamma, s, u0
     torch.cuda.empty_cache()
@@ -684,7 +694,7 @@ def main():
     del solver, u0
     torch.cuda.empty_cache()
     if not args.no_large_batch:
-        out["large_batch4"] = large_batch_measurement(steps=10, adj_steps=10 if args.no_adjoint else 20, k=5)
+        out["large_batch4"] = large_batch_measurement(steps=10, adj_steps=10 if args.no_adjoint else 200)
     if not args.no_pulse:
         out["pulse_8shell"] = pulse_8shell_measurement(args)
     if not args.no_batched:
