@@ -521,15 +521,19 @@ GHP_HD int s3(int i, int j) {
 }
 GHP_HD double pmul(int a, int b) { return a == b ? 1.0 : 2.0; }
 
-template <class Load, class Store>
-GHP_HD void rhs_vjp_pairs(const double* u, const double* H, const double* dH, double g0, double g1,
-                          double g2, const double* lam, Load load, Store store, double* ubar, double* gbar) {
-  const double* psi = u;
-  const double* Pi = u + 10;
-  const double* Phi = u + 20;            // Phi_i pair n at Phi[10 i + n]
-  const double* lpsi = lam;
-  const double* lPi = lam + 10;
-  const double* lPhi = lam + 20;
+// The reverse pass in two parts, so that a kernel can run them as two
+// register-light passes: rhs_vjp_principal takes the derivative (principal)
+// terms, streaming the derivatives and their cotangents pair by pair, and
+// returns its partial cotangents of the geometry and of gamma1, gamma2 in
+// acc[12] = (N^i_b[3], N_b, giS[6], gamma1_b, gamma2_b), reading the
+// cotangent lam of d_t u through lamf(f); rhs_vjp_algebraic
+// continues from acc with the algebraic terms and the geometry's reverse.
+// rhs_vjp_pairs runs both; the sums are taken in the same order either way.
+#define GHP_VJP_ACC 12
+
+template <class LamF, class Load, class Store>
+GHP_HD void rhs_vjp_principal(const double* psi, double g1, double g2, LamF lamf, Load load, Store store,
+                              double* acc) {
   // geometry
   double gi[6], Nu[3], beta[3], N, tu[4], P[10];
   {
@@ -555,19 +559,19 @@ GHP_HD void rhs_vjp_pairs(const double* u, const double* H, const double* dH, do
       for (int b = a; b < 4; ++b)
         P[pair(a, b)] = ((a > 0 && b > 0) ? gi[s3(a - 1, b - 1)] : 0.0) - tu[a] * tu[b];
   }
-#pragma unroll
-  for (int f = 0; f < 50; ++f) ubar[f] = 0.0;
-  double Nu_b[3] = {0.0, 0.0, 0.0}, N_b = 0.0, giS[6] = {0, 0, 0, 0, 0, 0}, tu_b[4] = {0, 0, 0, 0};
-  double PS[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  double gb0 = 0.0, gb1 = 0.0, gb2 = 0.0;
+  double Nu_b[3] = {0.0, 0.0, 0.0}, N_b = 0.0, giS[6] = {0, 0, 0, 0, 0, 0};
+  double gb1 = 0.0, gb2 = 0.0;
+  (void)P;
+  (void)tu;
 
-  // (1) principal parts, streamed per pair
-#pragma unroll
+  // (1) principal parts, streamed per pair (not unrolled: one pair's
+  // derivatives and cotangents live at a time)
+#pragma unroll 1
   for (int n = 0; n < 10; ++n) {
     double dpsi[3], dPi[3], dPhi[3][3];
     load(n, dpsi, dPi, dPhi);
-    const double lp = lpsi[n], lP = lPi[n];
-    const double lF[3] = {lPhi[n], lPhi[10 + n], lPhi[20 + n]};
+    const double lp = lamf(n), lP = lamf(10 + n);
+    const double lF[3] = {lamf(20 + n), lamf(30 + n), lamf(40 + n)};
     double dpsi_b[3], dPi_b[3], dPhi_b[3][3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -604,6 +608,56 @@ GHP_HD void rhs_vjp_pairs(const double* u, const double* H, const double* dH, do
     for (int i = 0; i < 3; ++i) dps += lF[i] * dpsi[i];
     gb2 += N * dps + g1 * lP * adv;
   }
+
+  acc[0] = Nu_b[0]; acc[1] = Nu_b[1]; acc[2] = Nu_b[2]; acc[3] = N_b;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) acc[4 + i] = giS[i];
+  acc[10] = gb1;
+  acc[11] = gb2;
+}
+
+// u and lam are read through V (a pointer, or any type with v + k and v[i]),
+// so a kernel can leave them in memory instead of registers.
+template <class V>
+GHP_HD void rhs_vjp_algebraic(V u, const double* H, const double* dH, double g0, double g1, double g2, V lam,
+                              const double* acc, double* ubar, double* gbar) {
+  const V psi = u;
+  const V Pi = u + 10;
+  const V Phi = u + 20;                  // Phi_i pair n at Phi[10 i + n]
+  const V lpsi = lam;
+  const V lPi = lam + 10;
+  const V lPhi = lam + 20;
+  // geometry
+  double gi[6], Nu[3], beta[3], N, tu[4], P[10];
+  {
+    const double g11 = psi[4], g12 = psi[5], g13 = psi[6], g22 = psi[7], g23 = psi[8], g33 = psi[9];
+    const double A = g22 * g33 - g23 * g23, B = g13 * g23 - g12 * g33, Cc = g12 * g23 - g13 * g22;
+    const double D = g11 * g33 - g13 * g13, E = g12 * g13 - g11 * g23, F = g11 * g22 - g12 * g12;
+    const double idet = 1.0 / (g11 * A + g12 * B + g13 * Cc);
+    gi[0] = A * idet; gi[1] = B * idet; gi[2] = Cc * idet; gi[3] = D * idet; gi[4] = E * idet; gi[5] = F * idet;
+    beta[0] = psi[1]; beta[1] = psi[2]; beta[2] = psi[3];
+    double nsq = -psi[0];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      Nu[i] = gi[s3(i, 0)] * beta[0] + gi[s3(i, 1)] * beta[1] + gi[s3(i, 2)] * beta[2];
+      nsq += Nu[i] * beta[i];
+    }
+    N = sqrt(nsq);
+    tu[0] = 1.0 / N;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) tu[i + 1] = -Nu[i] / N;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = a; b < 4; ++b)
+        P[pair(a, b)] = ((a > 0 && b > 0) ? gi[s3(a - 1, b - 1)] : 0.0) - tu[a] * tu[b];
+  }
+#pragma unroll
+  for (int f = 0; f < 50; ++f) ubar[f] = 0.0;
+  double Nu_b[3] = {acc[0], acc[1], acc[2]}, N_b = acc[3];
+  double giS[6] = {acc[4], acc[5], acc[6], acc[7], acc[8], acc[9]}, tu_b[4] = {0, 0, 0, 0};
+  double PS[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double gb0 = 0.0, gb1 = acc[10], gb2 = acc[11];
 
   // (2) algebraic part of d_t psi, and the -g1 g2 N^i Phi_i term of d_t Pi
 #pragma unroll
@@ -1034,7 +1088,15 @@ GHP_HD void rhs_vjp_pairs(const double* u, const double* H, const double* dH, do
     }
   gbar[0] += gb0;
   gbar[1] += gb1;
-  gbar[2] += gb2;
+  gbar[2] += gb2;}
+
+template <class Load, class Store>
+GHP_HD void rhs_vjp_pairs(const double* u, const double* H, const double* dH, double g0, double g1,
+                          double g2, const double* lam, Load load, Store store, double* ubar, double* gbar) {
+  double acc[GHP_VJP_ACC];
+  auto lamf = [&](int f) { return lam[f]; };
+  rhs_vjp_principal(u, g1, g2, lamf, load, store, acc);
+  rhs_vjp_algebraic(u, H, dH, g0, g1, g2, lam, acc, ubar, gbar);
 }
 
 }  // namespace ghp

@@ -112,6 +112,7 @@ struct gh_ctx {
   double *d_Lb = nullptr, *d_dRb = nullptr, *d_dAb = nullptr, *d_T = nullptr;
   double *d_u1 = nullptr, *d_u2 = nullptr, *d_lam3 = nullptr, *d_mu1 = nullptr, *d_mu2 = nullptr;
   double *d_gpart = nullptr, *d_bcg = nullptr;
+  double* d_vacc = nullptr;          // [12][P]: geometry and gamma cotangents between the two reverse pointwise passes
   double *d_C = nullptr, *d_norm = nullptr;   // constraint values and norms for gh_constraints_vjp
 
   // Dormand-Prince work space (allocated on first use): seven stage
@@ -255,6 +256,7 @@ void free_domain(gh_ctx* c) {
   c->d_Lb = c->d_dRb = c->d_dAb = c->d_T = nullptr;
   c->d_u1 = c->d_u2 = c->d_lam3 = c->d_mu1 = c->d_mu2 = nullptr;
   c->d_gpart = c->d_bcg = nullptr;
+  c->d_vacc = nullptr;
   c->d_C = c->d_norm = nullptr;
   c->ang_method = 0;
   c->deriv_tr = c->filt_tr = false;
@@ -699,6 +701,7 @@ int ensure_adjoint(gh_ctx* c) {
   if ((rc = dalloc(c, &c->d_mu1, F50))) return rc;
   if ((rc = dalloc(c, &c->d_mu2, F50))) return rc;
   if ((rc = dalloc(c, &c->d_gpart, size_t(3) * c->n_blk))) return rc;
+  if ((rc = dalloc(c, &c->d_vacc, size_t(12) * c->P))) return rc;
   if ((rc = dalloc(c, &c->d_bcg, size_t(c->n_shells) * c->max_S))) return rc;
   if ((rc = dalloc(c, &c->d_C, size_t(64) * c->P))) return rc;
   if ((rc = dalloc(c, &c->d_norm, size_t(c->n_inst)))) return rc;
@@ -739,7 +742,8 @@ int queue_rhs_vjp(gh_ctx* c, const double* x, const double* mu, double* out, dou
   {
     Timed t(c, 6);
     HIPCHK(c, ghk::pointwise_vjp(c->d_sh, c->d_blk, c->n_blk, c->d_angtab, c->d_radtab, x, dR, dA, c->d_H,
-                                 c->d_dH, c->d_gamma, c->d_Lb, out, c->d_dRb, c->d_dAb, c->d_gpart, c->stream));
+                                 c->d_dH, c->d_gamma, c->d_Lb, out, c->d_dRb, c->d_dAb, c->d_gpart, c->d_vacc,
+                                 (long long)c->P, c->stream));
   }
   {
     Timed t(c, 7);

@@ -152,10 +152,13 @@ hipError_t bc_setup(const ShellDev* sh, int n_shells, int max_S, const double* a
 hipError_t nonfinite_count(const double* x, long long n, int* count, hipStream_t st);
 
 // adjoint
+// Reverse of the pointwise algebra in two passes; acc: work space of
+// 12 x p_total doubles (p_total = all points of the domain).
 hipError_t pointwise_vjp(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* angtab,
                          const double* radtab, const double* u, const double* dR, const double* dA,
                          const double* H, const double* dH, const double* gamma, const double* lam,
-                         double* ubar, double* dRb, double* dAb, double* gpart, hipStream_t st);
+                         double* ubar, double* dRb, double* dAb, double* gpart, double* acc, long long p_total,
+                         hipStream_t st);
 hipError_t constraints_vjp(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* angtab,
                            const double* radtab, const double* u, const double* H, const double* C,
                            const double* norm, const double* wsum, const double* lam_norm, double* ubar,

@@ -640,17 +640,80 @@ __global__ __launch_bounds__(256) void k_reduce_norm(const int* __restrict__ ran
 // Adjoint kernels.
 // ---------------------------------------------------------------------------
 
-// Reverse of the pointwise GH algebra and of the Cartesian Jacobian: from the
-// cotangent lam of the raw (pre-boundary) d_t u, write the direct cotangent of
-// u (overwriting ubar), the cotangents of the spherical derivatives (dRb and
-// dAb, laid out like dR and dA) and per-block sums of the gamma cotangents.
-__global__ __launch_bounds__(256) void k_pointwise_vjp(
+// Reverse of the pointwise GH algebra and of the Cartesian Jacobian, in two
+// register-light passes (one fused pass held 512 registers per lane and
+// spilled 2.8 kB of it to scratch memory).
+//
+// k_pointwise_vjp_principal: from the cotangent lam of the raw (pre-boundary)
+// d_t u, the cotangents of the spherical derivatives (dRb, dAb, laid out like
+// dR and dA) pair by pair, and the partial cotangents of the geometry and of
+// gamma1, gamma2 of these derivative terms into acc [12][P_total].
+__global__ __launch_bounds__(256) void k_pointwise_vjp_principal(
     const ShellDev* __restrict__ sh, const PtBlock* __restrict__ blk,
     const double* __restrict__ angtab, const double* __restrict__ radtab,
     const double* __restrict__ u, const double* __restrict__ dR, const double* __restrict__ dA,
+    const double* __restrict__ gamma, const double* __restrict__ lam, double* __restrict__ dRb,
+    double* __restrict__ dAb, double* __restrict__ acc, long long p_total) {
+  const PtBlock b = blk[blockIdx.x];
+  const ShellDev s = sh[b.shell];
+  const int P = s.n_r * s.S;
+  const int q = b.q0 + threadIdx.x;
+  if (q >= P) return;
+  const int r = q / s.S, a = q - r * s.S;
+  const long long ub = 50LL * s.pt_off + q;
+  const long long ab = 100LL * s.pt_off + (long long)r * 2 * s.S + a;
+  const long long astride = (long long)s.n_r * 2 * s.S;
+  const Jac J = jacobian(angtab + 5LL * (s.ang_off + a), radtab[2 * (s.rad_off + r)]);
+  double psi[10];
+#pragma unroll
+  for (int f = 0; f < 10; ++f) psi[f] = u[ub + (long long)f * P];
+  auto lamf = [&](int f) { return lam[ub + (long long)f * P]; };
+  // derivatives of the five fields of pair n, streamed from dR / dA
+  auto load = [&](int n, double* dpsi, double* dPi, double (*dPhi)[3]) {
+    cart(J, dR[ub + (long long)n * P], dA[ab + (long long)n * astride], dA[ab + (long long)n * astride + s.S], dpsi);
+    const int fp = 10 + n;
+    cart(J, dR[ub + (long long)fp * P], dA[ab + (long long)fp * astride], dA[ab + (long long)fp * astride + s.S], dPi);
+    for (int i = 0; i < 3; ++i) {
+      const int ff = 20 + 10 * i + n;
+      double d[3];
+      cart(J, dR[ub + (long long)ff * P], dA[ab + (long long)ff * astride], dA[ab + (long long)ff * astride + s.S], d);
+      dPhi[0][i] = d[0]; dPhi[1][i] = d[1]; dPhi[2][i] = d[2];
+    }
+  };
+  // Cartesian cotangents -> spherical cotangents (transpose of the Jacobian)
+  auto put = [&](int f, double x, double y, double z) {
+    dRb[ub + (long long)f * P] = J.xr * x + J.yr * y + J.zr * z;
+    dAb[ab + (long long)f * astride] = J.xt * x + J.yt * y + J.zt * z;
+    dAb[ab + (long long)f * astride + s.S] = J.xp * x + J.yp * y;
+  };
+  auto store = [&](int n, const double* dpsi_b, const double* dPi_b, const double (*dPhi_b)[3]) {
+    put(n, dpsi_b[0], dpsi_b[1], dpsi_b[2]);
+    put(10 + n, dPi_b[0], dPi_b[1], dPi_b[2]);
+    for (int i = 0; i < 3; ++i) put(20 + 10 * i + n, dPhi_b[0][i], dPhi_b[1][i], dPhi_b[2][i]);
+  };
+  double pa[GHP_VJP_ACC];
+  ghp::rhs_vjp_principal(psi, gamma[3 * s.instance + 1], gamma[3 * s.instance + 2], lamf, load, store, pa);
+  const long long pg = s.pt_off + q;
+#pragma unroll
+  for (int c = 0; c < GHP_VJP_ACC; ++c) acc[c * p_total + pg] = pa[c];
+}
+
+// A per-point field of a [component][point] array: v[i] is component i.
+struct Strided {
+  const double* p;
+  long long stride;
+  __device__ Strided operator+(int k) const { return Strided{p + k * stride, stride}; }
+  __device__ double operator[](int i) const { return p[i * stride]; }
+};
+
+// k_pointwise_vjp_algebraic: the algebraic terms and the reverse of the
+// geometry, continuing from acc: the direct cotangent of u (overwriting
+// ubar) and per-block sums of the gamma cotangents.
+__global__ __launch_bounds__(256) void k_pointwise_vjp_algebraic(
+    const ShellDev* __restrict__ sh, const PtBlock* __restrict__ blk, const double* __restrict__ u,
     const double* __restrict__ Hin, const double* __restrict__ dHin, const double* __restrict__ gamma,
-    const double* __restrict__ lam, double* __restrict__ ubar, double* __restrict__ dRb,
-    double* __restrict__ dAb, double* __restrict__ gpart) {
+    const double* __restrict__ lam, const double* __restrict__ acc, double* __restrict__ ubar,
+    double* __restrict__ gpart, long long p_total) {
   __shared__ double red[3][256];
   const PtBlock b = blk[blockIdx.x];
   const ShellDev s = sh[b.shell];
@@ -658,43 +721,16 @@ __global__ __launch_bounds__(256) void k_pointwise_vjp(
   const int q = b.q0 + threadIdx.x;
   double gb[3] = {0.0, 0.0, 0.0};
   if (q < P) {
-    const int r = q / s.S, a = q - r * s.S;
     const long long ub = 50LL * s.pt_off + q;
-    const long long ab = 100LL * s.pt_off + (long long)r * 2 * s.S + a;
-    const long long astride = (long long)s.n_r * 2 * s.S;
-    const Jac J = jacobian(angtab + 5LL * (s.ang_off + a), radtab[2 * (s.rad_off + r)]);
-    double uu[50], H[4], dH[16], lm[50], uo[50];
-    for (int f = 0; f < 50; ++f) {
-      uu[f] = u[ub + (long long)f * P];
-      lm[f] = lam[ub + (long long)f * P];
-    }
+    double H[4], dH[16], uo[50], pa[GHP_VJP_ACC];
     for (int c = 0; c < 4; ++c) H[c] = Hin[4LL * s.pt_off + (long long)c * P + q];
     for (int c = 0; c < 16; ++c) dH[c] = dHin[16LL * s.pt_off + (long long)c * P + q];
-    // derivatives of the five fields of pair n, streamed from dR / dA
-    auto load = [&](int n, double* dpsi, double* dPi, double (*dPhi)[3]) {
-      cart(J, dR[ub + (long long)n * P], dA[ab + (long long)n * astride], dA[ab + (long long)n * astride + s.S], dpsi);
-      const int fp = 10 + n;
-      cart(J, dR[ub + (long long)fp * P], dA[ab + (long long)fp * astride], dA[ab + (long long)fp * astride + s.S], dPi);
-      for (int i = 0; i < 3; ++i) {
-        const int ff = 20 + 10 * i + n;
-        double d[3];
-        cart(J, dR[ub + (long long)ff * P], dA[ab + (long long)ff * astride], dA[ab + (long long)ff * astride + s.S], d);
-        dPhi[0][i] = d[0]; dPhi[1][i] = d[1]; dPhi[2][i] = d[2];
-      }
-    };
-    // Cartesian cotangents -> spherical cotangents (transpose of the Jacobian)
-    auto put = [&](int f, double x, double y, double z) {
-      dRb[ub + (long long)f * P] = J.xr * x + J.yr * y + J.zr * z;
-      dAb[ab + (long long)f * astride] = J.xt * x + J.yt * y + J.zt * z;
-      dAb[ab + (long long)f * astride + s.S] = J.xp * x + J.yp * y;
-    };
-    auto store = [&](int n, const double* dpsi_b, const double* dPi_b, const double (*dPhi_b)[3]) {
-      put(n, dpsi_b[0], dpsi_b[1], dpsi_b[2]);
-      put(10 + n, dPi_b[0], dPi_b[1], dPi_b[2]);
-      for (int i = 0; i < 3; ++i) put(20 + 10 * i + n, dPhi_b[0][i], dPhi_b[1][i], dPhi_b[2][i]);
-    };
-    ghp::rhs_vjp_pairs(uu, H, dH, gamma[3 * s.instance], gamma[3 * s.instance + 1], gamma[3 * s.instance + 2], lm,
-                       load, store, uo, gb);
+    const long long pg = s.pt_off + q;
+    for (int c = 0; c < GHP_VJP_ACC; ++c) pa[c] = acc[c * p_total + pg];
+    // the fields and the cotangent are read where they are used (from the
+    // caches) rather than held in registers
+    ghp::rhs_vjp_algebraic(Strided{u + ub, P}, H, dH, gamma[3 * s.instance], gamma[3 * s.instance + 1],
+                           gamma[3 * s.instance + 2], Strided{lam + ub, P}, pa, uo, gb);
     for (int f = 0; f < 50; ++f) ubar[ub + (long long)f * P] = uo[f];
   }
   for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = gb[c];
@@ -1581,9 +1617,14 @@ hipError_t bc_setup(const ShellDev* sh, int n_shells, int max_S, const double* a
 hipError_t pointwise_vjp(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* angtab,
                          const double* radtab, const double* u, const double* dR, const double* dA,
                          const double* H, const double* dH, const double* gamma, const double* lam,
-                         double* ubar, double* dRb, double* dAb, double* gpart, hipStream_t st) {
-  hipLaunchKernelGGL(k_pointwise_vjp, dim3(n_blk), dim3(256), 0, st, sh, blk, angtab, radtab, u, dR, dA, H, dH,
-                     gamma, lam, ubar, dRb, dAb, gpart);
+                         double* ubar, double* dRb, double* dAb, double* gpart, double* acc, long long p_total,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_pointwise_vjp_principal, dim3(n_blk), dim3(256), 0, st, sh, blk, angtab, radtab, u, dR, dA,
+                     gamma, lam, dRb, dAb, acc, p_total);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pointwise_vjp_algebraic, dim3(n_blk), dim3(256), 0, st, sh, blk, u, H, dH, gamma, lam, acc,
+                     ubar, gpart, p_total);
   return hipGetLastError();
 }
 
