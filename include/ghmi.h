@@ -378,14 +378,6 @@ int gh_filter(gh_ctx* ctx, const double* u, double* out);
 int gh_tensor_filter_matrix(int L, int kind, const double* params, int transpose, long long* nnz,
                             long long* row_ptr, int* col, double* val);
 
-/* Measured ceiling of the FP64 matrix cores of device `device`: one launch
- * of back-to-back v_mfma_f64_16x16x4_f64 (eight independent accumulators per
- * wave, 32 waves per compute unit, `iters` iterations, no memory traffic in
- * the loop) timed with HIP events after a warm-up launch; *tflops receives the
- * rate.  Allocates and frees its own small output buffer and stream.  A
- * measurement aid beside the published peak, not part of the evolution. */
-int gh_probe_mfma_f64(int device, int iters, double* tflops);
-
 /* Message of the last error on this context (never NULL). */
 const char* gh_last_error(const gh_ctx* ctx);
 

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libghmi.so")
 SOURCES = ["csrc/ghmi_capi.hip", "csrc/ghmi_gemm.hip", "csrc/ghmi_kernels.hip", "csrc/ghmi_setup.cpp",
-           "csrc/ghmi_tensor_filter.cpp", "csrc/ghmi_probe.hip"]
+           "csrc/ghmi_tensor_filter.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -27,7 +27,7 @@ EXPORTS = [
     "gh_query", "gh_rhs_vjp", "gh_step_vjp", "gh_constraints_vjp",
     "gh_set_graph", "gh_step_stages", "gh_step_vjp_stages", "gh_step_dp5", "gh_set_angular",
     "gh_filter", "gh_tensor_filter_matrix", "gh_set_interface", "gh_set_gemm_variant",
-    "gh_constraints_static", "gh_probe_mfma_f64", "gh_set_outer_bc",
+    "gh_constraints_static", "gh_set_outer_bc",
 ]
 
 NUM_GEMM_VARIANTS = 13
@@ -76,7 +76,6 @@ def load_library(path=LIB_PATH):
         "gh_step": (i, [vp, vp, i]),
         "gh_constraints": (i, [vp, vp, vp, vp]),
         "gh_constraints_static": (i, [vp, vp, vp, vp]),
-        "gh_probe_mfma_f64": (i, [i, i, pd]),
         "gh_last_error": (ctypes.c_char_p, [vp]),
         "gh_grid_coords": (i, [i, psh, pd]),
         "gh_host_operator": (i, [i, i, pd, pd]),
@@ -153,16 +152,6 @@ def host_operator(kind, n, params=None):
     if rc:
         raise GHError(rc, "gh_host_operator")
     return out
-
-
-def probe_mfma_f64(device=0, iters=20000):
-    """Sustained FP64 MFMA rate of the device in TFLOP/s (gh_probe_mfma_f64)."""
-    lib = load_library()
-    out = ctypes.c_double(0.0)
-    rc = lib.gh_probe_mfma_f64(int(device), int(iters), ctypes.byref(out))
-    if rc:
-        raise GHError(rc, "gh_probe_mfma_f64")
-    return out.value
 
 
 def tensor_filter_matrix(L, kind, params, transpose=False):
