@@ -50,14 +50,16 @@ PROFILE_PULSE = os.path.join(ROOT, "profiles", "pulse_8shell_step_kernels.md")
 KERNEL_SOURCES = ["ghmi_gemm.hip", "ghmi_gemm.h"]
 
 
-def gemm_traffic(profile, variant, order):
-    """HBM bytes per launch of the derivative GEMM from the committed PMC records.
+def gemm_traffic(profile, variant, order, tail=-1, chunks=0):
+    """HBM bytes of one derivative pass from the committed PMC records.
 
-    The profile summary lists, for every kernel variant and tile order,
-    FETCH_SIZE and WRITE_SIZE per dispatch scaled by a plain copy's counts
-    (`traffic-record:` lines), and the hash of the GEMM sources they were
-    measured with (`traffic-sources:`).  Returns None unless the hash matches
-    the sources of the running library and a record for (variant, order) exists.
+    The profile summary lists, per GEMM plan (kernel variant, tile order and,
+    for a split plan, the tail variant and its K chunks), FETCH_SIZE and
+    WRITE_SIZE per pass (main launch, tail launch and chunk sum) scaled by a
+    plain copy's counts (`traffic-record:` lines), and the hash of the GEMM
+    sources they were measured with (`traffic-sources:`).  Returns None unless
+    the hash matches the sources of the running library and a record for the
+    running plan exists.
     """
     import hashlib
     try:
@@ -73,7 +75,8 @@ def gemm_traffic(profile, variant, order):
     for line in lines:
         if line.startswith("traffic-record:"):
             rec = dict(kv.split("=", 1) for kv in line.split()[1:])
-            if int(rec["variant"]) == variant and int(rec["order"]) == order:
+            if (int(rec["variant"]) == variant and int(rec["order"]) == order
+                    and int(rec.get("tail", -1)) == tail and int(rec.get("chunks", 0)) == (chunks if tail >= 0 else 0)):
                 return int(rec["bytes_per_launch"])
     return None
 
@@ -493,15 +496,16 @@ def timed_steps(wl, solver, u0_dev, steps, warmup, profile):
     avg_s = ms_g / n_g / 1e3
     flops = costs.angular_gemm_flops(wl.shells)
     achieved = flops / avg_s / 1e12
-    one_launch = solver.query(14) < 0
+    tail, chunks = solver.query(14), solver.query(16)
     return {
         "value": P * 3 * steps / t,
         "ms_per_step": t / steps * 1e3,
         "roofline": {"kernel": "angular derivative GEMM (FP64 MFMA)", "bound": "mfma",
                      "achieved": achieved, "peak": MI355X_FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / MI355X_FP64_PEAK_TFLOPS,
-                     "traffic": gemm_traffic(profile, solver.query(6), solver.query(4)) if one_launch else None,
-                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "traffic": gemm_traffic(profile, solver.query(6), solver.query(4), tail, chunks),
+                     "traffic_unit": "bytes per derivative pass between L2 and memory (rocprofv3 FETCH_SIZE + "
+                                     "WRITE_SIZE, copy-calibrated; main launch, and tail and chunk sum of a split plan)",
                      "algorithmic_bytes": costs.angular_gemm_bytes(wl.shells),
                      "flops_per_launch": flops, "avg_launch_us": avg_s * 1e6, "launches_timed": n_g},
         "paper_model": dict(costs.domain_model(wl.shells), note="the paper's dense shell differentiator "

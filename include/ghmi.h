@@ -285,7 +285,8 @@ int gh_kernel_stats(gh_ctx* ctx, int kind, long long* launches, double* total_ms
  * derivative GEMM chosen by the autotuner, as BM*1000 + BN; 1: the same for the
  * filter GEMM (0 without filter); 2: number of tiles of one derivative GEMM
  * launch; 3: total collocation points; 4: tile order of the derivative GEMM
- * (0: each XCD takes whole column blocks, 1: whole row blocks); 5: the same
+ * (0: each XCD takes whole column blocks, 1: whole row blocks, 2: blocks of
+ * 8 x 8 tiles); 5: the same
  * for the filter GEMM; 6: kernel variant of the derivative GEMM (index into
  * the library's list of tile shape, wave layout and LDS layout); 7: the same
  * for the filter GEMM (-1 without filter); 8: the angular method (gh_set_angular);
@@ -316,7 +317,8 @@ int gh_query(const gh_ctx* ctx, int what, long long* value);
  * plan 0: the angular derivative GEMM, 1: the filter GEMM (filter_kind 1);
  * shape: variant index 0 .. 12 (tile, wave layout, LDS layout, k-slice depth;
  * gh_query 6/7 report the current one); order 0: column blocks per XCD, 1:
- * row blocks.  A pinned plan is one launch (no tail).  GH_ERR_ARG otherwise.
+ * row blocks, 2: blocks of 8 x 8 tiles.  A pinned plan is one launch (no
+ * tail).  GH_ERR_ARG otherwise.
  * Drops a captured step graph. */
 int gh_set_gemm_variant(gh_ctx* ctx, int plan, int shape, int order);
 

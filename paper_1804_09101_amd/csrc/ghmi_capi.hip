@@ -451,7 +451,7 @@ int autotune(gh_ctx* c, GemmPlan& pl, const double* src, double* dst, int role) 
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
   for (int sh = 0; sh < ghk::NUM_TILE_SHAPES; ++sh) {
-    for (int order = 0; order < 2; ++order) {
+    for (int order = 0; order < ghk::NUM_TILE_ORDERS; ++order) {
       int rc = plan_upload(c, pl, sh, order);
       if (rc) return rc;
       float ms = 0;
@@ -1730,8 +1730,9 @@ int gh_constraints_vjp(gh_ctx* c, const double* u, const double* lam_norm, doubl
 int gh_set_gemm_variant(gh_ctx* c, int plan, int shape, int order) {
   if (!c) return GH_ERR_ARG;
   if (!c->have_domain) return fail(c, GH_ERR_ORDER, "gh_set_domain has not been called");
-  if (plan < 0 || plan > 1 || shape < 0 || shape >= ghk::NUM_TILE_SHAPES || order < 0 || order > 1)
-    return fail(c, GH_ERR_ARG, "plan 0 or 1, shape 0 .. NUM_TILE_SHAPES-1, order 0 or 1");
+  if (plan < 0 || plan > 1 || shape < 0 || shape >= ghk::NUM_TILE_SHAPES || order < 0 ||
+      order >= ghk::NUM_TILE_ORDERS)
+    return fail(c, GH_ERR_ARG, "plan 0 or 1, shape 0 .. NUM_TILE_SHAPES-1, order 0 .. 2");
   if (plan == 1 && c->filter_kind != 1) return fail(c, GH_ERR_ARG, "the domain has no filter GEMM (filter_kind 1)");
   HIPCHK(c, hipSetDevice(c->device));
   HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -1,4 +1,4 @@
-"""Every kernel variant of the grouped GEMM, in both tile orders, pinned in
+"""Every kernel variant of the grouped GEMM, in every tile order, pinned in
 turn (gh_set_gemm_variant) for the derivative and the filter GEMM, on a
 mixed-L domain whose sizes are ragged for every tile: K = S = 72 (L = 5, not a
 multiple of 16 or 32), 128 and 288; row counts 50 n_r not multiples of the tile
@@ -27,7 +27,7 @@ def test_every_variant_and_order():
     c.s.step(tuned, 1)
     worst_rhs = worst_step = 0.0
     for shape in range(ghmi.NUM_GEMM_VARIANTS):
-        for order in (0, 1):
+        for order in (0, 1, 2):
             c.s.set_gemm_variant(0, shape, order)
             c.s.set_gemm_variant(1, shape, order)
             assert c.s.query(6) == shape and c.s.query(7) == shape and c.s.query(4) == order
