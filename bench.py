@@ -17,7 +17,7 @@ operators by transforms (gh_set_angular 2); its 4-instance batch (forward,
 and the adjoint/forward cost ratio of a checkpointed gradient of the final
 constraint norm); the 8-shell pulse workload (its own GEMM roofline, graph,
 transforms, constraints, the interface projection taken from the state, the
-tensor-coupled filter, adaptive Dormand-Prince 5(4) stepping, the 200-step
+constraint-preserving outer boundary, the tensor-coupled filter, adaptive Dormand-Prince 5(4) stepping, the 200-step
 adjoint/forward ratio); 64 heterogeneous Kerr holes in one context against
 one context per hole.  cpu_baseline: the CPU oracle on one shell of the
 20-shell domain on one thread (and on every thread of the pool).
@@ -221,6 +221,23 @@ def interface_state_measurement(solver, u0_dev, steps):
     t = time.perf_counter() - t0
     solver.set_interface(0)
     return {"mode": "interface projection from the state (gh_set_interface 1)", "ms_per_step": t / steps * 1e3,
+            "value": solver.P * 3 * steps / t, "unit": "grid-point RHS evals/s"}
+
+
+def outer_bc_measurement(solver, u0_dev, steps):
+    """The same RK3 steps with the constraint-preserving outer boundary
+    (gh_set_outer_bc 1: one more small kernel per stage on the outer faces)."""
+    import torch
+    solver.set_outer_bc(1)
+    u = u0_dev.clone()
+    solver.step(u, 5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solver.step(u, steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    solver.set_outer_bc(0)
+    return {"mode": "constraint-preserving outer boundary (gh_set_outer_bc 1)", "ms_per_step": t / steps * 1e3,
             "value": solver.P * 3 * steps / t, "unit": "grid-point RHS evals/s"}
 
 
@@ -616,6 +633,8 @@ def pulse_8shell_measurement(args):
         f"{out['constraints']['with_C']['ms_per_evaluation']:.3f} ms with the per-point array")
     out["interface_state"] = interface_state_measurement(solver, u0, args.steps)
     log(f"interface from state: {out['interface_state']['ms_per_step']:.3f} ms/step")
+    out["outer_bc"] = outer_bc_measurement(solver, u0, args.steps)
+    log(f"constraint-preserving outer boundary: {out['outer_bc']['ms_per_step']:.3f} ms/step")
     if not args.no_tensor_filter:
         out["tensor_filter"] = tensor_filter_measurement(wl, min(args.steps, 50))
         tfm = out["tensor_filter"]

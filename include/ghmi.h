@@ -322,6 +322,22 @@ int gh_query(const gh_ctx* ctx, int what, long long* value);
  * Drops a captured step graph. */
 int gh_set_gemm_variant(gh_ctx* ctx, int plan, int shape, int order);
 
+/* Pin any GEMM plan of the context, including a split plan (for reproducible
+ * timing and to check every plan form).  plan 0: angular derivative, 1:
+ * filter, 2: transposed derivative (adjoint), 3: transposed filter, 4:
+ * Fourier analysis, 5: Fourier synthesis of the derivatives, 6: Fourier
+ * synthesis of the filter (4-6 exist after gh_set_angular 1 or 2), 7, 8:
+ * PhysToSpec and SpecToPhys of the tensor-coupled filter, 9, 10: their
+ * transposes (2, 3, 9, 10 set up the reverse pass on first use).  shape and
+ * order as in gh_set_gemm_variant.  tail_shape -1: one launch.  Otherwise a
+ * split plan: the leading rows that fill whole rounds of `round` tiles (0:
+ * one round = the number of compute units) in one launch of `shape`, the
+ * remaining rows (one group) in tiles of `tail_shape` over tail_chunks (1 .. 8)
+ * chunks of K with partial products in the plan's work space, then their sum
+ * in chunk order.  GH_ERR_ARG if the plan does not exist for this domain or
+ * its tiles do not split that way.  Drops a captured step graph. */
+int gh_set_gemm_plan(gh_ctx* ctx, int plan, int shape, int order, int tail_shape, int tail_chunks, int round);
+
 /* Where the characteristic projection at shell interfaces comes from.
  * mode 0 (default): the unit normal's metric normalisation and the upwind
  * choice (signs of the characteristic speeds) are taken from u_bg at

@@ -320,6 +320,18 @@ int dalloc(gh_ctx* c, T** p, size_t count) {
   return GH_OK;
 }
 
+// Free one allocation of the context early (the others go in free_domain).
+template <class T>
+void dfree(gh_ctx* c, T*& p) {
+  if (!p) return;
+  auto it = std::find(c->allocs.begin(), c->allocs.end(), static_cast<void*>(p));
+  if (it != c->allocs.end()) {
+    (void)hipFree(p);
+    c->allocs.erase(it);
+  }
+  p = nullptr;
+}
+
 template <class T>
 int upload(gh_ctx* c, T** p, const std::vector<T>& h) {
   int rc = dalloc(c, p, h.size());
@@ -328,8 +340,27 @@ int upload(gh_ctx* c, T** p, const std::vector<T>& h) {
   return GH_OK;
 }
 
+// Free the device tile lists and split work space of a plan (its groups stay),
+// so that re-planning (tuning trials, pinning) does not accumulate buffers.
+void plan_release(gh_ctx* c, GemmPlan& pl) {
+  if (!pl.d_tiles && !pl.d_tgroups && !pl.d_ttiles && !pl.d_work) return;
+  // queued launches may still read the lists
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->cap_stream) (void)hipStreamSynchronize(c->cap_stream);
+  dfree(c, pl.d_tiles);
+  if (pl.d_groups != pl.d_full) dfree(c, pl.d_groups);
+  pl.d_groups = nullptr;
+  dfree(c, pl.d_tgroups);
+  dfree(c, pl.d_ttiles);
+  dfree(c, pl.d_work);
+  pl.n_tiles = pl.n_ttiles = 0;
+  pl.tail_shape = -1;
+  pl.tail_chunks = 0;
+}
+
 // Build the tile list of a plan for one kernel variant and tile order and upload it.
 int plan_upload(gh_ctx* c, GemmPlan& pl, int shape, int order) {
+  plan_release(c, pl);
   std::vector<GemmTile> tiles = ghk::build_tiles(pl.groups, shape, order);
   pl.shape = shape;
   pl.order = order;
@@ -396,6 +427,7 @@ int plan_upload_split(gh_ctx* c, GemmPlan& pl, const std::vector<GemmGroup>& mai
     g.ldc = tail.N;
     kv.push_back(g);
   }
+  plan_release(c, pl);
   std::vector<GemmTile> tiles = ghk::build_tiles(mainv, shape, order);
   std::vector<GemmTile> ttiles = ghk::build_tiles(kv, tail_shape, 1);
   int rc;
@@ -1738,6 +1770,33 @@ int gh_set_gemm_variant(gh_ctx* c, int plan, int shape, int order) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   drop_graph(c);
   return plan_upload(c, plan ? c->filter : c->deriv, shape, order);
+}
+
+int gh_set_gemm_plan(gh_ctx* c, int plan, int shape, int order, int tail_shape, int tail_chunks, int round) {
+  if (!c) return GH_ERR_ARG;
+  if (!c->have_domain) return fail(c, GH_ERR_ORDER, "gh_set_domain has not been called");
+  if (plan < 0 || plan > 10) return fail(c, GH_ERR_ARG, "plan must be 0 .. 10");
+  if (shape < 0 || shape >= ghk::NUM_TILE_SHAPES || order < 0 || order >= ghk::NUM_TILE_ORDERS)
+    return fail(c, GH_ERR_ARG, "shape 0 .. NUM_TILE_SHAPES-1, order 0 .. 2");
+  if (tail_shape >= ghk::NUM_TILE_SHAPES || (tail_shape >= 0 && (tail_chunks < 1 || tail_chunks > 8)) || round < 0)
+    return fail(c, GH_ERR_ARG, "tail_shape -1 (one launch) or 0 .. NUM_TILE_SHAPES-1 with 1 .. 8 K chunks; round >= 0");
+  HIPCHK(c, hipSetDevice(c->device));
+  int rc;
+  if ((plan == 2 || plan == 3 || plan >= 9) && (rc = ensure_adjoint(c))) return rc;
+  if (plan >= 4 && plan <= 6 && !c->have_tr)
+    return fail(c, GH_ERR_ORDER, "the transform plans exist after gh_set_angular 1 or 2");
+  GemmPlan* const plans[11] = {&c->deriv, &c->filter, &c->derivT, &c->filterT, &c->tr_ana, &c->tr_syn,
+                               &c->tr_fsyn, &c->tf_p2s, &c->tf_s2p, &c->tf_p2sT, &c->tf_s2pT};
+  GemmPlan& pl = *plans[plan];
+  if (pl.groups.empty()) return fail(c, GH_ERR_ARG, "this domain has no such GEMM plan");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  drop_graph(c);
+  if (tail_shape < 0) return plan_upload(c, pl, shape, order);
+  std::vector<GemmGroup> mainv, tailv;
+  if (!split_rows(pl.groups, shape, round > 0 ? round : c->n_cu, mainv, tailv) || tailv.size() != 1)
+    return fail(c, GH_ERR_ARG, "no split of this plan's tiles into whole rounds of that size and one tail group");
+  if (tailv[0].K < 16 * tail_chunks) return fail(c, GH_ERR_ARG, "the tail's K is too short for that many chunks");
+  return plan_upload_split(c, pl, mainv, tailv[0], shape, order, tail_shape, tail_chunks);
 }
 
 int gh_set_outer_bc(gh_ctx* c, int mode) {

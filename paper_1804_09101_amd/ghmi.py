@@ -27,7 +27,7 @@ EXPORTS = [
     "gh_query", "gh_rhs_vjp", "gh_step_vjp", "gh_constraints_vjp",
     "gh_set_graph", "gh_step_stages", "gh_step_vjp_stages", "gh_step_dp5", "gh_set_angular",
     "gh_filter", "gh_tensor_filter_matrix", "gh_set_interface", "gh_set_gemm_variant",
-    "gh_constraints_static", "gh_set_outer_bc",
+    "gh_constraints_static", "gh_set_outer_bc", "gh_set_gemm_plan",
 ]
 
 NUM_GEMM_VARIANTS = 13
@@ -93,6 +93,7 @@ def load_library(path=LIB_PATH):
         "gh_filter": (i, [vp, vp, vp]),
         "gh_set_interface": (i, [vp, i]),
         "gh_set_outer_bc": (i, [vp, i]),
+        "gh_set_gemm_plan": (i, [vp, i, i, i, i, i, i]),
         "gh_set_gemm_variant": (i, [vp, i, i, i]),
         "gh_tensor_filter_matrix": (i, [i, i, pd, i, pll, pll, ctypes.POINTER(ctypes.c_int), pd]),
     }
@@ -315,6 +316,11 @@ class GHSolver:
         """Pin the kernel variant and tile order of the derivative (plan 0) or
         filter (plan 1) GEMM instead of the autotuner's choice."""
         self._check(self.lib.gh_set_gemm_variant(self.h, int(plan), int(shape), int(order)))
+
+    def set_gemm_plan(self, plan, shape, order, tail_shape=-1, tail_chunks=0, round_tiles=0):
+        """Pin any GEMM plan, one launch (tail_shape -1) or split (gh_set_gemm_plan)."""
+        self._check(self.lib.gh_set_gemm_plan(self.h, int(plan), int(shape), int(order), int(tail_shape),
+                                              int(tail_chunks), int(round_tiles)))
 
     def set_outer_bc(self, mode):
         """0: Dirichlet outer boundary; 1: constraint-preserving (gh_set_outer_bc)."""
