@@ -334,8 +334,9 @@ int gh_set_gemm_variant(gh_ctx* ctx, int plan, int shape, int order);
  * one round = the number of compute units) in one launch of `shape`, the
  * remaining rows (one group) in tiles of `tail_shape` over tail_chunks (1 .. 8)
  * chunks of K with partial products in the plan's work space, then their sum
- * in chunk order.  GH_ERR_ARG if the plan does not exist for this domain or
- * its tiles do not split that way.  Drops a captured step graph. */
+ * in chunk order.  GH_ERR_ARG if the plan does not exist for this domain,
+ * its tiles do not split that way, or the tail's K is under 16 per chunk.
+ * Drops a captured step graph. */
 int gh_set_gemm_plan(gh_ctx* ctx, int plan, int shape, int order, int tail_shape, int tail_chunks, int round);
 
 /* Where the characteristic projection at shell interfaces comes from.
