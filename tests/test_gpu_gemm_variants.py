@@ -39,7 +39,7 @@ def test_every_variant_and_order():
             print(f"  variant {shape} order {order}: rhs {e:.2e}, filtered step vs tuned {es:.2e}", flush=True)
             worst_rhs, worst_step = max(worst_rhs, e), max(worst_step, es)
             assert e < 1e-12 and es < 1e-13
-    for bad in ((2, 0, 0), (0, ghmi.NUM_GEMM_VARIANTS, 0), (0, 0, 2), (0, -1, 0)):
+    for bad in ((2, 0, 0), (0, ghmi.NUM_GEMM_VARIANTS, 0), (0, 0, 3), (0, -1, 0)):
         with pytest.raises(ghmi.GHError) as ei:
             c.s.set_gemm_variant(*bad)
         assert ei.value.code == -1
