@@ -483,6 +483,7 @@ int autotune(gh_ctx* c, GemmPlan& pl, const double* src, double* dst, int role) 
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
   for (int sh = 0; sh < ghk::NUM_TILE_SHAPES; ++sh) {
+    if (!ghk::shape_fits(sh, pl.groups)) continue;
     for (int order = 0; order < ghk::NUM_TILE_ORDERS; ++order) {
       int rc = plan_upload(c, pl, sh, order);
       if (rc) return rc;
@@ -505,7 +506,7 @@ int autotune(gh_ctx* c, GemmPlan& pl, const double* src, double* dst, int role) 
     for (int ts = 0; ts < ghk::NUM_TILE_SHAPES; ++ts) {
       int tbm, tbn;
       ghk::tile_dims(ts, &tbm, &tbn);
-      if (ts == best_shape || tbm * tbn >= bm * bn) continue;
+      if (ts == best_shape || tbm * tbn >= bm * bn || !ghk::shape_fits(ts, tailv)) continue;
       for (int chunks = 2; chunks <= 8; chunks *= 2) {
         if (tailv[0].K < 16 * chunks) continue;
         int rc = plan_upload_split(c, pl, mainv, tailv[0], best_shape, best_order, ts, chunks);
@@ -1766,6 +1767,8 @@ int gh_set_gemm_variant(gh_ctx* c, int plan, int shape, int order) {
       order >= ghk::NUM_TILE_ORDERS)
     return fail(c, GH_ERR_ARG, "plan 0 or 1, shape 0 .. NUM_TILE_SHAPES-1, order 0 .. 2");
   if (plan == 1 && c->filter_kind != 1) return fail(c, GH_ERR_ARG, "the domain has no filter GEMM (filter_kind 1)");
+  if (!ghk::shape_fits(shape, (plan ? c->filter : c->deriv).groups))
+    return fail(c, GH_ERR_ARG, "this variant loads directly into LDS and needs even K, N, lda, ldb and offsets");
   HIPCHK(c, hipSetDevice(c->device));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   drop_graph(c);
@@ -1789,6 +1792,8 @@ int gh_set_gemm_plan(gh_ctx* c, int plan, int shape, int order, int tail_shape, 
                                &c->tr_fsyn, &c->tf_p2s, &c->tf_s2p, &c->tf_p2sT, &c->tf_s2pT};
   GemmPlan& pl = *plans[plan];
   if (pl.groups.empty()) return fail(c, GH_ERR_ARG, "this domain has no such GEMM plan");
+  if (!ghk::shape_fits(shape, pl.groups))
+    return fail(c, GH_ERR_ARG, "this variant loads directly into LDS and needs even K, N, lda, ldb and offsets");
   HIPCHK(c, hipStreamSynchronize(c->stream));
   drop_graph(c);
   if (tail_shape < 0) return plan_upload(c, pl, shape, order);
@@ -1796,6 +1801,8 @@ int gh_set_gemm_plan(gh_ctx* c, int plan, int shape, int order, int tail_shape, 
   if (!split_rows(pl.groups, shape, round > 0 ? round : c->n_cu, mainv, tailv) || tailv.size() != 1)
     return fail(c, GH_ERR_ARG, "no split of this plan's tiles into whole rounds of that size and one tail group");
   if (tailv[0].K < 16 * tail_chunks) return fail(c, GH_ERR_ARG, "the tail's K is too short for that many chunks");
+  if (!ghk::shape_fits(tail_shape, tailv))
+    return fail(c, GH_ERR_ARG, "the tail variant loads directly into LDS and needs even K, N, lda, ldb and offsets");
   return plan_upload_split(c, pl, mainv, tailv[0], shape, order, tail_shape, tail_chunks);
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <vector>
 
 #include "ghmi_gemm.h"
@@ -165,27 +166,174 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(const GemmTile* __restr
     }
 }
 
+// Direct-to-LDS variant: the k-slices go from global memory straight into
+// LDS with the gfx950 global_load_lds_dwordx4 (16 bytes per lane, written to
+// LDS in lane order at a wave-uniform base), so no registers stage them and no
+// LDS stores are issued.  BK = 16.  The LDS layouts are chosen so that the
+// fragment reads of a half-wave (32 lanes) touch every LDS bank once:
+//   A slice: 16-byte k-pairs; one load instruction (a, b) brings rows
+//     16a .. 16a+15 and k-pairs 4b .. 4b+3, lane l = 16 (kp % 4) + m % 16.
+//   B slice: [16][BN] with the k-pairs of odd rows XOR-ed by 8 (128 bytes), so
+//     two consecutive k rows fall in opposite halves of the banks.
+// Rows past M and columns past N read clamped (finite) data that only reaches
+// outputs that are never stored; a ragged last k-slice is clamped the same
+// way and its A entries past K are zeroed in LDS before use.  Needs even K,
+// lda, ldb, a_off and N, and 16-byte aligned A and B (checked on the host).
+typedef __attribute__((address_space(1))) const void gvoid_t;
+typedef __attribute__((address_space(3))) void lvoid_t;
+
+template <int BM, int BN, int WGM, int WGN, int ROLE>
+__global__ __launch_bounds__(64 * WGM * WGN) void k_gemm_lds(const GemmTile* __restrict__ tiles,
+                                                             const GemmGroup* __restrict__ groups,
+                                                             const double* __restrict__ Abase,
+                                                             double* __restrict__ Cbase) {
+  constexpr int NW = WGM * WGN;
+  constexpr int BK = 16;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  static_assert(TM * 16 == WM && TN * 16 == WN, "wave sub-tile must be whole 16x16 blocks");
+  static_assert(BM % 16 == 0 && BN % 64 == 0 && BN <= 128, "A in 16-row groups, B rows of 64 or 128 doubles");
+  constexpr int AINS = (BM / 16) * 2;   // A load instructions per slice (1 KB each)
+  constexpr int BINS = BK * BN / 128;   // B load instructions per slice
+  constexpr int ASZ = BM * BK, BSZ = BK * BN;
+  __shared__ double lds[2][ASZ + BSZ];
+
+  const GemmTile t = tiles[blockIdx.x];
+  const GemmGroup G = groups[t.g];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave / WGN) * WM, wn = (wave % WGN) * WN;
+  const int M = G.M, N = G.N, K = G.K;
+  const double* __restrict__ Ag = Abase + G.a_off;
+  double* __restrict__ Cg = Cbase + G.c_off;
+
+  d4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  // Load instructions of one slice, spread evenly over the waves (wave index
+  // made uniform so that the LDS base goes to M0 without a loop over lanes).
+  static_assert(AINS % NW == 0 && BINS % NW == 0, "load instructions must split evenly over the waves");
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  const int a_m = lane & 15, a_kp = lane >> 4;
+  auto issue = [&](int k0, int buf) {
+#pragma unroll
+    for (int p = 0; p < AINS / NW; ++p) {
+      const int ins = wv + NW * p, a = ins >> 1, b = ins & 1;
+      const int row = min(t.m0 + 16 * a + a_m, M - 1);
+      const int k = min(k0 + 2 * (4 * b + a_kp), K - 2);
+      __builtin_amdgcn_global_load_lds((gvoid_t*)(Ag + (long long)row * G.lda + k), (lvoid_t*)&lds[buf][ins * 128],
+                                       16, 0, 0);
+    }
+#pragma unroll
+    for (int p = 0; p < BINS / NW; ++p) {
+      const int r = wv + NW * p;
+      const int e = r * 128 + 2 * lane;          // slice element of this lane's LDS pair
+      const int krow = e / BN, pos = (e % BN) >> 1;
+      const int pair = pos ^ ((krow & 1) << 3);  // the global pair that belongs there
+      const int k = min(k0 + krow, K - 1);
+      const int col = min(t.n0 + 2 * pair, N - 2);
+      __builtin_amdgcn_global_load_lds((gvoid_t*)(G.B + (long long)k * G.ldb + col),
+                                       (lvoid_t*)&lds[buf][ASZ + r * 128], 16, 0, 0);
+    }
+  };
+
+  const int nk = (K + BK - 1) / BK;
+  issue(0, 0);
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's loads of slice kt have landed in LDS
+    __syncthreads();                 // everyone's have, and slice kt-1 is no longer read
+    if (kt + 1 < nk) {
+      issue((kt + 1) * BK, buf ^ 1);
+    } else if (K - kt * BK < BK) {
+      // ragged last slice: zero A's k entries past K (k-pair layout)
+      const int kr = K - kt * BK;
+      for (int idx = tid; idx < BM * BK; idx += 64 * NW) {
+        const int ins = idx >> 7, w = idx & 127;
+        const int k = 2 * (4 * (ins & 1) + (w >> 5)) + (w & 1);
+        if (k >= kr) lds[buf][idx] = 0.0;
+      }
+      __syncthreads();
+    }
+    const double* As = lds[buf];
+    const double* Bs = lds[buf] + ASZ;
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      const int kr = kk * 4 + (lane >> 4);
+      double af[TM], bf[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int a = (wm >> 4) + i;
+        af[i] = As[((a * 2 + (kk >> 1)) * 64 + (2 * (kk & 1) + (lane >> 5)) * 16 + (lane & 15)) * 2 + ((lane >> 4) & 1)];
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int c = wn + j * 16 + (lane & 15);
+        bf[j] = Bs[kr * BN + (((c >> 1) ^ ((kr & 1) << 3)) << 1) + (c & 1)];
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+  }
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int col = t.n0 + wn + j * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = t.m0 + wm + i * 16 + (lane / 16) + 4 * v;
+        if (row < M && col < N) {
+          if (ROLE == 2) Cg[(long long)row * G.ldc + col] += acc[i][j][v];
+          else Cg[(long long)row * G.ldc + col] = acc[i][j][v];
+        }
+      }
+    }
+}
+
 }  // namespace
 
 namespace ghk {
 
 // Kernel variants the autotuner chooses from: tile BM x BN, WGM x WGN waves,
 // A layout in LDS (row-major padded or k-major).
+// Shapes 13 .. 16 load their k-slices directly into LDS (k_gemm_lds); each
+// has a register-staged twin of the same tile (7, 6, 9 and the 256 x 128
+// instantiation below) that a launch falls back to when A's base address is
+// not 16-byte aligned.  Both give bitwise the same result.
 struct TileShape {
   int bm, bn, wgm, wgn;
   bool arow;
   int bk;
+  bool direct;
 };
 static const TileShape kTiles[NUM_TILE_SHAPES] = {
-    {64, 64, 2, 2, false, 16},  {64, 128, 2, 2, false, 16}, {128, 64, 2, 2, false, 16},
-    {128, 128, 2, 2, false, 16}, {96, 64, 2, 2, false, 16},  {96, 64, 2, 2, true, 16},
-    {128, 64, 4, 2, true, 16},  {128, 128, 4, 2, true, 16}, {64, 128, 2, 4, true, 16},
-    {192, 64, 4, 2, true, 16},  {128, 64, 4, 2, true, 32},  {192, 64, 4, 2, true, 32},
-    {128, 128, 4, 2, true, 32}};
+    {64, 64, 2, 2, false, 16, false},  {64, 128, 2, 2, false, 16, false}, {128, 64, 2, 2, false, 16, false},
+    {128, 128, 2, 2, false, 16, false}, {96, 64, 2, 2, false, 16, false},  {96, 64, 2, 2, true, 16, false},
+    {128, 64, 4, 2, true, 16, false},  {128, 128, 4, 2, true, 16, false}, {64, 128, 2, 4, true, 16, false},
+    {192, 64, 4, 2, true, 16, false},  {128, 64, 4, 2, true, 32, false},  {192, 64, 4, 2, true, 32, false},
+    {128, 128, 4, 2, true, 32, false}, {128, 128, 4, 2, true, 16, true},  {128, 64, 4, 2, true, 16, true},
+    {192, 64, 4, 2, true, 16, true},   {256, 128, 4, 2, true, 16, true}};
 
 void tile_dims(int shape, int* bm, int* bn) {
   *bm = kTiles[shape].bm;
   *bn = kTiles[shape].bn;
+}
+
+bool shape_fits(int shape, const std::vector<GemmGroup>& groups) {
+  if (shape < 0 || shape >= NUM_TILE_SHAPES) return false;
+  if (!kTiles[shape].direct) return true;
+  for (const auto& g : groups)
+    if ((g.K & 1) || (g.N & 1) || (g.lda & 1) || (g.ldb & 1) || (g.a_off & 1) ||
+        (reinterpret_cast<uintptr_t>(g.B) & 15))
+      return false;
+  return true;
 }
 
 template <int ROLE>
@@ -211,15 +359,53 @@ static hipError_t gemm_role(int shape, const GemmTile* tiles, int n_tiles, const
     GH_GEMM_CASE(10, 128, 64, 4, 2, true, 32)
     GH_GEMM_CASE(11, 192, 64, 4, 2, true, 32)
     GH_GEMM_CASE(12, 128, 128, 4, 2, true, 32)
+    GH_GEMM_CASE(17, 256, 128, 4, 2, true, 16)
     default: return hipErrorInvalidValue;
   }
 #undef GH_GEMM_CASE
   return hipGetLastError();
 }
 
+template <int ROLE>
+static hipError_t gemm_direct(int shape, const GemmTile* tiles, int n_tiles, const GemmGroup* groups,
+                              const double* Abase, double* Cbase, hipStream_t st) {
+  if (reinterpret_cast<uintptr_t>(Abase) & 15) {
+    static const int twin[4] = {7, 6, 9, 17};
+    return gemm_role<ROLE>(twin[shape - 13], tiles, n_tiles, groups, Abase, Cbase, st);
+  }
+  dim3 grid(n_tiles);
+#define GH_GEMM_DIRECT(i, BM_, BN_, WGM_, WGN_)                                                            \
+  case i:                                                                                                  \
+    hipLaunchKernelGGL((k_gemm_lds<BM_, BN_, WGM_, WGN_, ROLE>), grid, dim3(64 * WGM_ * WGN_), 0, st, tiles, \
+                       groups, Abase, Cbase);                                                              \
+    break;
+  switch (shape) {
+    GH_GEMM_DIRECT(13, 128, 128, 4, 2)
+    GH_GEMM_DIRECT(14, 128, 64, 4, 2)
+    GH_GEMM_DIRECT(15, 192, 64, 4, 2)
+    GH_GEMM_DIRECT(16, 256, 128, 4, 2)
+    default: return hipErrorInvalidValue;
+  }
+#undef GH_GEMM_DIRECT
+  return hipGetLastError();
+}
+
 hipError_t gemm(int shape, const GemmTile* tiles, int n_tiles, const GemmGroup* groups,
                 const double* Abase, double* Cbase, hipStream_t st, int role) {
   if (n_tiles <= 0) return hipSuccess;
+  if (shape >= 13 && shape < NUM_TILE_SHAPES) {
+    switch (role) {
+      case 0: return gemm_direct<0>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
+      case 1: return gemm_direct<1>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
+      case 2: return gemm_direct<2>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
+      case 3: return gemm_direct<3>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
+      case 4: return gemm_direct<4>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
+      case 5: return gemm_direct<5>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
+      case 6: return gemm_direct<6>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
+      case 7: return gemm_direct<7>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (role) {
     case 0: return gemm_role<0>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
     case 1: return gemm_role<1>(shape, tiles, n_tiles, groups, Abase, Cbase, st);
