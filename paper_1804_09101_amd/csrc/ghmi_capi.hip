@@ -497,8 +497,10 @@ int autotune(gh_ctx* c, GemmPlan& pl, const double* src, double* dst, int role) 
     }
   }
   // the fastest variant split for whole rounds of tiles, its tail rows in
-  // smaller tiles of another variant
+  // smaller tiles of another variant; kept only when at least 1% faster than
+  // one launch (closer timings flip from run to run)
   int best_tail = -1, best_chunks = 0;
+  best *= 0.99f;
   std::vector<GemmGroup> mainv, tailv;
   if (split_rows(pl.groups, best_shape, c->n_cu, mainv, tailv) && tailv.size() == 1) {
     int bm, bn;
