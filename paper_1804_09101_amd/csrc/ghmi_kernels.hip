@@ -289,22 +289,34 @@ __global__ __launch_bounds__(256) void k_pointwise_rhs(
     }
 
   const long long ob = ub;
+  // The 15 spherical derivatives of pair n + 1 (dR, dA_theta, dA_phi of psi,
+  // Pi and the three Phi) are loaded before pair n is computed, and the
+  // scheduling barrier keeps the compiler from sinking them to their use: at
+  // one wave per SIMD nothing else would hide their latency.
+  auto load_pair = [&](int n, double (&raw)[15]) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      const int f = c < 2 ? 10 * c + n : 20 + 10 * (c - 2) + n;
+      const long long fo = (long long)f * P, fa = (long long)f * astride;
+      raw[3 * c] = dR[ub + fo];
+      raw[3 * c + 1] = dA[ab + fa];
+      raw[3 * c + 2] = dA[ab + fa + s.S];
+    }
+  };
+  double raw[2][15];
+  load_pair(0, raw[0]);
 #pragma unroll
   for (int n = 0; n < 10; ++n) {
+    if (n + 1 < 10) load_pair(n + 1, raw[(n + 1) & 1]);
+    __builtin_amdgcn_sched_barrier(0);
+    const double* rw = raw[n & 1];
     double dpsi[3], dPi[3], dPhi[3][3];   // dPhi[k][i] = d_k Phi_i
-    {
-      const long long fo = (long long)n * P, fa = (long long)n * astride;
-      cart(J, dR[ub + fo], dA[ab + fa], dA[ab + fa + s.S], dpsi);
-    }
-    {
-      const long long fo = (long long)(10 + n) * P, fa = (long long)(10 + n) * astride;
-      cart(J, dR[ub + fo], dA[ab + fa], dA[ab + fa + s.S], dPi);
-    }
+    cart(J, rw[0], rw[1], rw[2], dpsi);
+    cart(J, rw[3], rw[4], rw[5], dPi);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const long long fo = (long long)(20 + 10 * i + n) * P, fa = (long long)(20 + 10 * i + n) * astride;
       double d[3];
-      cart(J, dR[ub + fo], dA[ab + fa], dA[ab + fa + s.S], d);
+      cart(J, rw[6 + 3 * i], rw[7 + 3 * i], rw[8 + 3 * i], d);
       dPhi[0][i] = d[0]; dPhi[1][i] = d[1]; dPhi[2][i] = d[2];
     }
     const double adv_psi = G.Nu[0] * dpsi[0] + G.Nu[1] * dpsi[1] + G.Nu[2] * dpsi[2];
