@@ -304,10 +304,18 @@ __global__ __launch_bounds__(256) void k_pointwise_rhs(
     }
   };
   double raw[2][15];
+  double H[4], dHr[16];   // the background's gauge source terms, loaded with the last pair
   load_pair(0, raw[0]);
 #pragma unroll
   for (int n = 0; n < 10; ++n) {
-    if (n + 1 < 10) load_pair(n + 1, raw[(n + 1) & 1]);
+    if (n + 1 < 10) {
+      load_pair(n + 1, raw[(n + 1) & 1]);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) H[c] = Hin[4LL * s.pt_off + (long long)c * P + q];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) dHr[c] = dHin[16LL * s.pt_off + (long long)c * P + q];
+    }
     __builtin_amdgcn_sched_barrier(0);
     const double* rw = raw[n & 1];
     double dpsi[3], dPi[3], dPhi[3][3];   // dPhi[k][i] = d_k Phi_i
@@ -342,9 +350,7 @@ __global__ __launch_bounds__(256) void k_pointwise_rhs(
   // --- algebraic part of d_t Pi
   double Gm[4][10];
   christoffel(G, Pi, Phi, Gm);
-  double H[4], Hup[4], C[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) H[c] = Hin[4LL * s.pt_off + (long long)c * P + q];
+  double Hup[4], C[4];
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
     double s1 = 0.0;
@@ -396,13 +402,12 @@ __global__ __launch_bounds__(256) void k_pointwise_rhs(
     for (int j = 0; j < 3; ++j)
       v[j] = tPi[0] * G.gi[SYM3(0, j)] + tPi[1] * G.gi[SYM3(1, j)] + tPi[2] * G.gi[SYM3(2, j)];
   }
-  const long long hb = 16LL * s.pt_off + q;
 #pragma unroll
   for (int aa = 0; aa < 4; ++aa)
 #pragma unroll
     for (int bb = aa; bb < 4; ++bb) {
       const int n = SYM(aa, bb);
-      const double dHs = dHin[hb + (long long)(aa * 4 + bb) * P] + dHin[hb + (long long)(bb * 4 + aa) * P];
+      const double dHs = dHr[aa * 4 + bb] + dHr[bb * 4 + aa];
       const double GH = Hup[0] * Gm[0][n] + Hup[1] * Gm[1][n] + Hup[2] * Gm[2][n] + Hup[3] * Gm[3][n];
       const double vPhi = v[0] * Phi[n] + v[1] * Phi[10 + n] + v[2] * Phi[20 + n];
       // t_a = (-N, 0, 0, 0)

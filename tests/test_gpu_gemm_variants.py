@@ -45,6 +45,31 @@ def test_every_variant_and_order():
         assert ei.value.code == -1
 
 
+def test_misaligned_state_runs_on_the_staged_twin():
+    """The direct-to-LDS variants (13-16) move A with 16-byte loads; a state
+    whose base is only 8-byte aligned (a view one double into a buffer) runs on
+    the register-staged twin of the same tile, which accumulates in the same
+    order: bitwise the same RHS, and the oracle's to 1e-12."""
+    shells = [(0, 7, 7, 1.8, 2.7), (0, 9, 7, 2.7, 4.0), (1, 6, 11, 1.6, 3.1)]
+    holes = [(1.0, 0.0, (0, 0, 1)), (1.0, 0.5, (0.3, -0.2, 0.9))]
+    c = Case(_wl("misaligned", shells, holes), pert_amp=1e-3, seed=5)
+    u = dev(c.u0)
+    buf = torch.empty(u.numel() + 1, dtype=torch.float64, device=u.device)
+    um = buf[1:]
+    um.copy_(u)
+    assert u.data_ptr() % 16 == 0 and um.data_ptr() % 16 == 8
+    ref = c.oracle_rhs(c.u0)
+    scale = max(np.max(np.abs(ref)), c.term_scale(c.u0))
+    for shape in (13, 14, 15, 16):
+        c.s.set_gemm_variant(0, shape, 1)
+        a = c.s.rhs(u)
+        b = c.s.rhs(um)
+        e = float(np.max(np.abs(b.cpu().numpy() - ref)) / scale)
+        print(f"  variant {shape}: misaligned vs aligned {'bitwise' if torch.equal(a, b) else 'DIFFERENT'}, "
+              f"vs oracle {e:.2e}", flush=True)
+        assert torch.equal(a, b) and e < 1e-12
+
+
 def test_split_plan_matches_one_launch():
     """pulse_8shell's derivative GEMM has 1 056 tiles of 128 x 64, 4.125 per
     CU of the MI355X: the tuner may split it into whole rounds plus a tail over
