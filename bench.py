@@ -655,6 +655,32 @@ def pulse_8shell_measurement(args):
     return out
 
 
+def reverse_only(n=20):
+    """Reverse RK3 steps of the 8-shell workload from one state and one
+    cotangent, with events around every launch (per-kind averages)."""
+    import torch
+    from paper_1804_09101_amd import configs, ghmi
+    wl = configs.pulse_8shell()
+    s, u0 = upload_workload(wl)
+    lam = torch.from_numpy(np.random.default_rng(3).standard_normal(u0.numel())).to(u0.device)
+    out = s.step_vjp(u0, lam)
+    torch.cuda.synchronize()
+    s.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(n):
+        s.step_vjp(u0, lam, out=out)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    kinds = {}
+    for k in ghmi.KERNEL_KINDS:
+        cnt, ms = s.kernel_stats(k)
+        if cnt:
+            kinds[k] = {"launches": cnt, "avg_us": ms / cnt * 1e3}
+    s.set_timing(False)
+    return {"workload": "pulse_8shell reverse steps", "steps": n, "ms_per_reverse_step": t / n * 1e3,
+            "note": "events around every launch", "kernels": kinds}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -674,6 +700,9 @@ def main():
                     help="skip the 4-instance batch of the 20-shell domain (forward and adjoint)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (reference for HBM byte counters)")
+    ap.add_argument("--reverse-only", action="store_true",
+                    help="only time 20 reverse RK3 steps (gh_step_vjp) of the 8-shell workload, per kernel kind "
+                         "(a short run for the counters of the reverse kernels)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU only: the path would shard by instance or by shell across "
@@ -696,6 +725,9 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
+    if args.reverse_only:
+        print(json.dumps(reverse_only()))
+        return
 
     calib = calibration()
     log(f"calibration: device copy {calib['copy_gb_s']:.0f} GB/s")
