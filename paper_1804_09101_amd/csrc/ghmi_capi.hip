@@ -125,6 +125,11 @@ struct gh_ctx {
   double *d_ktab = nullptr, *d_X = nullptr;
   PtBlock* d_tblk = nullptr;                 // blocks of the theta step: 16 rows x 256 (node, column) pairs
   int n_tblk = 0, tr_nmax = 0;
+  // the matrix-core theta step for shells with n = L + 1 in {16, 32, 48, 64}:
+  // the transposed kernel table and the work items per n
+  double* d_ktabT = nullptr;
+  ThetaItem* d_titem[4] = {nullptr, nullptr, nullptr, nullptr};
+  int n_titem[4] = {0, 0, 0, 0};
   std::map<int, double*> d_fana, d_fsyn;    // per L: Fourier analysis [2n][2n] and synthesis (its transpose)
   GemmPlan tr_ana, tr_syn, tr_fsyn;
 
@@ -263,6 +268,11 @@ void free_domain(gh_ctx* c) {
   c->have_tr = false;
   c->d_ktab = c->d_X = nullptr;
   c->d_tblk = nullptr;
+  c->d_ktabT = nullptr;
+  for (int k = 0; k < 4; ++k) {
+    c->d_titem[k] = nullptr;
+    c->n_titem[k] = 0;
+  }
   c->n_tblk = c->tr_nmax = 0;
   c->d_fana.clear();
   c->d_fsyn.clear();
@@ -571,6 +581,16 @@ int validate_shells(int n_inst, int n_shells, const gh_shell* s, std::string& wh
 // All derivative work of one RHS: the angular GEMM and the radial derivative.
 // Radial (dR, [50] layout) and angular (dA, [100] layout) derivatives of u;
 // into the context's work space unless targets are given.
+// The theta step of the transform path (d_W -> d_X): the matrix-core kernel
+// for shells with n a multiple of 16, the register kernel for the others.
+int queue_theta(gh_ctx* c, int mode) {
+  HIPCHK(c, ghk::ang_theta(c->tr_nmax, c->d_sh, c->d_tblk, c->n_tblk, c->d_ktab, c->d_W, c->d_X, mode, c->stream));
+  for (int g = 0; g < 4; ++g)
+    HIPCHK(c, ghk::ang_theta_mfma(16 * (g + 1), c->d_sh, c->d_titem[g], c->n_titem[g], c->d_ktabT, c->d_W, c->d_X,
+                                  mode, c->stream));
+  return GH_OK;
+}
+
 int queue_derivs(gh_ctx* c, const double* u, double* dR = nullptr, double* dA = nullptr) {
   if (!dR) dR = c->d_dR;
   if (!dA) dA = c->d_dA;
@@ -580,7 +600,8 @@ int queue_derivs(gh_ctx* c, const double* u, double* dR = nullptr, double* dA = 
     Timed t(c, 8);
     HIPCHK(c, launch_plan(c->tr_ana, u, c->d_W,
                         c->stream, 4));
-    HIPCHK(c, ghk::ang_theta(c->tr_nmax, c->d_sh, c->d_tblk, c->n_tblk, c->d_ktab, c->d_W, c->d_X, 0, c->stream));
+    int rc;
+    if ((rc = queue_theta(c, 0))) return rc;
     HIPCHK(c, launch_plan(c->tr_syn, c->d_X, dA,
                         c->stream, 5));
   } else {
@@ -639,7 +660,8 @@ int queue_filter(gh_ctx* c, const double* src, double* dst) {
   if (c->filt_tr) {
     HIPCHK(c, launch_plan(c->tr_ana, src, c->d_W,
                         c->stream, 4));
-    HIPCHK(c, ghk::ang_theta(c->tr_nmax, c->d_sh, c->d_tblk, c->n_tblk, c->d_ktab, c->d_W, c->d_X, 1, c->stream));
+    int rc;
+    if ((rc = queue_theta(c, 1))) return rc;
     HIPCHK(c, launch_plan(c->tr_fsyn, c->d_X, dst,
                         c->stream, 5));
   } else {
@@ -1442,21 +1464,52 @@ int ensure_transform(gh_ctx* c) {
     c->d_fsyn[L] = dS;
   }
   if ((rc = upload(c, &c->d_ktab, ktab))) return rc;
+  // per order transposed ([kind][m][i'][i]) for the matrix-core theta step
+  std::vector<double> ktabT(ktab.size());
+  for (const auto& kv : kt_off) {
+    const int n = kv.first + 1;
+    const long long n2 = (long long)n * n;
+    for (long long km = 0; km < 3LL * n; ++km)
+      for (int i = 0; i < n; ++i)
+        for (int ip = 0; ip < n; ++ip) ktabT[kv.second + km * n2 + (long long)ip * n + i] = ktab[kv.second + km * n2 + (long long)i * n + ip];
+  }
+  if ((rc = upload(c, &c->d_ktabT, ktabT))) return rc;
   for (int k = 0; k < c->n_shells; ++k) c->h_sh[k].kt_off = kt_off[c->shells[k].L];
   HIPCHK(c, hipMemcpy(c->d_sh, c->h_sh.data(), c->h_sh.size() * sizeof(ShellDev), hipMemcpyHostToDevice));
   if ((rc = dalloc(c, &c->d_X, size_t(100) * c->P))) return rc;
-  // theta-step blocks: per shell, chunks of 16 (field, radius) rows x 256 (node, column) pairs
+  // theta step: shells with n = L + 1 a multiple of 16 on the matrix cores
+  // (items of 8 rows x 8 orders, per n); the others in blocks of 16 (field,
+  // radius) rows x 256 (node, column) pairs
   std::vector<PtBlock> tb;
+  std::vector<ThetaItem> ti[4];
   int maxn = 0;
   for (int k = 0; k < c->n_shells; ++k) {
-    const int S = c->h_sh[k].S, rows = 50 * c->shells[k].n_r;
-    maxn = std::max(maxn, c->shells[k].L + 1);
+    const int S = c->h_sh[k].S, rows = 50 * c->shells[k].n_r, n = c->shells[k].L + 1;
+    if (n % 16 == 0) {
+      // Workgroups go round-robin over the 8 XCDs, so the items are ordered
+      // in groups of 8 row blocks, order block after order block: every
+      // order block of a row block then runs on the same XCD in consecutive
+      // rounds, and the partial 128-byte lines each one writes (and reads)
+      // meet in that XCD's L2.  Groups are padded to 8 (r0 = -1: no work).
+      std::vector<ThetaItem>& v = ti[n / 16 - 1];
+      while (v.size() % 8) v.push_back(ThetaItem{k, -1, 0, 0});
+      const int nrb = (rows + 7) / 8;
+      for (int g0 = 0; g0 < nrb; g0 += 8)
+        for (int m0 = 0; m0 < n; m0 += 8)
+          for (int rb = g0; rb < g0 + 8; ++rb) v.push_back(ThetaItem{k, rb < nrb ? 8 * rb : -1, m0, 0});
+      continue;
+    }
+    maxn = std::max(maxn, n);
     for (int r0 = 0; r0 < rows; r0 += 16)
       for (int a0 = 0; a0 < S; a0 += 256) tb.push_back(PtBlock{k, r0 * S + a0});
   }
   c->tr_nmax = maxn <= 16 ? 16 : (maxn <= 32 ? 32 : 64);
   c->n_tblk = int(tb.size());
-  if ((rc = upload(c, &c->d_tblk, tb))) return rc;
+  if (!tb.empty() && (rc = upload(c, &c->d_tblk, tb))) return rc;
+  for (int g = 0; g < 4; ++g) {
+    c->n_titem[g] = int(ti[g].size());
+    if (!ti[g].empty() && (rc = upload(c, &c->d_titem[g], ti[g]))) return rc;
+  }
   // plans over maximal runs of consecutive shells with the same L: a state is
   // a [rows * n x 2n] matrix (rows = (field, radius) pairs), the theta output a
   // [rows * 2n x 2n] one laid out like the angular derivatives

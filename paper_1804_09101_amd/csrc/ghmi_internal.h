@@ -31,6 +31,14 @@ struct PtBlock {
   int q0;             // first local point index (r*S + a)
 };
 
+// Work item of the matrix-core theta step: 8 rows from r0, orders m0 .. m0+7.
+struct ThetaItem {
+  int shell;
+  int r0;
+  int m0;
+  int pad;
+};
+
 // Tensor-coupled filter, the coupling step on the coefficient array X (per
 // shell [field][radius][nsp]): Y = F X for every column (shell, radius).
 // The rows of F come in segments: rows (e, s) with e0 <= e < e0 + ne and
@@ -86,6 +94,11 @@ hipError_t fill_int(int* x, int n, int value, hipStream_t st);
 // 256 pairs; nmax: 16, 32 or 64 >= L + 1 of every shell.
 hipError_t ang_theta(int nmax, const ShellDev* sh, const PtBlock* tblk, int n_tblk, const double* ktab,
                      const double* AB, double* X, int mode, hipStream_t st);
+// The same step on the matrix cores for the shells with n = L + 1 (16, 32,
+// 48 or 64; one launch per n): items of 8 rows x 8 orders; ktabT: the
+// kernel table transposed per order ([3][n][i'][i], same offsets as ktab).
+hipError_t ang_theta_mfma(int n, const ShellDev* sh, const ThetaItem* items, int n_items, const double* ktabT,
+                          const double* AB, double* X, int mode, hipStream_t st);
 
 hipError_t fill_pattern(double* x, long long n, hipStream_t st);
 

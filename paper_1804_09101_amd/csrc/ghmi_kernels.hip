@@ -1286,6 +1286,122 @@ __global__ __launch_bounds__(256) void k_ang_theta(const ShellDev* __restrict__ 
 
 
 // ---------------------------------------------------------------------------
+// The theta step on the matrix cores, for shells with n = L + 1 a multiple of
+// 16 (v_mfma_f64_16x16x4_f64).  A work item is 8 rows x 8 orders m0 .. m0+7.
+// For one order m the step is a product
+//   C[i][(r, c)] = sum_i' K_m[i][i'] W_m[i'][(r, c)],
+// with the 16 columns (r, c) = (row r0 + r, c = 0 cos / 1 sin) of the item.
+// The item's coefficient columns are staged in LDS as [i'][m][c][r], 16
+// doubles per (i', m), each i' row padded by 16 doubles: consecutive i' then
+// fall in opposite halves of the banks, so the B operands of a half-wave hit
+// every bank once.  The kernel rows come from the transposed table
+// ktabT[kind][m][i'][i] as MFMA A operands (16 consecutive i per
+// quarter-wave).  Four waves take two orders each.  Each workgroup reads and
+// writes whole 64-byte segments (the 8 orders of one (row, node, c)); the
+// host orders the items so that the other segments of the same lines are
+// handled on the same XCD.  Items with r0 < 0 are padding.  The results are
+// stored through LDS in whole 64-byte runs (see below).
+// ---------------------------------------------------------------------------
+template <int N, int MODE>
+__global__ __launch_bounds__(256) void k_ang_theta_mfma(const ShellDev* __restrict__ sh,
+                                                        const ThetaItem* __restrict__ items,
+                                                        const double* __restrict__ ktabT,
+                                                        const double* __restrict__ AB, double* __restrict__ X) {
+  constexpr int R = 8, MB = 8, NB = N / 16, KS = N / 4;
+  constexpr int ROWLEN = MB * 2 * R + 16;
+  static_assert(N % 16 == 0, "n must be a multiple of 16");
+  __shared__ double Ws[N * ROWLEN];
+  const ThetaItem it = items[blockIdx.x];
+  if (it.r0 < 0) return;   // padding of the XCD grouping
+  const ShellDev s = sh[it.shell];
+  const int nc = 2 * N, S = s.S;
+  const int nrows = 50 * s.n_r;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double* __restrict__ Wg = AB + 50LL * s.pt_off;
+  // stage the item's columns: 16-byte loads of two consecutive orders
+  for (int idx = tid; idx < R * N * 2 * (MB / 2); idx += 256) {
+    const int mp2 = idx % (MB / 2);
+    int t = idx / (MB / 2);
+    const int c = t & 1;
+    t >>= 1;
+    const int ip = t % N, r = t / N;
+    const int row = min(it.r0 + r, nrows - 1);
+    const double2 v =
+        *reinterpret_cast<const double2*>(Wg + (long long)row * S + ip * nc + c * N + it.m0 + 2 * mp2);
+    Ws[ip * ROWLEN + (4 * mp2 + c) * R + r] = v.x;
+    Ws[ip * ROWLEN + (4 * mp2 + 2 + c) * R + r] = v.y;
+  }
+  __syncthreads();
+  const double* __restrict__ Kt = ktabT + s.kt_off;
+  const long long n3 = (long long)N * N * N, n2 = (long long)N * N;
+  const int col = lane & 15, q = lane >> 4;
+  d4 rA[MB / 4][NB], rB[MB / 4][NB];
+#pragma unroll
+  for (int w = 0; w < MB / 4; ++w) {
+    const int m = it.m0 + wave + 4 * w;
+    const double* __restrict__ KA = Kt + (MODE == 0 ? 0 : 2 * n3) + m * n2;   // d/dtheta or filter
+    const double* __restrict__ KB = Kt + n3 + m * n2;                         // d/dphi
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi) {
+      rA[w][bi] = d4{0.0, 0.0, 0.0, 0.0};
+      rB[w][bi] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int ip = ks * 4 + q;
+      const double b = Ws[ip * ROWLEN + (wave + 4 * w) * 16 + col];
+#pragma unroll
+      for (int bi = 0; bi < NB; ++bi) {
+        const int i = bi * 16 + col;
+        rA[w][bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(KA[ip * N + i], b, rA[w][bi], 0, 0, 0);
+        if (MODE == 0) rB[w][bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(KB[ip * N + i], b, rB[w][bi], 0, 0, 0);
+      }
+    }
+  }
+  // The results go out through LDS (the staging buffer, free again), one
+  // part at a time (d/dtheta or the filter; then d/dphi with its cos and sin
+  // slots exchanged and the sin one negated), as runs of the item's 8
+  // orders: 64 bytes per (row, node, slot), written by 4 lanes at once.  In
+  // LDS a run of row r, node i, slot c sits at r * OST + i * 16 + c * 8: the
+  // row stride is odd, so the 32 (r, c, node parity) of a half-wave's stores
+  // fall in distinct banks.
+  constexpr int OST = N * 16 + 1;
+  static_assert(R * OST <= N * ROWLEN, "the output runs fit in the staging buffer");
+  const int rr = col & 7, c = col >> 3;
+  const int nrun = R * N * 2;
+#pragma unroll
+  for (int part = 0; part < (MODE == 0 ? 2 : 1); ++part) {
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < MB / 4; ++w)
+#pragma unroll
+      for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = bi * 16 + q + 4 * v;
+          const int slot = part == 0 ? c : 1 - c;
+          const double val = part == 0 ? rA[w][bi][v] : (c == 0 ? rB[w][bi][v] : -rB[w][bi][v]);
+          Ws[rr * OST + i * 16 + slot * 8 + wave + 4 * w] = val;
+        }
+    __syncthreads();
+    for (int idx = tid; idx < nrun * 4; idx += 256) {
+      const int run = idx >> 2, h = idx & 3;
+      const int r = run / (2 * N), rem = run - r * 2 * N, i = rem >> 1, sl = rem & 1;
+      const int row = it.r0 + r;
+      if (row >= nrows) continue;
+      const double* o = Ws + r * OST + i * 16 + sl * 8 + 2 * h;
+      double2 val;
+      val.x = o[0];
+      val.y = o[1];
+      double* dst = MODE == 0 ? X + 100LL * s.pt_off + (long long)row * 2 * S + part * S
+                              : X + 50LL * s.pt_off + (long long)row * S;
+      *reinterpret_cast<double2*>(dst + i * nc + sl * N + it.m0 + 2 * h) = val;
+    }
+  }
+}
+
+
+// ---------------------------------------------------------------------------
 // Tensor-coupled filter: the coupling step Y = F X on the angular
 // coefficients.  One workgroup (16 waves) per work item (segment, NC columns
 // (shell, radius), a range of slices): the segment's inputs are staged in
@@ -1725,8 +1841,27 @@ hipError_t fill_int(int* x, int n, int value, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t ang_theta_mfma(int n, const ShellDev* sh, const ThetaItem* items, int n_items, const double* ktabT,
+                          const double* AB, double* X, int mode, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  dim3 grid(n_items), block(256);
+#define GH_ANGM(NN)                                                                                         \
+  if (mode == 0) hipLaunchKernelGGL((k_ang_theta_mfma<NN, 0>), grid, block, 0, st, sh, items, ktabT, AB, X); \
+  else hipLaunchKernelGGL((k_ang_theta_mfma<NN, 1>), grid, block, 0, st, sh, items, ktabT, AB, X);
+  switch (n) {
+    case 16: GH_ANGM(16) break;
+    case 32: GH_ANGM(32) break;
+    case 48: GH_ANGM(48) break;
+    case 64: GH_ANGM(64) break;
+    default: return hipErrorInvalidValue;
+  }
+#undef GH_ANGM
+  return hipGetLastError();
+}
+
 hipError_t ang_theta(int nmax, const ShellDev* sh, const PtBlock* tblk, int n_tblk, const double* ktab,
                      const double* AB, double* X, int mode, hipStream_t st) {
+  if (n_tblk <= 0) return hipSuccess;
   dim3 grid(n_tblk), block(256);
 #define GH_ANG(NM)                                                                                        \
   if (mode == 0) hipLaunchKernelGGL((k_ang_theta<NM, 0>), grid, block, 0, st, sh, tblk, ktab, AB, X);   \
