@@ -315,7 +315,7 @@ int gh_query(const gh_ctx* ctx, int what, long long* value);
 /* Pin the kernel variant and tile order of a GEMM plan instead of the
  * autotuner's choice (for reproducible timing, and to check every variant):
  * plan 0: the angular derivative GEMM, 1: the filter GEMM (filter_kind 1);
- * shape: variant index 0 .. 16 (tile, wave layout, LDS layout, k-slice depth;
+ * shape: variant index 0 .. 17 (tile, wave layout, LDS layout, k-slice depth;
  * gh_query 6/7 report the current one); order 0: column blocks per XCD, 1:
  * row blocks, 2: blocks of 8 x 8 tiles.  A pinned plan is one launch (no
  * tail).  GH_ERR_ARG otherwise.

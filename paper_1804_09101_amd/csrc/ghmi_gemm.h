@@ -25,13 +25,13 @@ struct GemmTile {
 namespace ghk {
 
 // Grouped GEMM (ghmi_gemm.hip).  shape: index of a kernel variant (tile
-// BM x BN, wave layout, LDS layout of A, k-slice depth; 13 .. 16 load the
+// BM x BN, wave layout, LDS layout of A, k-slice depth; 13 .. 17 load the
 // slices directly into LDS and need shape_fits); order: 0 column blocks, 1 row
 // blocks or 2 blocks of 8 x 8 tiles per XCD.  role: 0 angular derivative, 1 filter, 2 transposed
 // derivative (C += A B), 3 transposed filter, 4 Fourier analysis, 5 Fourier
 // synthesis, 6 PhysToSpec and 7 SpecToPhys of the tensor-coupled filter
 // (separate kernel symbols).
-enum { NUM_TILE_SHAPES = 17, NUM_TILE_ORDERS = 3 };
+enum { NUM_TILE_SHAPES = 18, NUM_TILE_ORDERS = 3 };
 void tile_dims(int shape, int* bm, int* bn);
 // whether a variant can run these groups (the direct-to-LDS ones need even K,
 // N, lda, ldb and a_off, and a 16-byte aligned B)

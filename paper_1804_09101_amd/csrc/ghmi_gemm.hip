@@ -326,9 +326,9 @@ namespace ghk {
 
 // Kernel variants the autotuner chooses from: tile BM x BN, WGM x WGN waves,
 // A layout in LDS (row-major padded or k-major).
-// Shapes 13 .. 16 load their k-slices directly into LDS (k_gemm_lds); each
-// has a register-staged twin of the same tile (7, 6, 9 and the 256 x 128
-// instantiation below) that a launch falls back to when A's base address is
+// Shapes 13 .. 17 load their k-slices directly into LDS (k_gemm_lds); each
+// has a register-staged twin of the same tile (7, 6, 9, the 256 x 128
+// instantiation below, 3) that a launch falls back to when A's base address is
 // not 16-byte aligned.  Both give bitwise the same result.
 struct TileShape {
   int bm, bn, wgm, wgn;
@@ -342,7 +342,7 @@ static const TileShape kTiles[] = {
     {128, 64, 4, 2, true, 16, false},  {128, 128, 4, 2, true, 16, false}, {64, 128, 2, 4, true, 16, false},
     {192, 64, 4, 2, true, 16, false},  {128, 64, 4, 2, true, 32, false},  {192, 64, 4, 2, true, 32, false},
     {128, 128, 4, 2, true, 32, false}, {128, 128, 4, 2, true, 16, true},  {128, 64, 4, 2, true, 16, true},
-    {192, 64, 4, 2, true, 16, true},   {256, 128, 4, 2, true, 16, true}};
+    {192, 64, 4, 2, true, 16, true},   {256, 128, 4, 2, true, 16, true},  {128, 128, 2, 2, true, 16, true}};
 static_assert(sizeof(kTiles) / sizeof(kTiles[0]) == NUM_TILE_SHAPES, "one table row per tile shape");
 
 void tile_dims(int shape, int* bm, int* bn) {
@@ -394,7 +394,7 @@ template <int ROLE>
 static hipError_t gemm_direct(int shape, const GemmTile* tiles, int n_tiles, const GemmGroup* groups,
                               const double* Abase, double* Cbase, hipStream_t st) {
   if (reinterpret_cast<uintptr_t>(Abase) & 15) {
-    static const int twin[4] = {7, 6, 9, 100};
+    static const int twin[5] = {7, 6, 9, 100, 3};
     return gemm_role<ROLE>(twin[shape - 13], tiles, n_tiles, groups, Abase, Cbase, st);
   }
   dim3 grid(n_tiles);
@@ -408,6 +408,7 @@ static hipError_t gemm_direct(int shape, const GemmTile* tiles, int n_tiles, con
     GH_GEMM_DIRECT(14, 128, 64, 4, 2)
     GH_GEMM_DIRECT(15, 192, 64, 4, 2)
     GH_GEMM_DIRECT(16, 256, 128, 4, 2)
+    GH_GEMM_DIRECT(17, 128, 128, 2, 2)
     default: return hipErrorInvalidValue;
   }
 #undef GH_GEMM_DIRECT

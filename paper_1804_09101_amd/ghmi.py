@@ -30,7 +30,7 @@ EXPORTS = [
     "gh_constraints_static", "gh_set_outer_bc", "gh_set_gemm_plan",
 ]
 
-NUM_GEMM_VARIANTS = 17
+NUM_GEMM_VARIANTS = 18
 
 KERNEL_KINDS = {"deriv_gemm": 0, "filter_gemm": 1, "radial": 2, "pointwise": 3, "boundary": 4,
                 "rk_combine_vjp": 5, "pointwise_vjp": 6, "deriv_gemm_T": 7,

@@ -60,7 +60,7 @@ def test_misaligned_state_runs_on_the_staged_twin():
     assert u.data_ptr() % 16 == 0 and um.data_ptr() % 16 == 8
     ref = c.oracle_rhs(c.u0)
     scale = max(np.max(np.abs(ref)), c.term_scale(c.u0))
-    for shape in (13, 14, 15, 16):
+    for shape in (13, 14, 15, 16, 17):
         c.s.set_gemm_variant(0, shape, 1)
         a = c.s.rhs(u)
         b = c.s.rhs(um)
