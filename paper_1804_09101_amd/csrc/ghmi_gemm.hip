@@ -360,6 +360,31 @@ bool shape_fits(int shape, const std::vector<GemmGroup>& groups) {
   return true;
 }
 
+// The instantiated variants: (index, BM, BN, WGM, WGN, A row-major, BK) for
+// the register-staged kernel (100: the 256 x 128 twin of shape 16, not a
+// tuner choice), (index, BM, BN, WGM, WGN) for the direct-to-LDS one.
+#define GH_GEMM_STAGED_LIST(X)        \
+  X(0, 64, 64, 2, 2, false, 16)       \
+  X(1, 64, 128, 2, 2, false, 16)      \
+  X(2, 128, 64, 2, 2, false, 16)      \
+  X(3, 128, 128, 2, 2, false, 16)     \
+  X(4, 96, 64, 2, 2, false, 16)       \
+  X(5, 96, 64, 2, 2, true, 16)        \
+  X(6, 128, 64, 4, 2, true, 16)       \
+  X(7, 128, 128, 4, 2, true, 16)      \
+  X(8, 64, 128, 2, 4, true, 16)       \
+  X(9, 192, 64, 4, 2, true, 16)       \
+  X(10, 128, 64, 4, 2, true, 32)      \
+  X(11, 192, 64, 4, 2, true, 32)      \
+  X(12, 128, 128, 4, 2, true, 32)     \
+  X(100, 256, 128, 4, 2, true, 16)
+#define GH_GEMM_DIRECT_LIST(X) \
+  X(13, 128, 128, 4, 2)        \
+  X(14, 128, 64, 4, 2)         \
+  X(15, 192, 64, 4, 2)         \
+  X(16, 256, 128, 4, 2)        \
+  X(17, 128, 128, 2, 2)
+
 template <int ROLE>
 static hipError_t gemm_role(int shape, const GemmTile* tiles, int n_tiles, const GemmGroup* groups,
                             const double* Abase, double* Cbase, hipStream_t st) {
@@ -370,20 +395,7 @@ static hipError_t gemm_role(int shape, const GemmTile* tiles, int n_tiles, const
                        tiles, groups, Abase, Cbase);                                                       \
     break;
   switch (shape) {
-    GH_GEMM_CASE(0, 64, 64, 2, 2, false, 16)
-    GH_GEMM_CASE(1, 64, 128, 2, 2, false, 16)
-    GH_GEMM_CASE(2, 128, 64, 2, 2, false, 16)
-    GH_GEMM_CASE(3, 128, 128, 2, 2, false, 16)
-    GH_GEMM_CASE(4, 96, 64, 2, 2, false, 16)
-    GH_GEMM_CASE(5, 96, 64, 2, 2, true, 16)
-    GH_GEMM_CASE(6, 128, 64, 4, 2, true, 16)
-    GH_GEMM_CASE(7, 128, 128, 4, 2, true, 16)
-    GH_GEMM_CASE(8, 64, 128, 2, 4, true, 16)
-    GH_GEMM_CASE(9, 192, 64, 4, 2, true, 16)
-    GH_GEMM_CASE(10, 128, 64, 4, 2, true, 32)
-    GH_GEMM_CASE(11, 192, 64, 4, 2, true, 32)
-    GH_GEMM_CASE(12, 128, 128, 4, 2, true, 32)
-    GH_GEMM_CASE(100, 256, 128, 4, 2, true, 16)
+    GH_GEMM_STAGED_LIST(GH_GEMM_CASE)
     default: return hipErrorInvalidValue;
   }
 #undef GH_GEMM_CASE
@@ -404,11 +416,7 @@ static hipError_t gemm_direct(int shape, const GemmTile* tiles, int n_tiles, con
                        groups, Abase, Cbase);                                                              \
     break;
   switch (shape) {
-    GH_GEMM_DIRECT(13, 128, 128, 4, 2)
-    GH_GEMM_DIRECT(14, 128, 64, 4, 2)
-    GH_GEMM_DIRECT(15, 192, 64, 4, 2)
-    GH_GEMM_DIRECT(16, 256, 128, 4, 2)
-    GH_GEMM_DIRECT(17, 128, 128, 2, 2)
+    GH_GEMM_DIRECT_LIST(GH_GEMM_DIRECT)
     default: return hipErrorInvalidValue;
   }
 #undef GH_GEMM_DIRECT
