@@ -703,8 +703,10 @@ int queue_rhs(gh_ctx* c, const double* u, double* out) {
   return GH_OK;
 }
 
-// One SSP-RK3 stage: out = c0 u0 + c1 (us + dt L(us)).  The raw d_t u goes to
-// the work space; the stage kernel applies the boundary treatment on the fly.
+// One SSP-RK3 stage: out = c0 u0 + c1 (us + dt L(us)).  The pointwise kernel
+// writes the stage value of every point off the treated faces straight to
+// out, and the raw d_t u of the face points to the work space; the face
+// kernel then applies the boundary treatment there and finishes the stage.
 // With `keep` (150 P doubles) the derivatives of us are written there and kept.
 int queue_stage(gh_ctx* c, double c0, const double* u0, double c1, const double* us, double* out,
                 double* keep = nullptr) {
@@ -714,8 +716,8 @@ int queue_stage(gh_ctx* c, double c0, const double* u0, double c1, const double*
   if (rc) return rc;
   {
     Timed t(c, 3);
-    HIPCHK(c, ghk::pointwise_rhs(c->d_sh, c->d_blk, c->n_blk, c->d_angtab, c->d_radtab, us, dR, dA, c->d_H,
-                                 c->d_dH, c->d_gamma, c->d_W, c->stream));
+    HIPCHK(c, ghk::pointwise_stage(c->d_sh, c->d_blk, c->n_blk, c->d_angtab, c->d_radtab, us, dR, dA, c->d_H,
+                                   c->d_dH, c->d_gamma, c->d_W, c->d_dt, c0, u0, c1, out, c->stream));
   }
   {
     Timed t(c, 4);
@@ -724,8 +726,8 @@ int queue_stage(gh_ctx* c, double c0, const double* u0, double c1, const double*
     if (c->outer_mode)
       HIPCHK(c, ghk::outer_cpbc(c->d_sh, c->n_shells, c->max_S, c->d_angtab, c->d_radtab, us, dR, dA, c->d_gamma,
                                 c->d_W, c->stream));
-    HIPCHK(c, ghk::stage_bc(c->d_sh, c->d_blk, c->n_blk, tab, c->d_gamma, c->d_dt, c0, u0, c1, us, c->d_W,
-                            out, c->outer_mode, c->stream));
+    HIPCHK(c, ghk::stage_faces(c->d_sh, c->n_shells, c->max_S, tab, c->d_gamma, c->d_dt, c0, u0, c1, us, c->d_W,
+                               out, c->outer_mode, c->stream));
   }
   return GH_OK;
 }

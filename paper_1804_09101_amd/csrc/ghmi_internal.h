@@ -135,6 +135,20 @@ hipError_t pointwise_rhs(const ShellDev* sh, const PtBlock* blk, int n_blk, cons
                          const double* H, const double* dH, const double* gamma, double* rhs,
                          hipStream_t st);
 
+// d_t u of the stage state us and the SSP-RK3 stage out = c0 u0 + c1 (us + dt
+// L) in one pass: out gets every point off the treated faces, L (raw d_t u)
+// the points on them, for stage_faces.  out may alias u0.
+hipError_t pointwise_stage(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* angtab,
+                           const double* radtab, const double* us, const double* dR, const double* dA,
+                           const double* H, const double* dH, const double* gamma, double* L, const double* dt,
+                           double c0, const double* u0, double c1, double* out, hipStream_t st);
+
+// The treated faces of that stage: boundary treatment of L there (read only)
+// and the stage update.  out may alias u0.
+hipError_t stage_faces(const ShellDev* sh, int n_shells, int max_S, const double* bctab, const double* gamma,
+                       const double* dt, double c0, const double* u0, double c1, const double* us, const double* L,
+                       double* out, int outer_mode, hipStream_t st);
+
 // outer_mode 0: Dirichlet d_t u = 0 on outer faces; 1: outer faces left as
 // they are (already treated in place by outer_cpbc).
 hipError_t boundary(const ShellDev* sh, int n_shells, int max_S, const double* bctab,
@@ -145,12 +159,6 @@ hipError_t boundary(const ShellDev* sh, int n_shells, int max_S, const double* b
 hipError_t outer_cpbc(const ShellDev* sh, int n_shells, int max_S, const double* angtab, const double* radtab,
                       const double* u, const double* dR, const double* dA, const double* gamma, double* rhs,
                       hipStream_t st);
-
-// One SSP-RK3 stage, out = c0 u0 + c1 (us + dt L'), with the boundary
-// treatment of L (raw d_t u, read only) applied on the fly; out may alias u0.
-hipError_t stage_bc(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* bctab,
-                    const double* gamma, const double* dt, double c0, const double* u0, double c1,
-                    const double* us, const double* L, double* out, int outer_mode, hipStream_t st);
 
 hipError_t constraints(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* angtab,
                        const double* radtab, const double* u, const double* dR, const double* dA,

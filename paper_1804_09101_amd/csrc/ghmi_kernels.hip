@@ -226,18 +226,28 @@ __device__ __forceinline__ void cart(const Jac& J, double dr, double dt, double 
   d[2] = J.zr * dr + J.zt * dt;
 }
 
+// STAGE 1, 2: the kernel also takes the SSP-RK3 stage out = c0 u0 + c1 (u +
+// dt L) (u is the stage state it reads anyway; STAGE 1: c0 = 0, no u0).  Points on a face that the boundary
+// treatment changes (an interface face, the outer face) still get the raw
+// d_t u in rhs, for k_stage_faces; every other point gets only its stage
+// value in out.  out may alias u0 (each element is read before it is written,
+// by the same thread), not u or rhs.
+template <int STAGE>
 __global__ __launch_bounds__(256) void k_pointwise_rhs(
     const ShellDev* __restrict__ sh, const PtBlock* __restrict__ blk,
     const double* __restrict__ angtab, const double* __restrict__ radtab,
     const double* __restrict__ u, const double* __restrict__ dR, const double* __restrict__ dA,
     const double* __restrict__ Hin, const double* __restrict__ dHin,
-    const double* __restrict__ gamma, double* __restrict__ rhs) {
+    const double* __restrict__ gamma, double* __restrict__ rhs,
+    const double* __restrict__ dtp, double c0, const double* u0, double c1, double* out) {
   const PtBlock b = blk[blockIdx.x];
   const ShellDev s = sh[b.shell];
   const int P = s.n_r * s.S;
   const int q = b.q0 + threadIdx.x;
   if (q >= P) return;
   const int r = q / s.S, a = q - r * s.S;
+  const bool face = STAGE && ((r == s.n_r - 1 && (s.outer || s.bc_off >= 0)) || (r == 0 && !s.inner));
+  const double dtv = STAGE ? dtp[s.instance] : 0.0;
   const long long ub = 50LL * s.pt_off + q;                       // field f at ub + f*P
   const long long ab = 100LL * s.pt_off + (long long)r * 2 * s.S + a;   // d_theta of f at ab + f*n_r*2S
   const long long astride = (long long)s.n_r * 2 * s.S;
@@ -289,11 +299,25 @@ __global__ __launch_bounds__(256) void k_pointwise_rhs(
     }
 
   const long long ob = ub;
+  // d_t u of field f (its state value us, its stage-base value u0v)
+  auto put = [&](int f, double val, double usv, double u0v) {
+    const long long e = ob + (long long)f * P;
+    if (STAGE == 0) {
+      rhs[e] = val;
+    } else if (face) {
+      rhs[e] = val;
+    } else {
+      double v = c1 * (usv + dtv * val);
+      if (STAGE == 2) v += c0 * u0v;
+      out[e] = v;
+    }
+  };
   // The 15 spherical derivatives of pair n + 1 (dR, dA_theta, dA_phi of psi,
   // Pi and the three Phi) are loaded before pair n is computed, and the
   // scheduling barrier keeps the compiler from sinking them to their use: at
   // one wave per SIMD nothing else would hide their latency.
-  auto load_pair = [&](int n, double (&raw)[15]) {
+  // (with a stage base, its u0 of psi_n and the three Phi_in come along)
+  auto load_pair = [&](int n, double (&raw)[15], double (&b0)[4]) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       const int f = c < 2 ? 10 * c + n : 20 + 10 * (c - 2) + n;
@@ -302,14 +326,19 @@ __global__ __launch_bounds__(256) void k_pointwise_rhs(
       raw[3 * c + 1] = dA[ab + fa];
       raw[3 * c + 2] = dA[ab + fa + s.S];
     }
+    if (STAGE == 2) {
+      b0[0] = u0[ub + (long long)n * P];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) b0[1 + i] = u0[ub + (long long)(20 + 10 * i + n) * P];
+    }
   };
-  double raw[2][15];
+  double raw[2][15], b0[2][4];
   double H[4], dHr[16];   // the background's gauge source terms, loaded with the last pair
-  load_pair(0, raw[0]);
+  load_pair(0, raw[0], b0[0]);
 #pragma unroll
   for (int n = 0; n < 10; ++n) {
     if (n + 1 < 10) {
-      load_pair(n + 1, raw[(n + 1) & 1]);
+      load_pair(n + 1, raw[(n + 1) & 1], b0[(n + 1) & 1]);
     } else {
 #pragma unroll
       for (int c = 0; c < 4; ++c) H[c] = Hin[4LL * s.pt_off + (long long)c * P + q];
@@ -336,14 +365,14 @@ __global__ __launch_bounds__(256) void k_pointwise_rhs(
       for (int i = 0; i < 3; ++i) divPhi += G.gi[SYM3(k, i)] * dPhi[k][i];
     const double NPhi = G.Nu[0] * Phi[n] + G.Nu[1] * Phi[10 + n] + G.Nu[2] * Phi[20 + n];
 
-    rhs[ob + (long long)n * P] = (1.0 + g1) * adv_psi - N * Pi[n] - g1 * NPhi;
+    put(n, (1.0 + g1) * adv_psi - N * Pi[n] - g1 * NPhi, psi[n], b0[n & 1][0]);
     dtPi[n] = adv_Pi - N * divPhi + g1 * g2 * adv_psi - g1 * g2 * NPhi;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const double adv = G.Nu[0] * dPhi[0][i] + G.Nu[1] * dPhi[1][i] + G.Nu[2] * dPhi[2][i];
       double alg = 0.5 * N * ttPhi[i] * Pi[n] - g2 * N * Phi[i * 10 + n];
       alg += N * (Gt[i][0] * Phi[n] + Gt[i][1] * Phi[10 + n] + Gt[i][2] * Phi[20 + n]);
-      rhs[ob + (long long)(20 + 10 * i + n) * P] = adv - N * dPi[i] + g2 * N * dpsi[i] + alg;
+      put(20 + 10 * i + n, adv - N * dPi[i] + g2 * N * dpsi[i] + alg, Phi[i * 10 + n], b0[n & 1][1 + i]);
     }
   }
 
@@ -402,6 +431,9 @@ __global__ __launch_bounds__(256) void k_pointwise_rhs(
     for (int j = 0; j < 3; ++j)
       v[j] = tPi[0] * G.gi[SYM3(0, j)] + tPi[1] * G.gi[SYM3(1, j)] + tPi[2] * G.gi[SYM3(2, j)];
   }
+  // (the stage base of the Pi fields is loaded only here: hoisted into the
+  // algebra above, its ten values would not fit in the registers)
+  if (STAGE) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int aa = 0; aa < 4; ++aa)
 #pragma unroll
@@ -415,7 +447,7 @@ __global__ __launch_bounds__(256) void k_pointwise_rhs(
       const double damp = tCsym - psi[n] * tC;
       const double val = dtPi[n] + 2.0 * N * quad[n] - N * dHs + 2.0 * N * GH
                          - 0.5 * N * ttPi * Pi[n] - N * vPhi + g0 * N * damp;
-      rhs[ob + (long long)(10 + n) * P] = val;
+      put(10 + n, val, Pi[n], STAGE == 2 ? u0[ub + (long long)(10 + n) * P] : 0.0);
     }
 }
 
@@ -447,7 +479,7 @@ __device__ __forceinline__ void interface_pair(const double A[5], const double B
 // ---------------------------------------------------------------------------
 // Boundary treatment in place on d_t u: characteristic upwinding at
 // interfaces, Dirichlet at the outer boundary.  blockIdx.y = shell; threads
-// over angular points.  (Used by gh_rhs; a time step uses k_stage_bc.)
+// over angular points.  (Used by gh_rhs; a time step uses k_stage_faces.)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_boundary(const ShellDev* __restrict__ sh,
                                                   const double* __restrict__ bctab,
@@ -491,61 +523,68 @@ __global__ __launch_bounds__(256) void k_boundary(const ShellDev* __restrict__ s
 }
 
 // ---------------------------------------------------------------------------
-// SSP-RK3 stage with the boundary treatment folded in:
-//   out = c0 u0 + c1 (us + dt L'),
-// where L' is the raw d_t u in L except on treated faces: zero on the outer
-// boundary (outer_mode 0; with outer_mode 1 the outer face of L has already
-// been treated by k_outer_cpbc and is used as it is), the upwinded interface
-// value on both faces of an interface (each element recomputes its pair's
-// projection from L, which this kernel only reads, so both shells get bitwise
-// the same value).  dt per instance; blockIdx.y = field.  out may alias u0.
+// The faces of an SSP-RK3 stage whose other points k_pointwise_rhs<1 or 2>
+// has finished: on every face the boundary treatment changes, the treated
+// d_t u L' (from the raw one in L, read only) and out = c0 u0 + c1 (us + dt
+// L'), with the arithmetic of the pointwise kernel's stage value: zero d_t u
+// on the outer boundary (outer_mode 0; with outer_mode 1 k_outer_cpbc has
+// treated the outer face of L in place, and it is used as it is), the
+// upwinded interface value on both faces of an interface.  dt per instance.
+// blockIdx.x: angular points, y: shell,
+// z = 10 face + n: symmetric pair n (the five fields 10 c + n) of face 0, the
+// inner face (an interface with shell y - 1 unless it is an excision face),
+// or face 1, the outer face (the outer boundary, or an interface with shell
+// y + 1).  Both shells of an interface recompute the pair's projection, so
+// both get bitwise the same value.  out may alias u0.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_stage_bc(const ShellDev* __restrict__ sh,
-                                                  const PtBlock* __restrict__ blk,
-                                                  const double* __restrict__ bctab,
-                                                  const double* __restrict__ gamma,
-                                                  const double* __restrict__ dt, double c0,
-                                                  const double* u0, double c1,
-                                                  const double* __restrict__ us,
-                                                  const double* __restrict__ L, double* out,
-                                                  int outer_mode) {
-  const PtBlock b = blk[blockIdx.x];
-  const ShellDev s = sh[b.shell];
+__global__ __launch_bounds__(256) void k_stage_faces(const ShellDev* __restrict__ sh,
+                                                     const double* __restrict__ bctab,
+                                                     const double* __restrict__ gamma,
+                                                     const double* __restrict__ dt, double c0,
+                                                     const double* u0, double c1,
+                                                     const double* __restrict__ us,
+                                                     const double* __restrict__ L, double* out,
+                                                     int outer_mode) {
+  const int k = blockIdx.y;
+  const ShellDev s = sh[k];
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= s.S) return;
   const int P = s.n_r * s.S;
-  const int q = b.q0 + threadIdx.x;
-  if (q >= P) return;
-  const int f = blockIdx.y;
-  const long long e = 50LL * s.pt_off + (long long)f * P + q;
-  const int r = q / s.S;
-  double val;
-  if (r == s.n_r - 1 && s.outer) {
-    val = outer_mode ? L[e] : 0.0;
-  } else if ((r == s.n_r - 1 && s.bc_off >= 0) || (r == 0 && !s.inner)) {
-    // interface between shell ki (inner side) and ki + 1
-    const int ki = (r == 0) ? b.shell - 1 : b.shell;
-    const ShellDev si = sh[ki], so = sh[ki + 1];
-    const int a = q - r * s.S;
-    const int Pi = si.n_r * si.S, Po = so.n_r * so.S;
-    const long long ia = 50LL * si.pt_off + (long long)(si.n_r - 1) * si.S + a;
-    const long long ib = 50LL * so.pt_off + a;
-    const int n = f % 10, c = f / 10;
-    double A[5], B[5], o[5];
+  const int outer_face = blockIdx.z >= 10, n = blockIdx.z % 10;
+  const int r = outer_face ? s.n_r - 1 : 0;
+  const long long e0 = 50LL * s.pt_off + (long long)r * s.S + a;
+  const double dtv = dt[s.instance];
+  auto stage = [&](long long e, double val) {
+    double v = c1 * (us[e] + dtv * val);
+    if (c0 != 0.0) v += c0 * u0[e];
+    out[e] = v;
+  };
+  if (outer_face && s.outer) {
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      A[k] = L[ia + (long long)(10 * k + n) * Pi];
-      B[k] = L[ib + (long long)(10 * k + n) * Po];
+    for (int c = 0; c < 5; ++c) {
+      const long long e = e0 + (long long)(10 * c + n) * P;
+      stage(e, outer_mode ? L[e] : 0.0);
     }
-    interface_pair(A, B, bctab + si.bc_off + 9LL * a, gamma[3 * si.instance + 2], o);
-    val = o[0];
-#pragma unroll
-    for (int k = 1; k < 5; ++k)
-      if (c == k) val = o[k];
-  } else {
-    val = L[e];
+    return;
   }
-  double v = c1 * (us[e] + dt[s.instance] * val);
-  if (c0 != 0.0) v += c0 * u0[e];
-  out[e] = v;
+  if (outer_face ? s.bc_off < 0 : s.inner) return;
+  // the interface between shell ki (inner side) and ki + 1
+  const int ki = outer_face ? k : k - 1;
+  const ShellDev si = sh[ki], so = sh[ki + 1];
+  const int Pi = si.n_r * si.S, Po = so.n_r * so.S;
+  const long long ia = 50LL * si.pt_off + (long long)(si.n_r - 1) * si.S + a;
+  const long long ib = 50LL * so.pt_off + a;
+  const double* T = bctab + si.bc_off + 9LL * a;
+  const double g2 = gamma[3 * si.instance + 2];
+  double A[5], B[5], o[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    A[c] = L[ia + (long long)(10 * c + n) * Pi];
+    B[c] = L[ib + (long long)(10 * c + n) * Po];
+  }
+  interface_pair(A, B, T, g2, o);
+#pragma unroll
+  for (int c = 0; c < 5; ++c) stage(e0 + (long long)(10 * c + n) * P, o[c]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1697,8 +1736,30 @@ hipError_t pointwise_rhs(const ShellDev* sh, const PtBlock* blk, int n_blk, cons
                          const double* radtab, const double* u, const double* dR, const double* dA,
                          const double* H, const double* dH, const double* gamma, double* rhs,
                          hipStream_t st) {
-  hipLaunchKernelGGL(k_pointwise_rhs, dim3(n_blk), dim3(256), 0, st, sh, blk, angtab, radtab, u, dR,
-                     dA, H, dH, gamma, rhs);
+  hipLaunchKernelGGL(k_pointwise_rhs<0>, dim3(n_blk), dim3(256), 0, st, sh, blk, angtab, radtab, u, dR,
+                     dA, H, dH, gamma, rhs, nullptr, 0.0, nullptr, 0.0, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t pointwise_stage(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* angtab,
+                           const double* radtab, const double* us, const double* dR, const double* dA,
+                           const double* H, const double* dH, const double* gamma, double* L, const double* dt,
+                           double c0, const double* u0, double c1, double* out, hipStream_t st) {
+  if (c0 != 0.0 && !u0) return hipErrorInvalidValue;
+  if (c0 != 0.0)
+    hipLaunchKernelGGL(k_pointwise_rhs<2>, dim3(n_blk), dim3(256), 0, st, sh, blk, angtab, radtab, us, dR,
+                       dA, H, dH, gamma, L, dt, c0, u0, c1, out);
+  else
+    hipLaunchKernelGGL(k_pointwise_rhs<1>, dim3(n_blk), dim3(256), 0, st, sh, blk, angtab, radtab, us, dR,
+                       dA, H, dH, gamma, L, dt, c0, u0, c1, out);
+  return hipGetLastError();
+}
+
+hipError_t stage_faces(const ShellDev* sh, int n_shells, int max_S, const double* bctab, const double* gamma,
+                       const double* dt, double c0, const double* u0, double c1, const double* us, const double* L,
+                       double* out, int outer_mode, hipStream_t st) {
+  dim3 grid((max_S + 255) / 256, n_shells, 20), block(256);
+  hipLaunchKernelGGL(k_stage_faces, grid, block, 0, st, sh, bctab, gamma, dt, c0, u0, c1, us, L, out, outer_mode);
   return hipGetLastError();
 }
 
@@ -1714,15 +1775,6 @@ hipError_t outer_cpbc(const ShellDev* sh, int n_shells, int max_S, const double*
                       hipStream_t st) {
   dim3 grid((max_S + 255) / 256, n_shells), block(256);
   hipLaunchKernelGGL(k_outer_cpbc, grid, block, 0, st, sh, angtab, radtab, u, dR, dA, gamma, rhs);
-  return hipGetLastError();
-}
-
-hipError_t stage_bc(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* bctab,
-                    const double* gamma, const double* dt, double c0, const double* u0, double c1,
-                    const double* us, const double* L, double* out, int outer_mode, hipStream_t st) {
-  dim3 grid(n_blk, 50), block(256);
-  hipLaunchKernelGGL(k_stage_bc, grid, block, 0, st, sh, blk, bctab, gamma, dt, c0, u0, c1, us, L, out,
-                     outer_mode);
   return hipGetLastError();
 }
 
