@@ -1480,7 +1480,7 @@ int ensure_transform(gh_ctx* c) {
   HIPCHK(c, hipMemcpy(c->d_sh, c->h_sh.data(), c->h_sh.size() * sizeof(ShellDev), hipMemcpyHostToDevice));
   if ((rc = dalloc(c, &c->d_X, size_t(100) * c->P))) return rc;
   // theta step: shells with n = L + 1 a multiple of 16 on the matrix cores
-  // (items of 8 rows x 8 orders, per n); the others in blocks of 16 (field,
+  // (items of 8 rows x 8 or 16 orders, per n); the others in blocks of 16 (field,
   // radius) rows x 256 (node, column) pairs
   std::vector<PtBlock> tb;
   std::vector<ThetaItem> ti[4];
@@ -1495,9 +1495,9 @@ int ensure_transform(gh_ctx* c) {
       // meet in that XCD's L2.  Groups are padded to 8 (r0 = -1: no work).
       std::vector<ThetaItem>& v = ti[n / 16 - 1];
       while (v.size() % 8) v.push_back(ThetaItem{k, -1, 0, 0});
-      const int nrb = (rows + 7) / 8;
+      const int nrb = (rows + 7) / 8, mb = ghk::theta_item_orders(n);
       for (int g0 = 0; g0 < nrb; g0 += 8)
-        for (int m0 = 0; m0 < n; m0 += 8)
+        for (int m0 = 0; m0 < n; m0 += mb)
           for (int rb = g0; rb < g0 + 8; ++rb) v.push_back(ThetaItem{k, rb < nrb ? 8 * rb : -1, m0, 0});
       continue;
     }

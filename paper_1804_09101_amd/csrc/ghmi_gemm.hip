@@ -182,17 +182,18 @@ __global__ __launch_bounds__(64 * WGM * WGN) void k_gemm(const GemmTile* __restr
 typedef __attribute__((address_space(1))) const void gvoid_t;
 typedef __attribute__((address_space(3))) void lvoid_t;
 
-// Launch bounds: two workgroups per CU (four waves per SIMD, at most 128
-// VGPRs) unless the accumulators alone take 128 registers.  The MFMA pipe
+// Launch bounds (the second argument of HIP's __launch_bounds__ is the least
+// number of waves per SIMD): four waves per SIMD (at most 128 registers)
+// unless the accumulators alone take 128 registers, then two.  The MFMA pipe
 // stays fed only at four waves per SIMD: a variant of 130 VGPRs (three waves)
 // measured 8% slower.
 template <int BM, int BN, int WGM, int WGN>
-constexpr int lds_min_blocks() {
-  return (BM / WGM / 16) * (BN / WGN / 16) * 8 < 128 ? 16 / (WGM * WGN) : 8 / (WGM * WGN);
+constexpr int lds_min_waves() {
+  return (BM / WGM / 16) * (BN / WGN / 16) * 8 < 128 ? 4 : 2;
 }
 
 template <int BM, int BN, int WGM, int WGN, int ROLE>
-__global__ __launch_bounds__(64 * WGM * WGN, (lds_min_blocks<BM, BN, WGM, WGN>())) void k_gemm_lds(const GemmTile* __restrict__ tiles,
+__global__ __launch_bounds__(64 * WGM * WGN, (lds_min_waves<BM, BN, WGM, WGN>())) void k_gemm_lds(const GemmTile* __restrict__ tiles,
                                                              const GemmGroup* __restrict__ groups,
                                                              const double* __restrict__ Abase,
                                                              double* __restrict__ Cbase) {

@@ -95,8 +95,10 @@ hipError_t fill_int(int* x, int n, int value, hipStream_t st);
 hipError_t ang_theta(int nmax, const ShellDev* sh, const PtBlock* tblk, int n_tblk, const double* ktab,
                      const double* AB, double* X, int mode, hipStream_t st);
 // The same step on the matrix cores for the shells with n = L + 1 (16, 32,
-// 48 or 64; one launch per n): items of 8 rows x 8 orders; ktabT: the
-// kernel table transposed per order ([3][n][i'][i], same offsets as ktab).
+// 48 or 64; one launch per n): items of 8 rows x theta_item_orders(n) orders
+// (m0 a multiple of it); ktabT: the kernel table transposed per order
+// ([3][n][i'][i], same offsets as ktab).
+int theta_item_orders(int n);
 hipError_t ang_theta_mfma(int n, const ShellDev* sh, const ThetaItem* items, int n_items, const double* ktabT,
                           const double* AB, double* X, int mode, hipStream_t st);
 

@@ -1326,7 +1326,9 @@ __global__ __launch_bounds__(256) void k_ang_theta(const ShellDev* __restrict__ 
 
 // ---------------------------------------------------------------------------
 // The theta step on the matrix cores, for shells with n = L + 1 a multiple of
-// 16 (v_mfma_f64_16x16x4_f64).  A work item is 8 rows x 8 orders m0 .. m0+7.
+// 16 (v_mfma_f64_16x16x4_f64).  A work item is 8 rows x MB orders m0 ..
+// m0+MB-1 (MB = 16 for n <= 32: every access a whole 128-byte line; 8 for
+// n = 48, 64, where 16 orders would leave one workgroup per CU's LDS).
 // For one order m the step is a product
 //   C[i][(r, c)] = sum_i' K_m[i][i'] W_m[i'][(r, c)],
 // with the 16 columns (r, c) = (row r0 + r, c = 0 cos / 1 sin) of the item.
@@ -1335,20 +1337,24 @@ __global__ __launch_bounds__(256) void k_ang_theta(const ShellDev* __restrict__ 
 // fall in opposite halves of the banks, so the B operands of a half-wave hit
 // every bank once.  The kernel rows come from the transposed table
 // ktabT[kind][m][i'][i] as MFMA A operands (16 consecutive i per
-// quarter-wave).  Four waves take two orders each.  Each workgroup reads and
-// writes whole 64-byte segments (the 8 orders of one (row, node, c)); the
-// host orders the items so that the other segments of the same lines are
-// handled on the same XCD.  Items with r0 < 0 are padding.  The results are
-// stored through LDS in whole 64-byte runs (see below).
+// quarter-wave).  MB / 2 waves take two orders each.  Each workgroup reads
+// and writes whole 8 MB-byte segments (the MB orders of one (row, node, c));
+// with MB = 8 the host orders the items so that the other half of each line
+// is handled on the same XCD.  Items with r0 < 0 are padding.  The results
+// are stored through LDS in whole runs (see below).
 // ---------------------------------------------------------------------------
-template <int N, int MODE>
-__global__ __launch_bounds__(256) void k_ang_theta_mfma(const ShellDev* __restrict__ sh,
-                                                        const ThetaItem* __restrict__ items,
-                                                        const double* __restrict__ ktabT,
-                                                        const double* __restrict__ AB, double* __restrict__ X) {
-  constexpr int R = 8, MB = 8, NB = N / 16, KS = N / 4;
+// (16-order items: two workgroups of 8 waves per CU, so at least four waves
+// per SIMD, at most 128 registers)
+template <int N, int MODE, int MB>
+__global__ __launch_bounds__(32 * MB, MB == 16 ? 4 : 1) void k_ang_theta_mfma(const ShellDev* __restrict__ sh,
+                                                            const ThetaItem* __restrict__ items,
+                                                            const double* __restrict__ ktabT,
+                                                            const double* __restrict__ AB, double* __restrict__ X) {
+  constexpr int R = 8, NB = N / 16, KS = N / 4;
+  constexpr int NW = MB / 2, NT = 64 * NW;   // waves of two orders each
   constexpr int ROWLEN = MB * 2 * R + 16;
   static_assert(N % 16 == 0, "n must be a multiple of 16");
+  static_assert(MB == 8 || MB == 16, "items of 8 or 16 orders");
   __shared__ double Ws[N * ROWLEN];
   const ThetaItem it = items[blockIdx.x];
   if (it.r0 < 0) return;   // padding of the XCD grouping
@@ -1358,7 +1364,7 @@ __global__ __launch_bounds__(256) void k_ang_theta_mfma(const ShellDev* __restri
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double* __restrict__ Wg = AB + 50LL * s.pt_off;
   // stage the item's columns: 16-byte loads of two consecutive orders
-  for (int idx = tid; idx < R * N * 2 * (MB / 2); idx += 256) {
+  for (int idx = tid; idx < R * N * 2 * (MB / 2); idx += NT) {
     const int mp2 = idx % (MB / 2);
     int t = idx / (MB / 2);
     const int c = t & 1;
@@ -1374,10 +1380,10 @@ __global__ __launch_bounds__(256) void k_ang_theta_mfma(const ShellDev* __restri
   const double* __restrict__ Kt = ktabT + s.kt_off;
   const long long n3 = (long long)N * N * N, n2 = (long long)N * N;
   const int col = lane & 15, q = lane >> 4;
-  d4 rA[MB / 4][NB], rB[MB / 4][NB];
+  d4 rA[2][NB], rB[2][NB];
 #pragma unroll
-  for (int w = 0; w < MB / 4; ++w) {
-    const int m = it.m0 + wave + 4 * w;
+  for (int w = 0; w < 2; ++w) {
+    const int m = it.m0 + wave + NW * w;
     const double* __restrict__ KA = Kt + (MODE == 0 ? 0 : 2 * n3) + m * n2;   // d/dtheta or filter
     const double* __restrict__ KB = Kt + n3 + m * n2;                         // d/dphi
 #pragma unroll
@@ -1388,7 +1394,7 @@ __global__ __launch_bounds__(256) void k_ang_theta_mfma(const ShellDev* __restri
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int ip = ks * 4 + q;
-      const double b = Ws[ip * ROWLEN + (wave + 4 * w) * 16 + col];
+      const double b = Ws[ip * ROWLEN + (wave + NW * w) * 16 + col];
 #pragma unroll
       for (int bi = 0; bi < NB; ++bi) {
         const int i = bi * 16 + col;
@@ -1399,12 +1405,14 @@ __global__ __launch_bounds__(256) void k_ang_theta_mfma(const ShellDev* __restri
   }
   // The results go out through LDS (the staging buffer, free again), one
   // part at a time (d/dtheta or the filter; then d/dphi with its cos and sin
-  // slots exchanged and the sin one negated), as runs of the item's 8
-  // orders: 64 bytes per (row, node, slot), written by 4 lanes at once.  In
-  // LDS a run of row r, node i, slot c sits at r * OST + i * 16 + c * 8: the
-  // row stride is odd, so the 32 (r, c, node parity) of a half-wave's stores
-  // fall in distinct banks.
-  constexpr int OST = N * 16 + 1;
+  // slots exchanged and the sin one negated), as runs of the item's MB
+  // orders: 8 MB bytes per (row, node, slot), written by MB / 2 lanes at once.
+  // In LDS a run of row r, node i, slot c sits at r * OST + i * IST + c * MB;
+  // the strides put the 32 stores of a half-wave, and its reads of the runs,
+  // in distinct banks.
+  constexpr int IST = MB == 8 ? 16 : 2 * MB + 1;
+  constexpr int OST = MB == 8 ? N * 16 + 1 : N * IST + 2;
+  constexpr int HL = MB / 2;   // lanes per run
   static_assert(R * OST <= N * ROWLEN, "the output runs fit in the staging buffer");
   const int rr = col & 7, c = col >> 3;
   const int nrun = R * N * 2;
@@ -1412,7 +1420,7 @@ __global__ __launch_bounds__(256) void k_ang_theta_mfma(const ShellDev* __restri
   for (int part = 0; part < (MODE == 0 ? 2 : 1); ++part) {
     __syncthreads();
 #pragma unroll
-    for (int w = 0; w < MB / 4; ++w)
+    for (int w = 0; w < 2; ++w)
 #pragma unroll
       for (int bi = 0; bi < NB; ++bi)
 #pragma unroll
@@ -1420,15 +1428,15 @@ __global__ __launch_bounds__(256) void k_ang_theta_mfma(const ShellDev* __restri
           const int i = bi * 16 + q + 4 * v;
           const int slot = part == 0 ? c : 1 - c;
           const double val = part == 0 ? rA[w][bi][v] : (c == 0 ? rB[w][bi][v] : -rB[w][bi][v]);
-          Ws[rr * OST + i * 16 + slot * 8 + wave + 4 * w] = val;
+          Ws[rr * OST + i * IST + slot * MB + wave + NW * w] = val;
         }
     __syncthreads();
-    for (int idx = tid; idx < nrun * 4; idx += 256) {
-      const int run = idx >> 2, h = idx & 3;
+    for (int idx = tid; idx < nrun * HL; idx += NT) {
+      const int run = idx / HL, h = idx % HL;
       const int r = run / (2 * N), rem = run - r * 2 * N, i = rem >> 1, sl = rem & 1;
       const int row = it.r0 + r;
       if (row >= nrows) continue;
-      const double* o = Ws + r * OST + i * 16 + sl * 8 + 2 * h;
+      const double* o = Ws + r * OST + i * IST + sl * MB + 2 * h;
       double2 val;
       val.x = o[0];
       val.y = o[1];
@@ -1893,13 +1901,19 @@ hipError_t fill_int(int* x, int n, int value, hipStream_t st) {
   return hipGetLastError();
 }
 
+int theta_item_orders(int n) { return n <= 32 ? 16 : 8; }
+
 hipError_t ang_theta_mfma(int n, const ShellDev* sh, const ThetaItem* items, int n_items, const double* ktabT,
                           const double* AB, double* X, int mode, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  dim3 grid(n_items), block(256);
-#define GH_ANGM(NN)                                                                                         \
-  if (mode == 0) hipLaunchKernelGGL((k_ang_theta_mfma<NN, 0>), grid, block, 0, st, sh, items, ktabT, AB, X); \
-  else hipLaunchKernelGGL((k_ang_theta_mfma<NN, 1>), grid, block, 0, st, sh, items, ktabT, AB, X);
+  dim3 grid(n_items);
+#define GH_ANGM(NN)                                                                                             \
+  {                                                                                                             \
+    constexpr int MB = NN <= 32 ? 16 : 8;                                                                       \
+    const dim3 block(32 * MB);                                                                                  \
+    if (mode == 0) hipLaunchKernelGGL((k_ang_theta_mfma<NN, 0, MB>), grid, block, 0, st, sh, items, ktabT, AB, X); \
+    else hipLaunchKernelGGL((k_ang_theta_mfma<NN, 1, MB>), grid, block, 0, st, sh, items, ktabT, AB, X);         \
+  }
   switch (n) {
     case 16: GH_ANGM(16) break;
     case 32: GH_ANGM(32) break;
