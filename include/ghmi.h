@@ -271,8 +271,10 @@ int gh_constraints_vjp(gh_ctx* ctx, const double* u, const double* lam_norm, dou
  * and their summed duration in milliseconds since timing was enabled or last
  * queried, and clears that kind's record.
  * kind 0: angular derivative GEMM; 1: filter GEMM; 2: radial derivative;
- *      3: pointwise GH RHS; 4: boundary treatment (in gh_step together with
- *      the RK3 stage update); 5: RK3 stage combinations of the reverse pass;
+ *      3: pointwise GH RHS (in gh_step together with the RK3 stage update of
+ *      every point off the faces the boundary treatment changes); 4: boundary
+ *      treatment (in gh_step: those faces, with their stage update); 5: RK3
+ *      stage combinations of the reverse pass;
  *      6: pointwise reverse pass; 7: transposed angular derivative GEMM;
  *      8: angular derivatives by transforms (gh_set_angular 1: the three
  *      launches of one derivative pass counted as one); 9: the coupling
