@@ -1402,6 +1402,7 @@ __global__ __launch_bounds__(32 * MB, MB == 16 ? 4 : 1) void k_ang_theta_mfma(co
         if (MODE == 0) rB[w][bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(KB[ip * N + i], b, rB[w][bi], 0, 0, 0);
       }
     }
+    if (MB == 16) __builtin_amdgcn_sched_barrier(0);
   }
   // The results go out through LDS (the staging buffer, free again), one
   // part at a time (d/dtheta or the filter; then d/dphi with its cos and sin
