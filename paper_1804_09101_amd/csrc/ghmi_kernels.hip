@@ -226,10 +226,11 @@ __device__ __forceinline__ void cart(const Jac& J, double dr, double dt, double 
   d[2] = J.zr * dr + J.zt * dt;
 }
 
-// STAGE 1, 2: the kernel also takes the SSP-RK3 stage out = c0 u0 + c1 (u +
-// dt L) (u is the stage state it reads anyway; STAGE 1: c0 = 0, no u0).  Points on a face that the boundary
-// treatment changes (an interface face, the outer face) still get the raw
-// d_t u in rhs, for k_stage_faces; every other point gets only its stage
+// STAGE 0: d_t u of every point into rhs (gh_rhs).  STAGE 1, 2: the kernel
+// also takes the SSP-RK3 stage out = c0 u0 + c1 (u + dt L), u being the stage
+// state it reads anyway (STAGE 1: c0 = 0, no u0).  Points on a face that the
+// boundary treatment changes (an interface face, the outer face) still get the
+// raw d_t u in rhs, for k_stage_faces; every other point gets only its stage
 // value in out.  out may alias u0 (each element is read before it is written,
 // by the same thread), not u or rhs.
 template <int STAGE>
