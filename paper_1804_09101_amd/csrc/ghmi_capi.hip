@@ -1491,8 +1491,9 @@ int ensure_transform(gh_ctx* c) {
       // Workgroups go round-robin over the 8 XCDs, so the items are ordered
       // in groups of 8 row blocks, order block after order block: every
       // order block of a row block then runs on the same XCD in consecutive
-      // rounds, and the partial 128-byte lines each one writes (and reads)
-      // meet in that XCD's L2.  Groups are padded to 8 (r0 = -1: no work).
+      // rounds.  With 8-order items the half 128-byte lines each one writes
+      // (and reads) meet in that XCD's L2; 16-order items move whole lines.
+      // Groups are padded to 8 (r0 = -1: no work).
       std::vector<ThetaItem>& v = ti[n / 16 - 1];
       while (v.size() % 8) v.push_back(ThetaItem{k, -1, 0, 0});
       const int nrb = (rows + 7) / 8, mb = ghk::theta_item_orders(n);
