@@ -485,10 +485,15 @@ int time_plan(gh_ctx* c, const GemmPlan& pl, const double* src, double* dst, int
 }
 
 // Time every (tile shape, tile order) on the plan (A = src, C = dst work
-// space) and keep the fastest.
+// space) and keep the fastest.  Of the fastest shape's orders, order 2 (blocks
+// of 8 x 8 tiles per XCD) is kept when it is within 1% of the fastest: orders
+// that time alike can move very different bytes (on the 20-shell derivative
+// GEMM order 1 fetches twice what order 2 does, at the same speed), and
+// closer timings flip from run to run.
 int autotune(gh_ctx* c, GemmPlan& pl, const double* src, double* dst, int role) {
   float best = 1e30f;
   int best_shape = 0, best_order = 0;
+  float t_order[ghk::NUM_TILE_SHAPES][ghk::NUM_TILE_ORDERS];
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
@@ -499,12 +504,17 @@ int autotune(gh_ctx* c, GemmPlan& pl, const double* src, double* dst, int role) 
       if (rc) return rc;
       float ms = 0;
       if ((rc = time_plan(c, pl, src, dst, role, e0, e1, &ms))) return rc;
+      t_order[sh][order] = ms;
       if (ms < best) {
         best = ms;
         best_shape = sh;
         best_order = order;
       }
     }
+  }
+  if (best_order != 2 && t_order[best_shape][2] <= 1.01f * best) {
+    best_order = 2;
+    best = t_order[best_shape][2];
   }
   // the fastest variant split for whole rounds of tiles, its tail rows in
   // smaller tiles of another variant; kept only when at least 1% faster than
