@@ -804,14 +804,14 @@ int queue_rhs_vjp(gh_ctx* c, const double* x, const double* mu, double* out, dou
   if (c->n_fblk)
     HIPCHK(c, ghk::pointwise_rhs(c->d_sh, c->d_fblk, c->n_fblk, c->d_angtab, c->d_radtab, x, dR, dA, c->d_H,
                                  c->d_dH, c->d_gamma, c->d_W, c->stream));
-  LINCOMB(ghk::lincomb(c->d_sh, c->d_blk, c->n_blk, c->d_dt, 0, 1.0, mu, 0.0, nullptr, 0.0, nullptr, c->d_Lb,
-                         c->stream));
-  HIPCHK(c, ghk::boundary_vjp(c->d_sh, c->n_shells, c->max_S, c->d_bctab, c->d_gamma, c->d_W, c->d_Lb, c->d_bcg,
-                              c->stream));
+  // the transposed boundary treatment writes the faces' raw cotangent to
+  // d_Lb; the reverse pointwise passes read it there and mu elsewhere
+  HIPCHK(c, ghk::boundary_vjp(c->d_sh, c->n_shells, c->max_S, c->d_bctab, c->d_gamma, c->d_W, mu, c->d_Lb,
+                              c->d_bcg, c->stream));
   {
     Timed t(c, 6);
     HIPCHK(c, ghk::pointwise_vjp(c->d_sh, c->d_blk, c->n_blk, c->d_angtab, c->d_radtab, x, dR, dA, c->d_H,
-                                 c->d_dH, c->d_gamma, c->d_Lb, out, c->d_dRb, c->d_dAb, c->d_gpart, c->d_vacc,
+                                 c->d_dH, c->d_gamma, mu, c->d_Lb, out, c->d_dRb, c->d_dAb, c->d_gpart, c->d_vacc,
                                  (long long)c->P, c->stream));
   }
   {

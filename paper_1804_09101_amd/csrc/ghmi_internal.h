@@ -176,18 +176,22 @@ hipError_t nonfinite_count(const double* x, long long n, int* count, hipStream_t
 
 // adjoint
 // Reverse of the pointwise algebra in two passes; acc: work space of
-// 12 x p_total doubles (p_total = all points of the domain).
+// 12 x p_total doubles (p_total = all points of the domain).  The cotangent
+// of the raw d_t u is lamf on the faces the boundary treatment changes (from
+// boundary_vjp) and mu everywhere else.
 hipError_t pointwise_vjp(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* angtab,
                          const double* radtab, const double* u, const double* dR, const double* dA,
-                         const double* H, const double* dH, const double* gamma, const double* lam,
-                         double* ubar, double* dRb, double* dAb, double* gpart, double* acc, long long p_total,
-                         hipStream_t st);
+                         const double* H, const double* dH, const double* gamma, const double* mu,
+                         const double* lamf, double* ubar, double* dRb, double* dAb, double* gpart, double* acc,
+                         long long p_total, hipStream_t st);
 hipError_t constraints_vjp(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* angtab,
                            const double* radtab, const double* u, const double* H, const double* C,
                            const double* norm, const double* wsum, const double* lam_norm, double* ubar,
                            double* dRb, double* dAb, hipStream_t st);
+// Transposed boundary treatment: from mu (cotangent of the treated d_t u,
+// read only) the raw cotangent of every treated face into Lb (nothing else).
 hipError_t boundary_vjp(const ShellDev* sh, int n_shells, int max_S, const double* bctab, const double* gamma,
-                        const double* W, double* Lb, double* bcg, hipStream_t st);
+                        const double* W, const double* mu, double* Lb, double* bcg, hipStream_t st);
 hipError_t gamma_reduce(const int* blk_range, const int* shell_range, int n_inst, int max_S,
                         const double* gpart, const double* bcg, const double* dt, double coef, int use_dt,
                         double* g, hipStream_t st);

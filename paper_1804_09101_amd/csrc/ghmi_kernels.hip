@@ -226,6 +226,14 @@ __device__ __forceinline__ void cart(const Jac& J, double dr, double dt, double 
   d[2] = J.zr * dr + J.zt * dt;
 }
 
+// Whether local radial row r of shell s is a face the boundary treatment
+// changes: an interface face (the outer face of a shell with an interface
+// record, the inner face of a shell that is not an excision shell) or the
+// outer face of an instance.
+__device__ __forceinline__ bool treated_face(const ShellDev& s, int r) {
+  return (r == s.n_r - 1 && (s.outer || s.bc_off >= 0)) || (r == 0 && !s.inner);
+}
+
 // STAGE 0: d_t u of every point into rhs (gh_rhs).  STAGE 1, 2: the kernel
 // also takes the SSP-RK3 stage out = c0 u0 + c1 (u + dt L), u being the stage
 // state it reads anyway (STAGE 1: c0 = 0, no u0).  Points on a face that the
@@ -247,7 +255,7 @@ __global__ __launch_bounds__(256) void k_pointwise_rhs(
   const int q = b.q0 + threadIdx.x;
   if (q >= P) return;
   const int r = q / s.S, a = q - r * s.S;
-  const bool face = STAGE && ((r == s.n_r - 1 && (s.outer || s.bc_off >= 0)) || (r == 0 && !s.inner));
+  const bool face = STAGE && treated_face(s, r);
   const double dtv = STAGE ? dtp[s.instance] : 0.0;
   const long long ub = 50LL * s.pt_off + q;                       // field f at ub + f*P
   const long long ab = 100LL * s.pt_off + (long long)r * 2 * s.S + a;   // d_theta of f at ab + f*n_r*2S
@@ -709,14 +717,17 @@ __global__ __launch_bounds__(256) void k_pointwise_vjp_principal(
     const ShellDev* __restrict__ sh, const PtBlock* __restrict__ blk,
     const double* __restrict__ angtab, const double* __restrict__ radtab,
     const double* __restrict__ u, const double* __restrict__ dR, const double* __restrict__ dA,
-    const double* __restrict__ gamma, const double* __restrict__ lam, double* __restrict__ dRb,
-    double* __restrict__ dAb, double* __restrict__ acc, long long p_total) {
+    const double* __restrict__ gamma, const double* __restrict__ mu, const double* __restrict__ lamf_,
+    double* __restrict__ dRb, double* __restrict__ dAb, double* __restrict__ acc, long long p_total) {
   const PtBlock b = blk[blockIdx.x];
   const ShellDev s = sh[b.shell];
   const int P = s.n_r * s.S;
   const int q = b.q0 + threadIdx.x;
   if (q >= P) return;
   const int r = q / s.S, a = q - r * s.S;
+  // the cotangent of the raw d_t u: mu itself, or on a treated face the
+  // transposed boundary treatment's value
+  const double* __restrict__ lam = treated_face(s, r) ? lamf_ : mu;
   const long long ub = 50LL * s.pt_off + q;
   const long long ab = 100LL * s.pt_off + (long long)r * 2 * s.S + a;
   const long long astride = (long long)s.n_r * 2 * s.S;
@@ -769,8 +780,8 @@ struct Strided {
 __global__ __launch_bounds__(256) void k_pointwise_vjp_algebraic(
     const ShellDev* __restrict__ sh, const PtBlock* __restrict__ blk, const double* __restrict__ u,
     const double* __restrict__ Hin, const double* __restrict__ dHin, const double* __restrict__ gamma,
-    const double* __restrict__ lam, const double* __restrict__ acc, double* __restrict__ ubar,
-    double* __restrict__ gpart, long long p_total) {
+    const double* __restrict__ mu, const double* __restrict__ lamf_, const double* __restrict__ acc,
+    double* __restrict__ ubar, double* __restrict__ gpart, long long p_total) {
   __shared__ double red[3][256];
   const PtBlock b = blk[blockIdx.x];
   const ShellDev s = sh[b.shell];
@@ -786,6 +797,7 @@ __global__ __launch_bounds__(256) void k_pointwise_vjp_algebraic(
     for (int c = 0; c < GHP_VJP_ACC; ++c) pa[c] = acc[c * p_total + pg];
     // the fields and the cotangent are read where they are used (from the
     // caches) rather than held in registers
+    const double* lam = treated_face(s, q / s.S) ? lamf_ : mu;   // as in the principal pass
     ghp::rhs_vjp_algebraic(Strided{u + ub, P}, H, dH, gamma[3 * s.instance], gamma[3 * s.instance + 1],
                            gamma[3 * s.instance + 2], Strided{lam + ub, P}, pa, uo, gb);
     for (int f = 0; f < 50; ++f) ubar[ub + (long long)f * P] = uo[f];
@@ -800,7 +812,9 @@ __global__ __launch_bounds__(256) void k_pointwise_vjp_algebraic(
   if (threadIdx.x < 3) gpart[3LL * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// Transpose of the boundary treatment, in place on the cotangent L of d_t u.
+// Transpose of the boundary treatment: from the cotangent mu of the treated
+// d_t u, the cotangent of the raw d_t u on the treated faces goes to Lb (only
+// there; elsewhere it is mu itself, which the reverse pointwise passes read).
 // The interface map writes the same value into both shells, so its transpose
 // takes the summed cotangent back through reconstruction, upwind selection and
 // projection; the outer Dirichlet rows have zero transpose.  The gamma2
@@ -809,7 +823,8 @@ __global__ __launch_bounds__(256) void k_pointwise_vjp_algebraic(
 __global__ __launch_bounds__(256) void k_boundary_vjp(const ShellDev* __restrict__ sh, int max_S,
                                                       const double* __restrict__ bctab,
                                                       const double* __restrict__ gamma,
-                                                      const double* __restrict__ W, double* __restrict__ Lb,
+                                                      const double* __restrict__ W,
+                                                      const double* __restrict__ mu, double* __restrict__ Lb,
                                                       double* __restrict__ bcg) {
   const int k = blockIdx.y;
   const ShellDev s = sh[k];
@@ -832,7 +847,7 @@ __global__ __launch_bounds__(256) void k_boundary_vjp(const ShellDev* __restrict
       for (int n = 0; n < 10; ++n) {
         double l[5];
         for (int c = 0; c < 5; ++c)
-          l[c] = Lb[ia + (long long)(10 * c + n) * P] + Lb[ib + (long long)(10 * c + n) * Pt];
+          l[c] = mu[ia + (long long)(10 * c + n) * P] + mu[ib + (long long)(10 * c + n) * Pt];
         const double slL = sl[0] * l[2] + sl[1] * l[3] + sl[2] * l[4];
         const double ups_b = l[0] + g2 * l[1];
         const double up_b = 0.5 * l[1] + 0.5 * slL;
@@ -1811,15 +1826,15 @@ hipError_t bc_setup(const ShellDev* sh, int n_shells, int max_S, const double* a
 
 hipError_t pointwise_vjp(const ShellDev* sh, const PtBlock* blk, int n_blk, const double* angtab,
                          const double* radtab, const double* u, const double* dR, const double* dA,
-                         const double* H, const double* dH, const double* gamma, const double* lam,
-                         double* ubar, double* dRb, double* dAb, double* gpart, double* acc, long long p_total,
-                         hipStream_t st) {
+                         const double* H, const double* dH, const double* gamma, const double* mu,
+                         const double* lamf, double* ubar, double* dRb, double* dAb, double* gpart, double* acc,
+                         long long p_total, hipStream_t st) {
   hipLaunchKernelGGL(k_pointwise_vjp_principal, dim3(n_blk), dim3(256), 0, st, sh, blk, angtab, radtab, u, dR, dA,
-                     gamma, lam, dRb, dAb, acc, p_total);
+                     gamma, mu, lamf, dRb, dAb, acc, p_total);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pointwise_vjp_algebraic, dim3(n_blk), dim3(256), 0, st, sh, blk, u, H, dH, gamma, lam, acc,
-                     ubar, gpart, p_total);
+  hipLaunchKernelGGL(k_pointwise_vjp_algebraic, dim3(n_blk), dim3(256), 0, st, sh, blk, u, H, dH, gamma, mu, lamf,
+                     acc, ubar, gpart, p_total);
   return hipGetLastError();
 }
 
@@ -1833,9 +1848,9 @@ hipError_t constraints_vjp(const ShellDev* sh, const PtBlock* blk, int n_blk, co
 }
 
 hipError_t boundary_vjp(const ShellDev* sh, int n_shells, int max_S, const double* bctab, const double* gamma,
-                        const double* W, double* Lb, double* bcg, hipStream_t st) {
+                        const double* W, const double* mu, double* Lb, double* bcg, hipStream_t st) {
   dim3 grid((max_S + 255) / 256, n_shells), block(256);
-  hipLaunchKernelGGL(k_boundary_vjp, grid, block, 0, st, sh, max_S, bctab, gamma, W, Lb, bcg);
+  hipLaunchKernelGGL(k_boundary_vjp, grid, block, 0, st, sh, max_S, bctab, gamma, W, mu, Lb, bcg);
   return hipGetLastError();
 }
 
